@@ -1,0 +1,161 @@
+"""Pins of the patch smoother, V-cycle and PCG of the oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+import workloads as W
+from oracle import problem
+from oracle.assemble import l2_error
+from oracle.multigrid import Hierarchy, pcg
+
+
+def _hier(w, L=None, gamma_g=None):
+    if gamma_g is not None:
+        w = W.Workload(**{**w.__dict__, "gamma_g": gamma_g})
+        levels, mats, prols, _ = problem.build(w, n_levels=L, with_hierarchy=False)
+        # without ghost penalty small cuts can make local matrices indefinite;
+        # the identity tested with it is purely algebraic
+        return w, levels, mats, prols, Hierarchy(levels, mats, prols, n_c=w.n_c, require_spd=False)
+    levels, mats, prols, H = problem.build(w, n_levels=L)
+    return w, levels, mats, prols, H
+
+
+@pytest.fixture(scope="module")
+def disc3():
+    return _hier(W.offcentre_disc(2, 3))
+
+
+def test_patches_disjoint_within_colour_and_cover(disc3):
+    _, levels, _, _, H = disc3
+    for l in range(1, len(levels)):
+        seen = np.zeros(levels[l].n_dofs, dtype=int)
+        for ps in H.patches[l].values():
+            allc = np.concatenate(ps.dofs)
+            assert len(np.unique(allc)) == len(allc)  # disjoint within a colour class
+            seen[allc] += 1
+        assert seen.min() >= 1  # every DoF is smoothed
+
+
+def _colour_operator(H, l, key, n):
+    """B_c = sum_j Q_j^T A_j^{-1} Q_j with A_j^{-1} the stored local inverse."""
+    Bc = np.zeros((n, n))
+    ps = H.patches[l].get(key)
+    if ps is None:
+        return Bc
+    for dofs, inv in zip(ps.dofs, ps.invs):
+        Bc[np.ix_(dofs, dofs)] += inv
+    return Bc
+
+
+def _same_colour_coupling(A, ps):
+    worst = 0.0
+    for i, d1 in enumerate(ps.dofs):
+        for d2 in ps.dofs[i + 1:]:
+            worst = max(worst, np.abs(A[np.ix_(d1, d2)]).max())
+    return worst
+
+
+def test_sequential_mvs_without_ghost_equals_coloured():
+    """With gamma_g = 0 same-coloured patches do not couple (A[I_j, I_j'] = 0), so
+    the simultaneous update of a colour equals the sequential MVS over its patches:
+    every correction solves its own local problem with the residual at the start
+    of the step.  Checked as a backward error because local matrices without
+    ghost penalty have condition numbers up to ~1e7."""
+    w, levels, mats, _, H = _hier(W.offcentre_disc(2, 3), gamma_g=0.0)
+    l = len(levels) - 1
+    A = mats[l].toarray()
+    n = A.shape[0]
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    r0 = b - A @ x0
+    for key in H.schedule(l):
+        ps = H.patches[l].get(key)
+        if ps is None:
+            continue
+        assert _same_colour_coupling(A, ps) == 0.0
+        x = x0.copy()
+        H.colour_step(l, key, x, b)
+        dx = x - x0
+        touched = np.zeros(n, dtype=bool)
+        for dofs in ps.dofs:
+            Aj = A[np.ix_(dofs, dofs)]
+            res = Aj @ dx[dofs] - r0[dofs]
+            assert np.abs(res).max() <= 1e-8 * (np.abs(Aj).max() * np.abs(dx[dofs]).max() + np.abs(r0[dofs]).max())
+            touched[dofs] = True
+        assert np.all(dx[~touched] == 0.0)
+
+
+def test_ghost_penalty_couples_same_coloured_cut_patches(disc3):
+    """The inconsistency of the parallel smoother: with gamma_g > 0 some
+    same-coloured cut patches couple through ghost faces."""
+    _, levels, mats, _, H = disc3
+    l = len(levels) - 1
+    A = mats[l].toarray()
+    worst = max(_same_colour_coupling(A, ps) for (interior, _), ps in H.patches[l].items() if not interior)
+    assert worst > 0.0
+
+
+def test_two_grid_formula(disc3):
+    """Two-level V-cycle == (I - E_post (I - P A0^{-1} P^T A) E_pre) A^{-1}, with
+    E = prod_c (I - B_c A) over the colour schedule."""
+    w, levels, mats, prols, _ = disc3
+    H = Hierarchy(levels[:2], mats[:2], prols[:1], n_c=w.n_c)
+    A = mats[1].toarray()
+    n = A.shape[0]
+    I = np.eye(n)
+    E_pre = I.copy()
+    for key in H.schedule(1):
+        E_pre = (I - _colour_operator(H, 1, key, n) @ A) @ E_pre
+    E_post = I.copy()
+    for key in H.schedule(1, post=True):
+        E_post = (I - _colour_operator(H, 1, key, n) @ A) @ E_post
+    P = prols[0].toarray()
+    A0 = mats[0].toarray()
+    E = E_post @ (I - P @ np.linalg.solve(A0, P.T @ A)) @ E_pre
+    B_ref = (I - E) @ np.linalg.inv(A)
+    B = np.column_stack([H.vcycle(e) for e in I])
+    assert np.abs(B - B_ref).max() < 1e-10 * np.abs(B_ref).max()
+
+
+def test_vcycle_symmetric_positive(disc3):
+    _, levels, mats, _, H = disc3
+    n = levels[-1].n_dofs
+    B = np.column_stack([H.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - B.T).max() < 1e-12 * np.abs(B).max()
+    ev = np.linalg.eigvals(B @ mats[-1].toarray()).real
+    # exact patch solvers would bound the spectrum by 1; the ignored ghost
+    # coupling between same-coloured patches lets it exceed 1 by a little
+    assert ev.min() > 0.1 and ev.max() < 1.01
+
+
+def test_vcycle_q3_spd():
+    w, levels, mats, _, H = _hier(W.offcentre_disc(3, 3))
+    n = levels[-1].n_dofs
+    B = np.column_stack([H.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - B.T).max() < 1e-11 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T))[0] > 0
+
+
+def test_pcg_matches_direct_solve():
+    w, levels, mats, _, H = _hier(W.disc_q2())
+    b = problem.rhs(w, levels[-1])
+    x, it, hist = pcg(mats[-1], b, H.vcycle, rtol=1e-12)
+    xs = spl.spsolve(mats[-1].tocsc(), b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-9
+    assert it <= 12
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_l2_convergence_rate(k):
+    w = W.disc_q2().with_degree(k)
+    u, _, _ = problem.manufactured(2)
+    errs = []
+    for L in (4, 5):
+        levels, mats, _, H = problem.build(w, n_levels=L)
+        b = problem.rhs(w, levels[-1])
+        x, _, _ = pcg(mats[-1], b, H.vcycle, rtol=1e-11)
+        errs.append(l2_error(levels[-1], problem.shapes_of(w), problem.form_params(w), x, u))
+    assert math.log2(errs[0] / errs[1]) >= k + 0.8

@@ -1,0 +1,79 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle.
+
+This module only describes inputs: domain geometry, discretisation parameters
+and seeded random vectors.  It holds none of the method's arithmetic.
+
+Domains follow the benchmark configurations of the method's evaluation: a disc
+or a ball of radius 0.7 cut from the background box [-1, 1]^d, a union of
+seeded spheres, all on a 4^d coarse Cartesian mesh refined uniformly.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    dim: int
+    k: int                      # polynomial degree
+    n_levels: int               # levels 0..n_levels-1, N_l = coarse_cells * 2^l
+    coarse_cells: int = 4
+    lo: float = -1.0
+    hi: float = 1.0
+    centers: tuple = ()         # one tuple of length dim per shape
+    semi: tuple = ()            # semi-axes per shape (all equal for a sphere)
+    gamma_g: float = 0.1        # ghost penalty for every derivative order
+    ghost_exp_mode: int = 0     # 0: h^(2m-1) scaling, 1: h^(2m+1)
+    n_c: int = 2                # sweeps over the cut patches per smoothing step
+    rhs: str = "manufactured"   # "manufactured" (u = prod sin(pi x_j)) or "fourier"
+    nrhs: int = 1
+
+    @property
+    def gamma_D(self) -> float:
+        """Nitsche penalty; the penalty term reads gamma_D / h with gamma_D = 20 k (k+1)."""
+        return 20.0 * self.k * (self.k + 1)
+
+    @property
+    def fine_cells(self) -> int:
+        return self.coarse_cells * 2 ** (self.n_levels - 1)
+
+    def with_levels(self, n_levels: int) -> "Workload":
+        return Workload(**{**self.__dict__, "n_levels": n_levels,
+                           "name": f"{self.name}@{self.coarse_cells * 2 ** (n_levels - 1)}"})
+
+    def with_degree(self, k: int) -> "Workload":
+        return Workload(**{**self.__dict__, "k": k, "name": f"{self.name}-Q{k}"})
+
+
+def disc_q2() -> Workload:
+    """2-D disc |x| < 0.7 in [-1, 1]^2, Q2, 4 levels (4x4 to 32x32 cells)."""
+    return Workload("disc-r0.7-Q2", 2, 2, 4, centers=((0.0, 0.0),), semi=((0.7, 0.7),))
+
+
+def ball_q2() -> Workload:
+    """3-D ball |x| < 0.7 in [-1, 1]^3, Q2, 6 levels (4^3 to 128^3 cells)."""
+    return Workload("ball-r0.7-Q2", 3, 2, 6, centers=((0.0, 0.0, 0.0),), semi=((0.7, 0.7, 0.7),))
+
+
+def offcentre_disc(k: int = 2, n_levels: int = 4) -> Workload:
+    """A disc that is not symmetric w.r.t. the mesh, to exercise generic cuts."""
+    return Workload(f"disc-off-Q{k}", 2, k, n_levels, centers=((0.0731, -0.1123),), semi=((0.6613, 0.6613),))
+
+
+def offcentre_ball(k: int = 2, n_levels: int = 3) -> Workload:
+    return Workload(f"ball-off-Q{k}", 3, k, n_levels, centers=((0.0513, -0.0821, 0.0337),),
+                    semi=((0.6471, 0.6471, 0.6471),))
+
+
+def ellipse(k: int = 2, n_levels: int = 4) -> Workload:
+    return Workload(f"ellipse-Q{k}", 2, k, n_levels, centers=((0.031, -0.047),), semi=((0.72, 0.51),))
+
+
+def random_vector(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """Seeded standard-normal test vector(s), float64, shape (n,) or (nrhs, n)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((nrhs, n))
+    return v[0] if nrhs == 1 else v
