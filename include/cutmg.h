@@ -1,0 +1,157 @@
+/*
+ * cutmg - C ABI of the CutFEM vertex-patch multigrid for AMD MI355X (gfx950).
+ *
+ * Problem (Cui & Kanschat, "A multigrid method for CutFEM and its
+ * implementation on GPU", Section 2.1): Poisson's equation on a domain Omega
+ * cut from a Cartesian background box, discretised by continuous Q_k elements
+ * on the active cells (cells meeting Omega), Dirichlet data imposed by
+ * Nitsche's method (eq. (cutfem_nitsche)) and face ghost penalties on the faces
+ * next to cut cells (eq. (cutfem-ghost)).  The solver is the V-cycle of
+ * Section 2.2 with the coloured multiplicative vertex-patch smoother of
+ * Section 2.3 / eq. (smoother-split), used as preconditioner of CG.
+ *
+ * Conventions for every call below:
+ *  - Vectors are device pointers (HBM) to float64 arrays in the canonical DoF
+ *    order of their level: lexicographic on the (kN+1)^d Gauss-Lobatto node
+ *    lattice (x fastest) restricted to the nodes of active cells.  Sizes come
+ *    from cmg_ndofs.  The caller owns them; they must not alias unless stated.
+ *  - stream is a hipStream_t (NULL = default stream).  Every device call is
+ *    stream ordered and returns without synchronising, except cmg_solve, which
+ *    synchronises to test convergence.
+ *  - The library owns the hierarchy (geometry, matrices, patch inverses) in
+ *    device memory from cmg_setup until cmg_destroy.  Internal work vectors
+ *    are per problem: calls on one problem must not overlap in time.
+ *  - Errors: a negative cmg_status; the message of the failing call is
+ *    available from cmg_last_error() in the same thread.  Nothing is launched
+ *    when argument checks fail.
+ */
+#ifndef CUTMG_H
+#define CUTMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CMG_OK = 0,
+  CMG_EINVAL = -1,     /* bad argument, unsupported shape set, level out of range */
+  CMG_ENOMEM = -2,     /* device allocation failed */
+  CMG_EGEOM = -3,      /* no active cell on level 0, or an active cell without active parent */
+  CMG_ENOTSPD = -4,    /* Cholesky of a cut-patch or the coarse matrix failed */
+  CMG_ENOTCONV = -5,   /* CG reached maxit; x holds the last iterate */
+  CMG_EBREAKDOWN = -6, /* CG breakdown: p^T A p <= 0 or not finite */
+  CMG_EHIP = -7        /* a HIP runtime call failed */
+} cmg_status;
+
+typedef struct cmg_problem cmg_problem;
+
+/* Omega = union of axis-aligned ellipsoids sum_j ((x_j - c_ij)/s_ij)^2 < 1 (a
+ * sphere has equal semi-axes); host arrays of n_shapes * dim doubles.  The
+ * background box is [box_lo, box_hi]^dim. */
+typedef struct {
+  int dim;               /* 2 or 3 */
+  int n_shapes;          /* >= 1; cut-cell quadrature currently needs exactly 1 */
+  const double* centers;
+  const double* semi;
+  double box_lo, box_hi;
+} cmg_levelset;
+
+/* Discretisation and smoother parameters (paper Section 2 and Section 4). */
+typedef struct {
+  int k;                 /* polynomial degree, 1..3 */
+  int n_levels;          /* levels 0..n_levels-1, N_l = coarse_cells * 2^l cells per direction */
+  int coarse_cells;      /* cells per direction on level 0 */
+  double gamma_D;        /* Nitsche penalty: the boundary term is gamma_D / h */
+  double gamma_g;        /* ghost penalty for every derivative order m = 1..k */
+  int ghost_exp_mode;    /* 0: face weight h^(2m-1) / (m!)^2;  1: h^(2m+1) / (m!)^2 */
+  int n_c;               /* sweeps over the cut patches per smoothing step (eq. (smoother-split)) */
+  int quad_n;            /* Gauss points per smooth piece of a cut-cell rule (e.g. 14) */
+} cmg_params;
+
+typedef struct {
+  int iterations;        /* CG iterations = number of V-cycle applications */
+  double rel_residual;   /* final ||b - A x||_2 / ||b||_2 */
+  double n_frac;         /* fractional iteration count n_it * log10(rtol) / log10(rel_residual) */
+} cmg_solve_info;
+
+/* Build the level hierarchy on the host (geometry, cut-cell quadrature,
+ * element matrices, vertex patches, FP64 local and coarse inverses) and upload
+ * it to the current HIP device.  Synchronous.  On success *out owns the data. */
+cmg_status cmg_setup(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out);
+
+/* Same set-up without any device work (no HIP call): for inspecting the
+ * hierarchy with cmg_export on machines without a GPU.  Device calls on such a
+ * problem return CMG_EINVAL. */
+cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out);
+
+/* Number of DoFs on a level (0 = coarsest, n_levels-1 = finest). */
+cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);
+
+/* y = A_l x on one level (paper eq. (cutfem-ghost) in matrix form). */
+cmg_status cmg_apply(cmg_problem* p, int level, const double* x, double* y, void* stream);
+
+/* One colour step of the smoother on level >= 1 (paper eq. (local-solver)):
+ * for all patches j of the given class (interior != 0: interior patches with
+ * fast diagonalisation; 0: cut patches with dense inverses) and colour
+ * (0..2^dim-1): x[I_j] += A_j^{-1} (b - A_l x)[I_j], all from the x at entry.
+ * x is updated in place. */
+cmg_status cmg_colour_step(cmg_problem* p, int level, int interior, int colour, double* x, const double* b,
+                           void* stream);
+
+/* One smoothing step S(x, b) on level >= 1: interior colours 0..C-1, then n_c
+ * times the cut colours 0..C-1 (eq. (smoother-split)); post != 0 runs the same
+ * colour steps in reverse order.  x is updated in place. */
+cmg_status cmg_smooth(cmg_problem* p, int level, int post, double* x, const double* b, void* stream);
+
+/* Transfers between level l-1 and l >= 1 (paper Section 2.2): dir = 0
+ * prolongation (embedding) y_l = P_l x_{l-1}; dir = 1 restriction y_{l-1} =
+ * P_l^T x_l. */
+cmg_status cmg_transfer(cmg_problem* p, int level, int dir, const double* x, double* y, void* stream);
+
+/* Exact coarse solve x_0 = A_0^{-1} b_0 (dense FP64 inverse). */
+cmg_status cmg_coarse_solve(cmg_problem* p, const double* b, double* x, void* stream);
+
+/* One V-cycle on the finest level with zero initial guess: z = B r. */
+cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream);
+
+/* Preconditioned CG on the finest level from x = 0 until ||r|| <= rtol ||b||.
+ * Synchronises the stream once per iteration.  info may be NULL. */
+cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
+                     void* stream);
+
+/* Load vector of the manufactured problem u = prod_j sin(pi x_j), f = -Laplace u,
+ * Dirichlet data g = u (symmetric Nitsche terms), finest level, written to a
+ * HOST array of cmg_ndofs(finest) doubles. */
+cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host);
+
+/* Host-side description of a level for tests and diagnostics.
+ * what = 0: counts, 8 int64 into buf: n_dofs, n_cells_active, n_cut_cells,
+ *           n_interior_patches, n_cut_patches, sum of N_j^2 over cut patches,
+ *           n_ghost_faces, lattice nodes per direction;
+ * what = 1: lattice node index of every DoF (int32, n_dofs);
+ * what = 2: cell flags (uint8 per background cell, bit 0 active, bit 1 cut);
+ * what = 3: element matrices of the cut cells in the order of their cell
+ *           index, (k+1)^d x (k+1)^d row-major each, cell-local nodes x fastest;
+ * what = 4: dense inverse of A_0 (level 0 only), row-major;
+ * what = 16+c: vertex index of every interior patch of colour c (int32;
+ *           vertex V has index V_0 + (N+1) V_1 [+ (N+1)^2 V_2]);
+ * what = 24+c / 32+c / 40+c / 48+c: cut patches of colour c - node offsets
+ *           (int32, n_patch + 1), lattice nodes of their internal DoFs (int32),
+ *           dense inverses (double, N_j x N_j each, consecutive), vertex
+ *           index (int32, n_patch).
+ * *needed receives the byte size; buf may be NULL to query it. */
+cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed);
+
+void cmg_destroy(cmg_problem* p);
+
+/* Message of the last failing call in this thread ("" if none). */
+const char* cmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTMG_H */

@@ -1,0 +1,66 @@
+// Device-side views of one multigrid level and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cmg {
+
+// One level as seen by the kernels (all pointers are device pointers).
+struct KLevel {
+  int N;                     // cells per direction
+  int nn;                    // lattice nodes per direction, k N + 1
+  int64_t n_dofs;
+  const uint8_t* flags;      // per cell: bit 0 active, bit 1 cut
+  const int32_t* cut_id;     // per cell: index of its cut-cell matrix or -1
+  const uint8_t* ghost;      // per cell: bit 2*dir+side marks a ghost face
+  const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path
+  const int32_t* dof_node;   // lattice node of each DoF, ascending
+  const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
+  template <typename T>
+  __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
+};
+
+// Cut patches of one colour.
+struct CutGroupDev {
+  int n_patch;
+  int64_t n_nodes;
+  const int32_t* off;        // node offsets, n_patch + 1
+  const int64_t* inv_off;    // inverse offsets, n_patch + 1
+  const int32_t* nodes;      // lattice nodes of the internal DoFs
+  const void* inv;           // symmetric dense inverses, scalar type of the path
+  template <typename T>
+  __host__ __device__ const T* inv_t() const { return static_cast<const T*>(inv); }
+};
+
+int tables_size(int d, int k);
+
+template <typename T>
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, hipStream_t s);
+template <typename T>
+hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_cut_step(int d, int k, const KLevel& L, const CutGroupDev& G, T* x, const T* b, T* dbuf,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, hipStream_t s);
+template <typename T>
+hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, hipStream_t s);
+template <typename TS, typename TD>
+hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, hipStream_t s);
+template <typename TS, typename TD>
+hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, hipStream_t s);
+
+}  // namespace cmg
+
+namespace cmg {
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s);
+hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y += a x
+hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y = x + a y
+}  // namespace cmg

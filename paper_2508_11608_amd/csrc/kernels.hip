@@ -1,0 +1,691 @@
+// HIP kernels of the CutFEM vertex-patch multigrid for gfx950 (MI355X).
+//
+// Data layout: every level keeps its vectors on the full (kN+1)^d node lattice,
+// x fastest, with exact zeros at inactive nodes.  Lattice indexing needs no DoF
+// index lists inside the patch kernels, and the patches of one colour read
+// neighbouring x-rows, which keeps the HBM streams coalesced.  Compact vectors
+// (canonical DoF order) exist only at the library boundary.
+//
+// Operator (paper eq. (cutfem_nitsche) + eq. (cutfem-ghost)), evaluated row by
+// row for a node i:
+//   (A x)_i = sum_{active cells T containing i} row_i(E_T) x_T
+//           + sum_{ghost faces F of those cells} row_i(G_F) x_{T1 u T2}
+// with E_T the uncut stiffness (shared, kept in LDS) or the dense matrix of a
+// cut cell, and G_F = sum_m c_m (d^m-jump) x (1-D mass on the face) built from
+// 1-D tables: a face needs no stored data.
+//
+// Smoother colour steps (paper eqs. (local-solver), (smoother-split)):
+//   interior patches: one fused kernel - x on the patch closure is staged in
+//     LDS, the residual on the (2k-1)^d internal nodes uses the Cartesian
+//     stiffness, the local solve is fast diagonalisation (S (x) S (x) S) D^-1
+//     (S^T (x) S^T (x) S^T), and the internal values are updated in place.  Same
+//     coloured interior patches read only their own closure, so the fused
+//     update is race free.
+//   cut patches: residual (general rows incl. ghost faces, which may reach into
+//     a same-coloured neighbour) and dense inverse GEMV into a buffer, then a
+//     second kernel adds the corrections: every patch of the colour sees the
+//     state at the start of the step.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace cmg {
+namespace dev {
+
+template <int B, int E>
+struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
+template <int B>
+struct Pow<B, 0> { static constexpr int v = 1; };
+
+template <int D, int K>
+struct Shape {
+  static constexpr int N1 = K + 1;                 // nodes per cell and direction
+  static constexpr int NL = Pow<N1, D>::v;         // nodes per cell
+  static constexpr int NP1 = 2 * K - 1;            // internal patch nodes per direction
+  static constexpr int NP = Pow<NP1, D>::v;        // internal patch nodes
+  static constexpr int NC1 = 2 * K + 1;            // patch closure nodes per direction
+  static constexpr int NC = Pow<NC1, D>::v;
+  static constexpr int PPB = 256 / NP;             // patches per 256-thread block
+  // table layout (doubles), see LevelTables on the host
+  static constexpr int T_KCELL = 0;
+  static constexpr int T_MHAT = T_KCELL + NL * NL;
+  static constexpr int T_D0 = T_MHAT + N1 * N1;
+  static constexpr int T_D1 = T_D0 + K * N1;
+  static constexpr int T_GC = T_D1 + K * N1;
+  static constexpr int T_FDS = T_GC + K;
+  static constexpr int T_FDD = T_FDS + NP1 * NP1;
+  static constexpr int T_P1D = T_FDD + NP;
+  static constexpr int T_SIZE = T_P1D + NC1 * N1;
+};
+
+__device__ __forceinline__ int64_t lat(int D, int nn, const int* I) {
+  return D == 2 ? I[0] + (int64_t)nn * I[1] : I[0] + (int64_t)nn * (I[1] + (int64_t)nn * I[2]);
+}
+
+__device__ __forceinline__ int64_t cell_lin(int D, int N, const int* c) {
+  return D == 2 ? c[0] + (int64_t)N * c[1] : c[0] + (int64_t)N * (c[1] + (int64_t)N * c[2]);
+}
+
+// Contribution of the ghost face (dir, side) of cell c to the row of its local
+// node il:  sum_m gc[m] sigma_m sum_{tangential b} prod M[il_j, b_j] jump_m(b).
+template <int D, int K, typename T>
+__device__ T ghost_row(const KLevel& L, const T* __restrict__ x, const double* tab, const int* c, const int* il,
+                       int dir, int side) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1;
+  const double* mh = tab + S::T_MHAT;
+  const double* d0 = tab + S::T_D0;
+  const double* d1 = tab + S::T_D1;
+  const double* gc = tab + S::T_GC;
+  int lower[3] = {c[0], c[1], D == 3 ? c[2] : 0};
+  if (side == 0) lower[dir] -= 1;
+  // coefficient of the test function: sign and derivative trace of cell c
+  double sig[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) sig[m] = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
+  T acc = 0;
+  constexpr int NT = Pow<N1, D - 1>::v;
+  for (int bt = 0; bt < NT; ++bt) {
+    int b[3];
+    double w = 1.0;
+    {
+      int r = bt;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        if (j == dir) continue;
+        b[j] = r % N1;
+        r /= N1;
+        w *= mh[il[j] * N1 + b[j]];
+      }
+    }
+    T jm[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) jm[m] = 0;
+#pragma unroll
+    for (int bd = 0; bd <= K; ++bd) {
+      int I[3];
+#pragma unroll
+      for (int j = 0; j < D; ++j) I[j] = K * lower[j] + (j == dir ? bd : b[j]);
+      const T xl = x[lat(D, L.nn, I)];
+      I[dir] += K;  // same tangential node, upper cell
+      const T xu = x[lat(D, L.nn, I)];
+#pragma unroll
+      for (int m = 0; m < K; ++m) jm[m] += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * xu;
+    }
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) s += (T)sig[m] * jm[m];
+    acc += (T)w * s;
+  }
+  return acc;
+}
+
+// (A x)_i for the lattice node I (general rows: uncut, cut and ghost terms).
+template <int D, int K, typename T>
+__device__ T row_apply(const KLevel& L, const T* __restrict__ x, const double* tab, const int* I) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL;
+  int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int i = I[a];
+    if (i % K == 0) {
+      const int v = i / K;
+      int n = 0;
+      if (v - 1 >= 0) { cc[a][n] = v - 1; lc[a][n] = K; ++n; }
+      if (v < L.N) { cc[a][n] = v; lc[a][n] = 0; ++n; }
+      nc[a] = n;
+    } else {
+      cc[a][0] = i / K;
+      lc[a][0] = i % K;
+      nc[a] = 1;
+    }
+  }
+  T acc = 0;
+  const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
+  for (int comb = 0; comb < ncomb; ++comb) {
+    int c[3], il[3];
+    int r = comb;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int s = r % nc[a];
+      r /= nc[a];
+      c[a] = cc[a][s];
+      il[a] = lc[a][s];
+    }
+    const int64_t cl = cell_lin(D, L.N, c);
+    const uint8_t f = L.flags[cl];
+    if (!(f & 1)) continue;
+    int iloc = il[0] + N1 * il[1];
+    if (D == 3) iloc += N1 * N1 * il[2];
+    const bool cut = f & 2;
+    const double* row = cut ? nullptr : tab + S::T_KCELL + iloc * NL;
+    const T* crow = cut ? L.cut_mats_t<T>() + ((int64_t)L.cut_id[cl] * NL + iloc) * NL : nullptr;
+    int base[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) base[a] = K * c[a];
+    T s = 0;
+#pragma unroll
+    for (int b = 0; b < NL; ++b) {
+      int J[3];
+      int rb = b;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { J[a] = base[a] + rb % N1; rb /= N1; }
+      const T xv = x[lat(D, L.nn, J)];
+      s += (cut ? crow[b] : (T)row[b]) * xv;
+    }
+    acc += s;
+    const uint8_t g = L.ghost[cl];
+    if (g) {
+#pragma unroll
+      for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+          if (g & (1 << (2 * dir + side))) acc += ghost_row<D, K, T>(L, x, tab, c, il, dir, side);
+    }
+  }
+  return acc;
+}
+
+template <int D, int K>
+__device__ void load_tables(const double* __restrict__ g, double* s, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = g[i];
+}
+
+// y = A x (b == nullptr) or y = b - A x, for every active node.
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y) {
+  using S = Shape<D, K>;
+  __shared__ double tab[S::T_SIZE];
+  load_tables<D, K>(L.tables, tab, S::T_SIZE);
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= L.n_dofs) return;
+  const int32_t node = L.dof_node[i];
+  int I[3];
+  int r = node;
+#pragma unroll
+  for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
+  const T ax = row_apply<D, K, T>(L, x, tab, I);
+  y[node] = b ? b[node] - ax : ax;
+}
+
+// Fused colour step over interior patches.
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* __restrict__ verts, int nv,
+                                                       T* __restrict__ x, const T* __restrict__ b) {
+  using S = Shape<D, K>;
+  constexpr int NP = S::NP, NP1 = S::NP1, NC = S::NC, NC1 = S::NC1, PPB = S::PPB, N1 = S::N1, NL = S::NL;
+  __shared__ double tab[S::T_SIZE];
+  __shared__ T xs[PPB][NC];
+  __shared__ T ra[PPB][NP];
+  __shared__ T rb[PPB][NP];
+  load_tables<D, K>(L.tables, tab, S::T_SIZE);
+  const int p = threadIdx.x / NP, i = threadIdx.x % NP;
+  const int gp0 = blockIdx.x * PPB;
+  const int NV = L.N + 1;
+  // stage the closures of all patches of this block
+  for (int e = threadIdx.x; e < PPB * NC; e += blockDim.x) {
+    const int pp = e / NC, q = e % NC;
+    T v = 0;
+    if (gp0 + pp < nv) {
+      int vr = verts[gp0 + pp];
+      int J[3];
+      int rq = q;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int Va = vr % NV;
+        vr /= NV;
+        J[a] = K * Va - K + rq % NC1;
+        rq /= NC1;
+      }
+      v = x[lat(D, L.nn, J)];
+    }
+    xs[pp][q] = v;
+  }
+  __syncthreads();
+  const bool active = p < PPB && gp0 + p < nv;
+  int pi[3] = {0, 0, 0};
+  int64_t node = 0;
+  if (active) {
+    int vr = verts[gp0 + p];
+    int J[3];
+    int ri = i;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int Va = vr % NV;
+      vr /= NV;
+      pi[a] = ri % NP1 + 1;
+      ri /= NP1;
+      J[a] = K * Va - K + pi[a];
+    }
+    node = lat(D, L.nn, J);
+    // residual with the Cartesian stiffness: cells of the patch containing the node
+    int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (pi[a] == K) { cc[a][0] = 0; lc[a][0] = K; cc[a][1] = 1; lc[a][1] = 0; nc[a] = 2; }
+      else if (pi[a] < K) { cc[a][0] = 0; lc[a][0] = pi[a]; }
+      else { cc[a][0] = 1; lc[a][0] = pi[a] - K; }
+    }
+    T ax = 0;
+    const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
+    for (int comb = 0; comb < ncomb; ++comb) {
+      int c[3], il[3];
+      int r = comb;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int s = r % nc[a];
+        r /= nc[a];
+        c[a] = cc[a][s];
+        il[a] = lc[a][s];
+      }
+      int iloc = il[0] + N1 * il[1];
+      if (D == 3) iloc += N1 * N1 * il[2];
+      const double* row = tab + S::T_KCELL + iloc * NL;
+#pragma unroll
+      for (int bq = 0; bq < NL; ++bq) {
+        int q = 0, stride = 1, rb2 = bq;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          q += (K * c[a] + rb2 % N1) * stride;
+          rb2 /= N1;
+          stride *= NC1;
+        }
+        ax += (T)row[bq] * xs[p][q];
+      }
+    }
+    ra[p][i] = b[node] - ax;
+  }
+  __syncthreads();
+  // fast diagonalisation: apply S^T along every direction, scale, apply S
+  const double* fs = tab + S::T_FDS;
+  T* src = &ra[0][0];
+  T* dst = &rb[0][0];
+  for (int stage = 0; stage < 2 * D; ++stage) {
+    const int a = stage % D;
+    const bool transpose = stage < D;
+    if (active) {
+      int ia[3];
+      int rr = i;
+#pragma unroll
+      for (int j = 0; j < D; ++j) { ia[j] = rr % NP1; rr /= NP1; }
+      int strideA = 1;
+      for (int j = 0; j < a; ++j) strideA *= NP1;
+      const int baseIdx = i - ia[a] * strideA;
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NP1; ++q) {
+        const double m = transpose ? fs[q * NP1 + ia[a]] : fs[ia[a] * NP1 + q];
+        s += (T)m * src[p * NP + baseIdx + q * strideA];
+      }
+      if (stage == D - 1) s *= (T)tab[S::T_FDD + i];
+      dst[p * NP + i] = s;
+    }
+    __syncthreads();
+    T* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (active) x[node] += src[p * NP + i];
+}
+
+// Cut patches, phase 1: residual on internal nodes and dense local solve.
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_cut_solve(KLevel L, CutGroupDev G, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ dbuf) {
+  using S = Shape<D, K>;
+  constexpr int NP = S::NP, PPB = S::PPB;
+  __shared__ double tab[S::T_SIZE];
+  __shared__ T rs[PPB][NP];
+  load_tables<D, K>(L.tables, tab, S::T_SIZE);
+  __syncthreads();
+  const int p = threadIdx.x / NP, i = threadIdx.x % NP;
+  const int gp = blockIdx.x * PPB + p;
+  const bool inpatch = p < PPB && gp < G.n_patch;
+  int off = 0, nj = 0;
+  if (inpatch) {
+    off = G.off[gp];
+    nj = G.off[gp + 1] - off;
+  }
+  if (inpatch && i < nj) {
+    const int32_t node = G.nodes[off + i];
+    int I[3];
+    int r = node;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
+    rs[p][i] = b[node] - row_apply<D, K, T>(L, x, tab, I);
+  }
+  __syncthreads();
+  if (inpatch && i < nj) {
+    const T* inv = G.inv_t<T>() + G.inv_off[gp];
+    T s = 0;
+    for (int j = 0; j < nj; ++j) s += inv[(int64_t)j * nj + i] * rs[p][j];
+    dbuf[off + i] = s;
+  }
+}
+
+// Cut patches, phase 2: x[I_j] += d_j for all patches of the colour.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cut_update(const int32_t* __restrict__ nodes, int64_t n,
+                                                    const T* __restrict__ dbuf, T* __restrict__ x) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) x[nodes[e]] += dbuf[e];
+}
+
+// x_f[I] += sum_J P(I, J) x_c[J] for every active fine node (embedding).
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const T* __restrict__ xc,
+                                                     T* __restrict__ xf) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1;
+  __shared__ double p1d[S::NC1 * N1];
+  for (int t = threadIdx.x; t < S::NC1 * N1; t += blockDim.x) p1d[t] = Lf.tables[S::T_P1D + t];
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= Lf.n_dofs) return;
+  const int32_t node = Lf.dof_node[i];
+  int J0[3], nq[3];
+  double w[3][N1];
+  int r = node;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int I = r % Lf.nn;
+    r /= Lf.nn;
+    const int q = I % (2 * K);
+    if (q == 0) { J0[a] = I / 2; nq[a] = 1; w[a][0] = 1.0; }
+    else {
+      J0[a] = K * (I / (2 * K));
+      nq[a] = N1;
+#pragma unroll
+      for (int bb = 0; bb < N1; ++bb) w[a][bb] = p1d[q * N1 + bb];
+    }
+  }
+  T acc = 0;
+  const int ncomb = nq[0] * nq[1] * (D == 3 ? nq[2] : 1);
+  for (int comb = 0; comb < ncomb; ++comb) {
+    int J[3];
+    double wt = 1.0;
+    int rc = comb;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int s = rc % nq[a];
+      rc /= nq[a];
+      J[a] = J0[a] + s;
+      wt *= w[a][s];
+    }
+    acc += (T)wt * xc[lat(D, Lc.nn, J)];
+  }
+  xf[node] += acc;
+}
+
+// b_c[J] = sum_I P(I, J) r_f[I] for every active coarse node (transpose).
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T* __restrict__ rf,
+                                                  T* __restrict__ bc) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1;
+  constexpr int MAXL = 4 * K - 1;
+  __shared__ double p1d[S::NC1 * N1];
+  for (int t = threadIdx.x; t < S::NC1 * N1; t += blockDim.x) p1d[t] = Lf.tables[S::T_P1D + t];
+  __syncthreads();
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= Lc.n_dofs) return;
+  const int32_t node = Lc.dof_node[j];
+  int fi[3][MAXL], nf[3];
+  double w[3][MAXL];
+  int r = node;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int J = r % Lc.nn;
+    r /= Lc.nn;
+    int n = 0;
+    if (J % K == 0) {
+      const int v = J / K;
+      fi[a][n] = 2 * J;
+      w[a][n] = 1.0;
+      ++n;
+      if (v - 1 >= 0)
+        for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * (v - 1) + q; w[a][n] = p1d[q * N1 + K]; ++n; }
+      if (v < Lc.N)
+        for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * v + q; w[a][n] = p1d[q * N1 + 0]; ++n; }
+    } else {
+      const int C = J / K, bb = J % K;
+      for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * C + q; w[a][n] = p1d[q * N1 + bb]; ++n; }
+    }
+    nf[a] = n;
+  }
+  T acc = 0;
+  const int ncomb = nf[0] * nf[1] * (D == 3 ? nf[2] : 1);
+  for (int comb = 0; comb < ncomb; ++comb) {
+    int I[3];
+    double wt = 1.0;
+    int rc = comb;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int s = rc % nf[a];
+      rc /= nf[a];
+      I[a] = fi[a][s];
+      wt *= w[a][s];
+    }
+    acc += (T)wt * rf[lat(D, Lf.nn, I)];
+  }
+  bc[node] = acc;
+}
+
+// x_0 = A_0^{-1} b_0 on the coarsest level: one 64-wide wavefront per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const int32_t* __restrict__ dof_node,
+                                                int n0, const T* __restrict__ b, T* __restrict__ x) {
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= n0) return;
+  T s = 0;
+  for (int j = lane; j < n0; j += 64) s += inv[(int64_t)row * n0 + j] * b[dof_node[j]];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) x[dof_node[row]] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_active(const int32_t* __restrict__ dof_node, int64_t n, T* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[dof_node[i]] = 0;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ dof_node, int64_t n,
+                                                 const TS* __restrict__ src, TD* __restrict__ lat_dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) lat_dst[dof_node[i]] = (TD)src[i];
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ dof_node, int64_t n,
+                                                const TS* __restrict__ lat_src, TD* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (TD)lat_src[dof_node[i]];
+}
+
+}  // namespace dev
+
+// ---------------------------------------------------------------------------
+// Host launchers: dispatch on (dimension, degree).
+namespace {
+
+inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
+
+template <typename F>
+hipError_t dispatch(int d, int k, F&& f) {
+  if (d == 2 && k == 1) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+  if (d == 2 && k == 2) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+  if (d == 2 && k == 3) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+  if (d == 3 && k == 1) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{});
+  if (d == 3 && k == 2) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
+  if (d == 3 && k == 3) return f(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int tables_size(int d, int k) {
+  int n = -1;
+  (void)dispatch(d, k, [&](auto D, auto K) {
+    n = dev::Shape<D.value, K.value>::T_SIZE;
+    return hipSuccess;
+  });
+  return n;
+}
+
+template <typename T>
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, hipStream_t s) {
+  if (L.n_dofs == 0) return hipSuccess;
+  return dispatch(d, k, [&](auto D, auto K) {
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(blocks(L.n_dofs)), dim3(256), 0, s, L, x, b, y);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
+                                hipStream_t s) {
+  if (nv == 0) return hipSuccess;
+  return dispatch(d, k, [&](auto D, auto K) {
+    constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
+    hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(blocks(nv, PPB)), dim3(256), 0, s, L,
+                       verts, nv, x, b);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_cut_step(int d, int k, const KLevel& L, const CutGroupDev& G, T* x, const T* b, T* dbuf,
+                           hipStream_t s) {
+  if (G.n_patch == 0) return hipSuccess;
+  return dispatch(d, k, [&](auto D, auto K) {
+    constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
+    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(blocks(G.n_patch, PPB)), dim3(256), 0, s, L,
+                       G, x, b, dbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes)), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf,
+                       x);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s) {
+  return dispatch(d, k, [&](auto D, auto K) {
+    hipLaunchKernelGGL((dev::k_prolong_add<D.value, K.value, T>), dim3(blocks(Lf.n_dofs)), dim3(256), 0, s, Lc, Lf,
+                       xc, xf);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s) {
+  return dispatch(d, k, [&](auto D, auto K) {
+    hipLaunchKernelGGL((dev::k_restrict<D.value, K.value, T>), dim3(blocks(Lc.n_dofs)), dim3(256), 0, s, Lc, Lf,
+                       rf, bc);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((dev::k_coarse<T>), dim3(blocks(n0, 4)), dim3(256), 0, s, inv, dof_node, n0, b, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((dev::k_zero_active<T>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, x);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((dev::k_scatter<TS, TD>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, src, lat);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((dev::k_gather<TS, TD>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, lat, dst);
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply<double>(int, int, const KLevel&, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_interior_step<double>(int, int, const KLevel&, const int32_t*, int, double*,
+                                                 const double*, hipStream_t);
+template hipError_t launch_cut_step<double>(int, int, const KLevel&, const CutGroupDev&, double*, const double*,
+                                            double*, hipStream_t);
+template hipError_t launch_prolong_add<double>(int, int, const KLevel&, const KLevel&, const double*, double*,
+                                               hipStream_t);
+template hipError_t launch_restrict<double>(int, int, const KLevel&, const KLevel&, const double*, double*,
+                                            hipStream_t);
+template hipError_t launch_coarse<double>(const double*, const int32_t*, int, const double*, double*, hipStream_t);
+template hipError_t launch_zero_active<double>(const int32_t*, int64_t, double*, hipStream_t);
+template hipError_t launch_scatter<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
+template hipError_t launch_gather<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
+
+}  // namespace cmg
+
+// ---------------------------------------------------------------------------
+// Vector kernels of the Krylov solver on compact vectors.
+namespace cmg {
+namespace dev {
+
+// Per-block partial sums of x . y (fixed order, so repeat runs are bitwise equal).
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y,
+                                                     int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_axpy(int64_t n, double a, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+__global__ __launch_bounds__(256) void k_xpay(int64_t n, double a, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] + a * y[i];
+}
+
+}  // namespace dev
+
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(dev::k_dot_partial, dim3(nblk), dim3(256), 0, s, x, y, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_axpy, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_xpay, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace cmg

@@ -1,0 +1,226 @@
+"""ctypes binding of libcutmg.so (the C ABI declared in include/cutmg.h).
+
+Argument marshalling only: every step of the multigrid runs in the HIP library.
+Vectors are torch tensors on the GPU (float64, contiguous, canonical DoF order
+of their level); torch provides the device memory and the current HIP stream.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_HERE, "libcutmg.so")
+
+CMG_STATUS = {0: "CMG_OK", -1: "CMG_EINVAL", -2: "CMG_ENOMEM", -3: "CMG_EGEOM", -4: "CMG_ENOTSPD",
+              -5: "CMG_ENOTCONV", -6: "CMG_EBREAKDOWN", -7: "CMG_EHIP"}
+
+
+class CutmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{CMG_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class LevelSet(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_shapes", ctypes.c_int),
+                ("centers", ctypes.POINTER(ctypes.c_double)), ("semi", ctypes.POINTER(ctypes.c_double)),
+                ("box_lo", ctypes.c_double), ("box_hi", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("n_levels", ctypes.c_int), ("coarse_cells", ctypes.c_int),
+                ("gamma_D", ctypes.c_double), ("gamma_g", ctypes.c_double), ("ghost_exp_mode", ctypes.c_int),
+                ("n_c", ctypes.c_int), ("quad_n", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("n_frac", ctypes.c_double)]
+
+
+EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
+            "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured",
+            "cmg_export", "cmg_destroy", "cmg_last_error"]
+
+_lib = None
+
+
+def load_library():
+    """Load libcutmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBRARY_PATH):
+        raise RuntimeError(f"{LIBRARY_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIBRARY_PATH)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "cmg_setup": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), ctypes.POINTER(P)],
+        "cmg_setup_host": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), ctypes.POINTER(P)],
+        "cmg_ndofs": [P, I, ctypes.POINTER(ctypes.c_int64)],
+        "cmg_apply": [P, I, V, V, V],
+        "cmg_colour_step": [P, I, I, I, V, V, V],
+        "cmg_smooth": [P, I, I, V, V, V],
+        "cmg_transfer": [P, I, I, V, V, V],
+        "cmg_coarse_solve": [P, V, V, V],
+        "cmg_vcycle": [P, V, V, V],
+        "cmg_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
+        "cmg_rhs_manufactured": [P, ctypes.POINTER(ctypes.c_double)],
+        "cmg_export": [P, I, I, V, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.cmg_destroy.argtypes = [P]
+    lib.cmg_destroy.restype = None
+    lib.cmg_last_error.argtypes = []
+    lib.cmg_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise CutmgError(status, _lib.cmg_last_error().decode())
+
+
+def _dev(t, n=None):
+    """Device pointer of a contiguous float64 CUDA tensor (optionally of length n)."""
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Problem:
+    """One CutFEM multigrid hierarchy owned by the library."""
+
+    def __init__(self, workload, device: bool = True, quad_n: int = 14):
+        lib = load_library()
+        d = workload.dim
+        self.workload = workload
+        self.dim = d
+        self._centers = (ctypes.c_double * (len(workload.centers) * d))(*[v for c in workload.centers for v in c])
+        self._semi = (ctypes.c_double * (len(workload.semi) * d))(*[v for s in workload.semi for v in s])
+        ls = LevelSet(d, len(workload.centers), self._centers, self._semi, workload.lo, workload.hi)
+        prm = Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
+                     workload.ghost_exp_mode, workload.n_c, quad_n)
+        h = ctypes.c_void_p()
+        fn = lib.cmg_setup if device else lib.cmg_setup_host
+        _check(fn(ctypes.byref(ls), ctypes.byref(prm), ctypes.byref(h)))
+        self._h = h
+        self.n_levels = workload.n_levels
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _lvl(self, level):
+        return self.n_levels - 1 if level is None or level < 0 else level
+
+    def ndofs(self, level=None) -> int:
+        n = ctypes.c_int64()
+        _check(_lib.cmg_ndofs(self._h, self._lvl(level), ctypes.byref(n)))
+        return n.value
+
+    def _empty(self, level):
+        import torch
+
+        return torch.empty(self.ndofs(level), dtype=torch.float64, device="cuda")
+
+    def apply(self, level, x, y=None):
+        level = self._lvl(level)
+        y = self._empty(level) if y is None else y
+        n = self.ndofs(level)
+        _check(_lib.cmg_apply(self._h, level, _dev(x, n), _dev(y, n), _stream()))
+        return y
+
+    def colour_step(self, level, interior: bool, colour: int, x, b):
+        level = self._lvl(level)
+        n = self.ndofs(level)
+        _check(_lib.cmg_colour_step(self._h, level, int(bool(interior)), colour, _dev(x, n), _dev(b, n), _stream()))
+        return x
+
+    def smooth(self, level, post: bool, x, b):
+        level = self._lvl(level)
+        n = self.ndofs(level)
+        _check(_lib.cmg_smooth(self._h, level, int(bool(post)), _dev(x, n), _dev(b, n), _stream()))
+        return x
+
+    def prolongate(self, level, xc, y=None):
+        level = self._lvl(level)
+        y = self._empty(level) if y is None else y
+        _check(_lib.cmg_transfer(self._h, level, 0, _dev(xc, self.ndofs(level - 1)), _dev(y, self.ndofs(level)),
+                                 _stream()))
+        return y
+
+    def restrict(self, level, xf, y=None):
+        level = self._lvl(level)
+        y = self._empty(level - 1) if y is None else y
+        _check(_lib.cmg_transfer(self._h, level, 1, _dev(xf, self.ndofs(level)), _dev(y, self.ndofs(level - 1)),
+                                 _stream()))
+        return y
+
+    def coarse_solve(self, b, x=None):
+        x = self._empty(0) if x is None else x
+        n = self.ndofs(0)
+        _check(_lib.cmg_coarse_solve(self._h, _dev(b, n), _dev(x, n), _stream()))
+        return x
+
+    def vcycle(self, r, z=None):
+        z = self._empty(None) if z is None else z
+        n = self.ndofs(None)
+        _check(_lib.cmg_vcycle(self._h, _dev(r, n), _dev(z, n), _stream()))
+        return z
+
+    def solve(self, b, x=None, rtol=1e-8, maxit=200, raise_on_fail=True):
+        x = self._empty(None) if x is None else x
+        n = self.ndofs(None)
+        info = SolveInfo()
+        st = _lib.cmg_solve(self._h, _dev(b, n), _dev(x, n), rtol, maxit, ctypes.byref(info), _stream())
+        if raise_on_fail:
+            _check(st)
+        return x, {"iterations": info.iterations, "rel_residual": info.rel_residual, "n_frac": info.n_frac,
+                   "status": st}
+
+    def rhs_manufactured(self) -> np.ndarray:
+        b = np.empty(self.ndofs(None), dtype=np.float64)
+        _check(_lib.cmg_rhs_manufactured(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return b
+
+    def export(self, level, what: int, dtype) -> np.ndarray:
+        level = self._lvl(level)
+        need = ctypes.c_size_t()
+        _check(_lib.cmg_export(self._h, level, what, None, 0, ctypes.byref(need)))
+        out = np.empty(need.value // np.dtype(dtype).itemsize, dtype=dtype)
+        if need.value:
+            _check(_lib.cmg_export(self._h, level, what, out.ctypes.data_as(ctypes.c_void_p), need.value,
+                                   ctypes.byref(need)))
+        return out
+
+    def counts(self, level=None) -> dict:
+        v = self.export(level, 0, np.int64)
+        keys = ["n_dofs", "active_cells", "cut_cells", "interior_patches", "cut_patches", "sum_nj2",
+                "ghost_faces", "nodes_per_dir"]
+        return dict(zip(keys, (int(t) for t in v)))

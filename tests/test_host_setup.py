@@ -1,0 +1,123 @@
+"""The library's host set-up (geometry, cut-cell matrices, patches, local and
+coarse inverses) against the oracle, on the CPU: cmg_setup_host does no device
+work.  Also checks that the C ABI exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import problem as OP
+from oracle.assemble import cut_cell_matrix
+from oracle.multigrid import build_patches
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2508_11608_amd", "libcutmg.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcutmg.so not built")
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "cutmg.h")).read()
+    declared = set(re.findall(r"\b(cmg_[a-z_]+)\s*\(", header))
+    lib = ctypes.CDLL(LIB)
+    missing = [name for name in sorted(declared) if not hasattr(lib, name)]
+    assert not missing, missing
+    from paper_2508_11608_amd import EXPORTED
+    assert declared == set(EXPORTED)
+
+
+def _workloads():
+    return [W.disc_q2(), W.offcentre_disc(3, 3), W.offcentre_disc(1, 4), W.ellipse(2, 3),
+            W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2)]
+
+
+@pytest.fixture(scope="module", params=_workloads(), ids=lambda w: w.name)
+def pair(request):
+    from paper_2508_11608_amd import Problem
+
+    w = request.param
+    P = Problem(w, device=False)
+    levels, mats, prols, H = OP.build(w)
+    return w, P, levels, mats, H
+
+
+def _dof_of_lattice(level, nodes):
+    flat = level.dof_of_node.transpose().reshape(-1)  # x fastest lattice numbering
+    return flat[nodes]
+
+
+def test_dof_numbering(pair):
+    w, P, levels, _, _ = pair
+    for l, lev in enumerate(levels):
+        dn = P.export(l, 1, np.int32)
+        assert len(dn) == lev.n_dofs
+        assert np.array_equal(_dof_of_lattice(lev, dn), np.arange(lev.n_dofs))
+        flags = P.export(l, 2, np.uint8).reshape((lev.N,) * w.dim)
+        assert np.array_equal((flags & 1).astype(bool), lev.active.transpose())
+        assert np.array_equal((flags & 2).astype(bool), lev.cut.transpose())
+
+
+def test_cut_cell_matrices(pair):
+    w, P, levels, _, _ = pair
+    shape = OP.shapes_of(w)[0]
+    fp = OP.form_params(w)
+    nl = (w.k + 1) ** w.dim
+    for l in (0, len(levels) - 1):
+        lev = levels[l]
+        E = P.export(l, 3, np.float64).reshape(-1, nl, nl)
+        cells = [tuple(int(v) for v in reversed(c)) for c in np.argwhere(lev.cut.transpose())]
+        assert len(cells) == E.shape[0]
+        step = max(1, len(cells) // 25)
+        for i in range(0, len(cells), step):
+            ref = cut_cell_matrix(lev, shape, cells[i], fp)
+            assert np.abs(E[i] - ref).max() <= 2e-13 * np.abs(ref).max(), (l, cells[i])
+
+
+def test_patches_and_local_inverses(pair):
+    w, P, levels, mats, H = pair
+    d = w.dim
+    for l in range(1, len(levels)):
+        lev = levels[l]
+        NV = lev.N + 1
+        groups = H.patches[l]
+        for c in range(2 ** d):
+            verts = P.export(l, 16 + c, np.int32)
+            ref = groups.get((True, c))
+            ref_v = sorted(sum(V[i] * NV ** i for i in range(d)) for V in (ref.vertices if ref else []))
+            assert sorted(verts.tolist()) == ref_v
+            off = P.export(l, 24 + c, np.int32)
+            nodes = P.export(l, 32 + c, np.int32)
+            inv = P.export(l, 40 + c, np.float64)
+            cverts = P.export(l, 48 + c, np.int32)
+            ref = groups.get((False, c))
+            if ref is None:
+                assert len(cverts) == 0
+                continue
+            by_vertex = {sum(V[i] * NV ** i for i in range(d)): (dofs, iv)
+                         for V, dofs, iv in zip(ref.vertices, ref.dofs, ref.invs)}
+            assert sorted(cverts.tolist()) == sorted(by_vertex)
+            pos = 0
+            for p, v in enumerate(cverts):
+                dofs = _dof_of_lattice(lev, nodes[off[p]:off[p + 1]])
+                rdofs, rinv = by_vertex[int(v)]
+                assert np.array_equal(dofs, rdofs)
+                nj = len(dofs)
+                mine = inv[pos:pos + nj * nj].reshape(nj, nj)
+                pos += nj * nj
+                assert np.abs(mine - rinv).max() <= 1e-10 * np.abs(rinv).max()
+
+
+def test_coarse_inverse(pair):
+    w, P, levels, mats, H = pair
+    inv = P.export(0, 4, np.float64).reshape(levels[0].n_dofs, -1)
+    ref = np.linalg.inv(mats[0].toarray())
+    assert np.abs(inv - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_manufactured_rhs(pair):
+    w, P, levels, _, _ = pair
+    b = P.rhs_manufactured()
+    ref = OP.rhs(w, levels[-1])
+    assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
