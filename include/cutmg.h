@@ -122,6 +122,20 @@ cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream);
 cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
                      void* stream);
 
+/* Kernel timing for measurements.  While kind_mask is non-zero, every kernel
+ * launch of a kind whose bit is set is bracketed by HIP events on its stream.
+ * Kinds: 0 operator apply / residual, 1 interior colour step, 2 cut colour
+ * step (residual + dense solve), 3 cut colour update, 4 prolongation,
+ * 5 restriction, 6 coarse solve, 7 layout (zero / scatter / gather),
+ * 8 CG vector operations.  cmg_timing synchronises the device and clears the
+ * records; 0 switches timing off. */
+cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask);
+
+/* Launch count and summed event time (ms) of one kernel kind since the last
+ * cmg_timing call, on one level (or all levels for level = -1).  Synchronises
+ * on the recorded events. */
+cmg_status cmg_timing_read(cmg_problem* p, int kind, int level, int64_t* launches, double* total_ms);
+
 /* Load vector of the manufactured problem u = prod_j sin(pi x_j), f = -Laplace u,
  * Dirichlet data g = u (symmetric Nitsche terms), finest level, written to a
  * HOST array of cmg_ndofs(finest) doubles. */

@@ -51,6 +51,12 @@ struct cmg_problem {
   double* part_host = nullptr;
   int nblk = 0;
   int device = 0;
+  // kernel timing: launches of the kinds in timing_mask are bracketed by events
+  unsigned timing_mask = 0;
+  struct Rec { int kind, level; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
 };
 
 namespace {
@@ -167,15 +173,51 @@ cmg_status check_level(const cmg_problem* p, int level, bool need_fine) {
   return CMG_OK;
 }
 
+// Brackets one kernel launch with HIP events when its kind is being timed.
+struct KTimer {
+  cmg_problem* P;
+  int kind, level;
+  hipStream_t s;
+  hipEvent_t b = nullptr;
+  KTimer(cmg_problem* P_, int kind_, int level_, hipStream_t s_) : P(P_), kind(kind_), level(level_), s(s_) {
+    if (!(P->timing_mask & (1u << kind))) return;
+    if (P->pool_used + 2 > P->pool.size()) {
+      for (int i = 0; i < 1024; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        P->pool.push_back(e);
+      }
+    }
+    hipEvent_t a = P->pool[P->pool_used++];
+    b = P->pool[P->pool_used++];
+    (void)hipEventRecord(a, s);
+    P->recs.push_back({kind, level, a, b});
+  }
+  ~KTimer() {
+    if (b) (void)hipEventRecord(b, s);
+  }
+};
+
+enum KernelKind { kApply = 0, kInterior = 1, kCutSolve = 2, kCutUpdate = 3, kProlong = 4, kRestrict = 5,
+                  kCoarse = 6, kLayout = 7, kVector = 8 };
+
 // ---- device-side building blocks on the internal lattice vectors ------------
 
 cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s) {
   const int d = P->H.cfg.dim, k = P->H.cfg.k;
   DevLevel& D = P->lv[l];
   if (interior) {
+    if (D.n_int[colour] == 0) return CMG_OK;
+    KTimer t(P, kInterior, l, s);
     HIP_TRY(cmg::launch_interior_step<double>(d, k, D.kl, D.int_verts[colour], D.n_int[colour], D.x, D.b, s));
   } else {
-    HIP_TRY(cmg::launch_cut_step<double>(d, k, D.kl, D.cut[colour], D.x, D.b, D.dbuf, s));
+    if (D.cut[colour].n_patch == 0) return CMG_OK;
+    {
+      KTimer t(P, kCutSolve, l, s);
+      HIP_TRY(cmg::launch_cut_solve<double>(d, k, D.kl, D.cut[colour], D.x, D.b, D.dbuf, s));
+    }
+    KTimer t(P, kCutUpdate, l, s);
+    HIP_TRY(cmg::launch_cut_update<double>(D.cut[colour], D.dbuf, D.x, s));
   }
   return CMG_OK;
 }
@@ -193,6 +235,7 @@ cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s) {
 
 cmg_status coarse(cmg_problem* P, hipStream_t s) {
   DevLevel& D = P->lv[0];
+  KTimer t(P, kCoarse, 0, s);
   HIP_TRY(cmg::launch_coarse<double>(P->coarse_inv, D.kl.dof_node, static_cast<int>(P->H.n_coarse), D.b, D.x, s));
   return CMG_OK;
 }
@@ -203,32 +246,47 @@ cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s) {
   const int L = P->H.cfg.n_levels - 1;
   for (int l = L; l >= 1; --l) {
     DevLevel& D = P->lv[l];
-    HIP_TRY(cmg::launch_zero_active<double>(D.kl.dof_node, D.kl.n_dofs, D.x, s));
+    {
+      KTimer t(P, kLayout, l, s);
+      HIP_TRY(cmg::launch_zero_active<double>(D.kl.dof_node, D.kl.n_dofs, D.x, s));
+    }
     TRY(smooth(P, l, false, s));
-    HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, D.b, D.r, s));
+    {
+      KTimer t(P, kApply, l, s);
+      HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, D.b, D.r, s));
+    }
+    KTimer t(P, kRestrict, l, s);
     HIP_TRY(cmg::launch_restrict<double>(d, k, P->lv[l - 1].kl, D.kl, D.r, P->lv[l - 1].b, s));
   }
   TRY(coarse(P, s));
   for (int l = 1; l <= L; ++l) {
     DevLevel& D = P->lv[l];
-    HIP_TRY(cmg::launch_prolong_add<double>(d, k, P->lv[l - 1].kl, D.kl, P->lv[l - 1].x, D.x, s));
+    {
+      KTimer t(P, kProlong, l, s);
+      HIP_TRY(cmg::launch_prolong_add<double>(d, k, P->lv[l - 1].kl, D.kl, P->lv[l - 1].x, D.x, s));
+    }
     TRY(smooth(P, l, true, s));
   }
   return CMG_OK;
 }
 
 cmg_status scatter(cmg_problem* P, int l, const double* src, double* lat, hipStream_t s) {
+  KTimer t(P, kLayout, l, s);
   HIP_TRY(cmg::launch_scatter<double, double>(P->lv[l].kl.dof_node, P->lv[l].kl.n_dofs, src, lat, s));
   return CMG_OK;
 }
 
 cmg_status gather(cmg_problem* P, int l, const double* lat, double* dst, hipStream_t s) {
+  KTimer t(P, kLayout, l, s);
   HIP_TRY(cmg::launch_gather<double, double>(P->lv[l].kl.dof_node, P->lv[l].kl.n_dofs, lat, dst, s));
   return CMG_OK;
 }
 
 cmg_status dot(cmg_problem* P, const double* x, const double* y, int64_t n, hipStream_t s, double* out) {
-  HIP_TRY(cmg::launch_dot_partial(x, y, n, P->part, P->nblk, s));
+  {
+    KTimer t(P, kVector, P->H.cfg.n_levels - 1, s);
+    HIP_TRY(cmg::launch_dot_partial(x, y, n, P->part, P->nblk, s));
+  }
   HIP_TRY(hipMemcpyAsync(P->part_host, P->part, P->nblk * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   double acc = 0.0;
@@ -318,6 +376,7 @@ void cmg_destroy(cmg_problem* p) {
     for (void* v : d.owned) (void)hipFree(v);
   for (void* v : p->owned) (void)hipFree(v);
   if (p->part_host) (void)hipHostFree(p->part_host);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -427,14 +486,20 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
   double rel = 1.0;
   for (int it = 1; it <= maxit; ++it) {
     TRY(scatter(p, L, p->kp, D.x, s));
-    HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, nullptr, D.r, s));
+    {
+      KTimer t(p, kApply, L, s);
+      HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, nullptr, D.r, s));
+    }
     TRY(gather(p, L, D.r, p->kq, s));
     double pq;
     TRY(dot(p, p->kp, p->kq, n, s, &pq));
     if (!(pq > 0.0) || !std::isfinite(pq)) return fail(CMG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
     const double alpha = rz / pq;
-    HIP_TRY(cmg::launch_axpy(n, alpha, p->kp, x, s));
-    HIP_TRY(cmg::launch_axpy(n, -alpha, p->kq, p->kr, s));
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_axpy(n, alpha, p->kp, x, s));
+      HIP_TRY(cmg::launch_axpy(n, -alpha, p->kq, p->kr, s));
+    }
     double rr;
     TRY(dot(p, p->kr, p->kr, n, s, &rr));
     rel = std::sqrt(rr) / nb;
@@ -447,10 +512,38 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
     TRY(cmg_vcycle(p, p->kr, p->kz, s));
     double rz_new;
     TRY(dot(p, p->kr, p->kz, n, s, &rz_new));
-    HIP_TRY(cmg::launch_xpay(n, rz_new / rz, p->kz, p->kp, s));
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_xpay(n, rz_new / rz, p->kz, p->kp, s));
+    }
     rz = rz_new;
   }
   return fail(CMG_ENOTCONV, "CG did not converge within maxit");
+}
+
+cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {
+  TRY(check_device(p));
+  HIP_TRY(hipDeviceSynchronize());
+  p->timing_mask = kind_mask;
+  p->recs.clear();
+  p->pool_used = 0;
+  return CMG_OK;
+}
+
+cmg_status cmg_timing_read(cmg_problem* p, int kind, int level, int64_t* launches, double* total_ms) {
+  TRY(check_device(p));
+  if (!launches || !total_ms) return fail(CMG_EINVAL, "null output");
+  *launches = 0;
+  *total_ms = 0.0;
+  for (const auto& r : p->recs) {
+    if (r.kind != kind || (level >= 0 && r.level != level)) continue;
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    *launches += 1;
+    *total_ms += ms;
+  }
+  return CMG_OK;
 }
 
 cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host) {

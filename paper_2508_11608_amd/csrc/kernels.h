@@ -42,8 +42,10 @@ template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
                                 hipStream_t s);
 template <typename T>
-hipError_t launch_cut_step(int d, int k, const KLevel& L, const CutGroupDev& G, T* x, const T* b, T* dbuf,
-                           hipStream_t s);
+hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s);
 template <typename T>

@@ -562,19 +562,22 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
 }
 
 template <typename T>
-hipError_t launch_cut_step(int d, int k, const KLevel& L, const CutGroupDev& G, T* x, const T* b, T* dbuf,
-                           hipStream_t s) {
+hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
+                            hipStream_t s) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
     hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(blocks(G.n_patch, PPB)), dim3(256), 0, s, L,
                        G, x, b, dbuf);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes)), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf,
-                       x);
     return hipGetLastError();
   });
+}
+
+template <typename T>
+hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, hipStream_t s) {
+  if (G.n_nodes == 0) return hipSuccess;
+  hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes)), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf, x);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -625,8 +628,9 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
 template hipError_t launch_apply<double>(int, int, const KLevel&, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_interior_step<double>(int, int, const KLevel&, const int32_t*, int, double*,
                                                  const double*, hipStream_t);
-template hipError_t launch_cut_step<double>(int, int, const KLevel&, const CutGroupDev&, double*, const double*,
-                                            double*, hipStream_t);
+template hipError_t launch_cut_solve<double>(int, int, const KLevel&, const CutGroupDev&, const double*,
+                                             const double*, double*, hipStream_t);
+template hipError_t launch_cut_update<double>(const CutGroupDev&, const double*, double*, hipStream_t);
 template hipError_t launch_prolong_add<double>(int, int, const KLevel&, const KLevel&, const double*, double*,
                                                hipStream_t);
 template hipError_t launch_restrict<double>(int, int, const KLevel&, const KLevel&, const double*, double*,

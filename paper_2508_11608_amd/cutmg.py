@@ -43,7 +43,7 @@ class SolveInfo(ctypes.Structure):
 
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured",
-            "cmg_export", "cmg_destroy", "cmg_last_error"]
+            "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error"]
 
 _lib = None
 
@@ -71,6 +71,8 @@ def load_library():
         "cmg_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_rhs_manufactured": [P, ctypes.POINTER(ctypes.c_double)],
         "cmg_export": [P, I, I, V, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "cmg_timing": [P, ctypes.c_uint],
+        "cmg_timing_read": [P, I, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -218,6 +220,23 @@ class Problem:
             _check(_lib.cmg_export(self._h, level, what, out.ctypes.data_as(ctypes.c_void_p), need.value,
                                    ctypes.byref(need)))
         return out
+
+    KERNEL_KINDS = {"apply": 0, "interior_step": 1, "cut_solve": 2, "cut_update": 3, "prolong": 4,
+                    "restrict": 5, "coarse": 6, "layout": 7, "vector": 8}
+
+    def timing(self, kinds=()):
+        """Bracket the launches of the named kernel kinds with HIP events (empty: off)."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << self.KERNEL_KINDS[k]
+        _check(_lib.cmg_timing(self._h, mask))
+
+    def timing_read(self, kind: str, level: int = -1):
+        """(launches, total ms) of one kernel kind since the last timing() call."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_lib.cmg_timing_read(self._h, self.KERNEL_KINDS[kind], level, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def counts(self, level=None) -> dict:
         v = self.export(level, 0, np.int64)
