@@ -69,6 +69,7 @@ typedef struct {
   int ghost_exp_mode;    /* 0: face weight h^(2m-1) / (m!)^2;  1: h^(2m+1) / (m!)^2 */
   int n_c;               /* sweeps over the cut patches per smoothing step (eq. (smoother-split)) */
   int quad_n;            /* Gauss points per smooth piece of a cut-cell rule (e.g. 14) */
+  int precond_fp32;      /* 1: the V-cycle runs in FP32 (see cmg_set_precision) */
 } cmg_params;
 
 typedef struct {
@@ -86,6 +87,15 @@ cmg_status cmg_setup(const cmg_levelset* ls, const cmg_params* prm, cmg_problem*
  * hierarchy with cmg_export on machines without a GPU.  Device calls on such a
  * problem return CMG_EINVAL. */
 cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out);
+
+/* Precision of the multigrid part: fp32 = 0 runs every V-cycle kernel in FP64;
+ * fp32 = 1 runs smoother, transfers, level residuals and the coarse solve in FP32
+ * on FP32 copies of the cut-cell matrices and of the local and coarse inverses,
+ * which are computed in FP64 and rounded (uploaded on first use).  CG
+ * (cmg_solve), its operator products and all ABI vectors stay FP64; cmg_apply,
+ * cmg_colour_step, cmg_smooth, cmg_transfer, cmg_coarse_solve and cmg_vcycle
+ * convert their FP64 arguments and run in the selected precision. */
+cmg_status cmg_set_precision(cmg_problem* p, int fp32);
 
 /* Number of DoFs on a level (0 = coarsest, n_levels-1 = finest). */
 cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);

@@ -1,5 +1,11 @@
 // C ABI of the CutFEM vertex-patch multigrid: device upload of the hierarchy,
 // V-cycle orchestration (paper Section 2.2) and preconditioned CG.
+//
+// The V-cycle runs in FP64 or, for the mixed-precision preconditioner, in FP32
+// (smoother, transfers, level residuals, coarse solve); the FP32 copies of the
+// cut-cell matrices and of the local and coarse inverses are rounded from the
+// FP64 factorisations.  CG, its operator products and every ABI vector stay
+// FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,22 +27,34 @@ cmg_status fail(cmg_status s, const std::string& msg) {
   return s;
 }
 
-#define HIP_TRY(...)                                                                      \
-  do {                                                                                    \
-    hipError_t e_ = (__VA_ARGS__);                                                            \
+#define HIP_TRY(...)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (__VA_ARGS__);                                                                       \
     if (e_ != hipSuccess) return fail(CMG_EHIP, std::string(#__VA_ARGS__ ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+#define TRY(expr)                \
+  do {                           \
+    cmg_status s_ = (expr);      \
+    if (s_ != CMG_OK) return s_; \
+  } while (0)
+
+template <typename T>
+struct Vecs {
+  T* x = nullptr;  // lattice work vectors
+  T* b = nullptr;
+  T* r = nullptr;
+  T* dbuf = nullptr;  // cut-patch corrections of one colour
+};
+
 struct DevLevel {
-  cmg::KLevel kl{};
-  std::vector<void*> owned;
-  double* x = nullptr;   // lattice work vectors
-  double* b = nullptr;
-  double* r = nullptr;
-  double* dbuf = nullptr;
+  cmg::KLevel kl64{}, kl32{};
+  Vecs<double> v64;
+  Vecs<float> v32;
   int32_t* int_verts[8] = {};
   int n_int[8] = {};
-  cmg::CutGroupDev cut[8] = {};
+  cmg::CutGroupDev cut64[8] = {}, cut32[8] = {};
+  int64_t max_cut_nodes = 0;
 };
 
 }  // namespace
@@ -44,8 +62,11 @@ struct DevLevel {
 struct cmg_problem {
   cmg::Hierarchy H;
   std::vector<DevLevel> lv;
-  double* coarse_inv = nullptr;
   std::vector<void*> owned;
+  double* coarse64 = nullptr;
+  float* coarse32 = nullptr;
+  bool fp32_ready = false;
+  bool fp32 = false;  // precision of the V-cycle
   // Krylov vectors (compact, finest level)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *part = nullptr;
   double* part_host = nullptr;
@@ -53,7 +74,10 @@ struct cmg_problem {
   int device = 0;
   // kernel timing: launches of the kinds in timing_mask are bracketed by events
   unsigned timing_mask = 0;
-  struct Rec { int kind, level; hipEvent_t a, b; };
+  struct Rec {
+    int kind, level;
+    hipEvent_t a, b;
+  };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -62,102 +86,160 @@ struct cmg_problem {
 namespace {
 
 template <typename T>
-cmg_status upload(cmg_problem* P, std::vector<void*>& owned, const std::vector<T>& host, T** dptr) {
+cmg::KLevel& kl(DevLevel& D);
+template <>
+cmg::KLevel& kl<double>(DevLevel& D) { return D.kl64; }
+template <>
+cmg::KLevel& kl<float>(DevLevel& D) { return D.kl32; }
+template <typename T>
+Vecs<T>& vecs(DevLevel& D);
+template <>
+Vecs<double>& vecs<double>(DevLevel& D) { return D.v64; }
+template <>
+Vecs<float>& vecs<float>(DevLevel& D) { return D.v32; }
+template <typename T>
+cmg::CutGroupDev& cutg(DevLevel& D, int c);
+template <>
+cmg::CutGroupDev& cutg<double>(DevLevel& D, int c) { return D.cut64[c]; }
+template <>
+cmg::CutGroupDev& cutg<float>(DevLevel& D, int c) { return D.cut32[c]; }
+template <typename T>
+T* coarse_inv(cmg_problem* P);
+template <>
+double* coarse_inv<double>(cmg_problem* P) { return P->coarse64; }
+template <>
+float* coarse_inv<float>(cmg_problem* P) { return P->coarse32; }
+
+template <typename T>
+cmg_status upload(std::vector<void*>& owned, const T* host, size_t n, T** dptr) {
   *dptr = nullptr;
-  if (host.empty()) return CMG_OK;
+  if (n == 0) return CMG_OK;
   void* p = nullptr;
-  if (hipMalloc(&p, host.size() * sizeof(T)) != hipSuccess) return fail(CMG_ENOMEM, "device allocation failed");
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return fail(CMG_ENOMEM, "device allocation failed");
   owned.push_back(p);
-  HIP_TRY(hipMemcpy(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p, host, n * sizeof(T), hipMemcpyHostToDevice));
   *dptr = static_cast<T*>(p);
   return CMG_OK;
 }
 
-cmg_status alloc_zero(std::vector<void*>& owned, size_t bytes, void** dptr) {
-  *dptr = nullptr;
-  if (bytes == 0) return CMG_OK;
-  if (hipMalloc(dptr, bytes) != hipSuccess) return fail(CMG_ENOMEM, "device allocation failed");
-  owned.push_back(*dptr);
-  HIP_TRY(hipMemset(*dptr, 0, bytes));
-  return CMG_OK;
+template <typename T>
+cmg_status upload(std::vector<void*>& owned, const std::vector<T>& host, T** dptr) {
+  return upload(owned, host.data(), host.size(), dptr);
 }
 
-#define TRY(expr)                       \
-  do {                                  \
-    cmg_status s_ = (expr);             \
-    if (s_ != CMG_OK) return s_;        \
-  } while (0)
+cmg_status upload_f32(std::vector<void*>& owned, const std::vector<double>& host, float** dptr) {
+  std::vector<float> f(host.begin(), host.end());
+  return upload(owned, f, dptr);
+}
+
+template <typename T>
+cmg_status alloc_zero(std::vector<void*>& owned, size_t n, T** dptr) {
+  *dptr = nullptr;
+  if (n == 0) return CMG_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return fail(CMG_ENOMEM, "device allocation failed");
+  owned.push_back(p);
+  HIP_TRY(hipMemset(p, 0, n * sizeof(T)));
+  *dptr = static_cast<T*>(p);
+  return CMG_OK;
+}
 
 cmg_status upload_all(cmg_problem* P) {
   const cmg::Config& cfg = P->H.cfg;
   const int L = cfg.n_levels;
+  auto& own = P->owned;
   P->lv.resize(L);
   for (int l = 0; l < L; ++l) {
     const cmg::HostLevel& h = P->H.levels[l];
     DevLevel& d = P->lv[l];
-    d.kl.N = h.N;
-    d.kl.nn = h.nn;
-    d.kl.n_dofs = h.n_dofs;
-    uint8_t* flags;
-    int32_t* cut_id;
-    uint8_t* ghost;
-    double* cm;
-    int32_t* dn;
-    double* tab;
-    TRY(upload(P, d.owned, h.cell_flags, &flags));
-    TRY(upload(P, d.owned, h.cut_id, &cut_id));
-    TRY(upload(P, d.owned, h.ghost_mask, &ghost));
-    TRY(upload(P, d.owned, h.cut_mats, &cm));
-    TRY(upload(P, d.owned, h.dof_node, &dn));
+    cmg::KLevel& k = d.kl64;
+    k.N = h.N;
+    k.nn = h.nn;
+    k.n_dofs = h.n_dofs;
+    uint8_t *flags, *ghost;
+    int32_t *cut_id, *dn;
+    double *cm, *tab;
+    TRY(upload(own, h.cell_flags, &flags));
+    TRY(upload(own, h.cut_id, &cut_id));
+    TRY(upload(own, h.ghost_mask, &ghost));
+    TRY(upload(own, h.cut_mats, &cm));
+    TRY(upload(own, h.dof_node, &dn));
     const cmg::LevelTables& t = P->H.tables[l];
     std::vector<double> packed;
     for (const auto* v : {&t.kcell, &t.mhat, &t.d0, &t.d1, &t.gcoef, &t.fd_s, &t.fd_dinv, &t.p1d})
       packed.insert(packed.end(), v->begin(), v->end());
     if (static_cast<int>(packed.size()) != cmg::tables_size(cfg.dim, cfg.k))
       return fail(CMG_EINVAL, "internal: table layout mismatch");
-    TRY(upload(P, d.owned, packed, &tab));
-    d.kl.flags = flags;
-    d.kl.cut_id = cut_id;
-    d.kl.ghost = ghost;
-    d.kl.cut_mats = cm;
-    d.kl.dof_node = dn;
-    d.kl.tables = tab;
-    const size_t lat_bytes = static_cast<size_t>(h.n_nodes) * sizeof(double);
-    TRY(alloc_zero(d.owned, lat_bytes, reinterpret_cast<void**>(&d.x)));
-    TRY(alloc_zero(d.owned, lat_bytes, reinterpret_cast<void**>(&d.b)));
-    TRY(alloc_zero(d.owned, lat_bytes, reinterpret_cast<void**>(&d.r)));
-    int64_t maxn = 0;
+    TRY(upload(own, packed, &tab));
+    k.flags = flags;
+    k.cut_id = cut_id;
+    k.ghost = ghost;
+    k.cut_mats = cm;
+    k.dof_node = dn;
+    k.tables = tab;
+    d.kl32 = k;
+    d.kl32.cut_mats = nullptr;
+    TRY(alloc_zero(own, h.n_nodes, &d.v64.x));
+    TRY(alloc_zero(own, h.n_nodes, &d.v64.b));
+    TRY(alloc_zero(own, h.n_nodes, &d.v64.r));
     for (int c = 0; c < 8; ++c) {
-      TRY(upload(P, d.owned, h.int_vertex[c], &d.int_verts[c]));
+      TRY(upload(own, h.int_vertex[c], &d.int_verts[c]));
       d.n_int[c] = static_cast<int>(h.int_vertex[c].size());
       const cmg::CutPatchGroup& g = h.cut[c];
-      cmg::CutGroupDev& G = d.cut[c];
+      cmg::CutGroupDev& G = d.cut64[c];
       G.n_patch = static_cast<int>(g.vertex.size());
       G.n_nodes = static_cast<int64_t>(g.nodes.size());
-      if (G.n_patch == 0) continue;
-      int32_t* off;
-      int64_t* ioff;
-      int32_t* nodes;
-      double* inv;
-      TRY(upload(P, d.owned, g.off, &off));
-      TRY(upload(P, d.owned, g.inv_off, &ioff));
-      TRY(upload(P, d.owned, g.nodes, &nodes));
-      TRY(upload(P, d.owned, g.inv, &inv));
-      G.off = off;
-      G.inv_off = ioff;
-      G.nodes = nodes;
-      G.inv = inv;
-      maxn = std::max(maxn, G.n_nodes);
+      if (G.n_patch > 0) {
+        int32_t *off, *nodes;
+        int64_t* ioff;
+        double* inv;
+        TRY(upload(own, g.off, &off));
+        TRY(upload(own, g.inv_off, &ioff));
+        TRY(upload(own, g.nodes, &nodes));
+        TRY(upload(own, g.inv, &inv));
+        G.off = off;
+        G.inv_off = ioff;
+        G.nodes = nodes;
+        G.inv = inv;
+      }
+      d.cut32[c] = G;
+      d.cut32[c].inv = nullptr;
+      d.max_cut_nodes = std::max(d.max_cut_nodes, G.n_nodes);
     }
-    TRY(alloc_zero(d.owned, static_cast<size_t>(maxn) * sizeof(double), reinterpret_cast<void**>(&d.dbuf)));
+    TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v64.dbuf));
   }
-  TRY(upload(P, P->owned, P->H.coarse_inv, &P->coarse_inv));
+  TRY(upload(own, P->H.coarse_inv, &P->coarse64));
   const int64_t n = P->H.levels.back().n_dofs;
-  for (double** v : {&P->kr, &P->kz, &P->kp, &P->kq})
-    TRY(alloc_zero(P->owned, n * sizeof(double), reinterpret_cast<void**>(v)));
+  for (double** v : {&P->kr, &P->kz, &P->kp, &P->kq}) TRY(alloc_zero(own, static_cast<size_t>(n), v));
   P->nblk = static_cast<int>(std::min<int64_t>(1024, (n + 255) / 256));
-  TRY(alloc_zero(P->owned, P->nblk * sizeof(double), reinterpret_cast<void**>(&P->part)));
+  TRY(alloc_zero(own, static_cast<size_t>(P->nblk), &P->part));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->part_host), P->nblk * sizeof(double), hipHostMallocDefault));
+  return CMG_OK;
+}
+
+// FP32 copies (rounded from the FP64 set-up) and FP32 work vectors, on first use.
+cmg_status ensure_fp32(cmg_problem* P) {
+  if (P->fp32_ready) return CMG_OK;
+  auto& own = P->owned;
+  for (size_t l = 0; l < P->lv.size(); ++l) {
+    const cmg::HostLevel& h = P->H.levels[l];
+    DevLevel& d = P->lv[l];
+    float* cm;
+    TRY(upload_f32(own, h.cut_mats, &cm));
+    d.kl32.cut_mats = cm;
+    for (int c = 0; c < 8; ++c) {
+      if (d.cut32[c].n_patch == 0) continue;
+      float* inv;
+      TRY(upload_f32(own, h.cut[c].inv, &inv));
+      d.cut32[c].inv = inv;
+    }
+    TRY(alloc_zero(own, h.n_nodes, &d.v32.x));
+    TRY(alloc_zero(own, h.n_nodes, &d.v32.b));
+    TRY(alloc_zero(own, h.n_nodes, &d.v32.r));
+    TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v32.dbuf));
+  }
+  TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
+  P->fp32_ready = true;
   return CMG_OK;
 }
 
@@ -168,7 +250,7 @@ cmg_status check_device(const cmg_problem* p) {
 }
 
 cmg_status check_level(const cmg_problem* p, int level, bool need_fine) {
-  if (!p) return fail(CMG_EINVAL, "null problem");
+  TRY(check_device(p));
   if (level < (need_fine ? 1 : 0) || level >= p->H.cfg.n_levels) return fail(CMG_EINVAL, "level out of range");
   return CMG_OK;
 }
@@ -176,10 +258,9 @@ cmg_status check_level(const cmg_problem* p, int level, bool need_fine) {
 // Brackets one kernel launch with HIP events when its kind is being timed.
 struct KTimer {
   cmg_problem* P;
-  int kind, level;
   hipStream_t s;
   hipEvent_t b = nullptr;
-  KTimer(cmg_problem* P_, int kind_, int level_, hipStream_t s_) : P(P_), kind(kind_), level(level_), s(s_) {
+  KTimer(cmg_problem* P_, int kind, int level, hipStream_t s_) : P(P_), s(s_) {
     if (!(P->timing_mask & (1u << kind))) return;
     if (P->pool_used + 2 > P->pool.size()) {
       for (int i = 0; i < 1024; ++i) {
@@ -198,30 +279,43 @@ struct KTimer {
   }
 };
 
-enum KernelKind { kApply = 0, kInterior = 1, kCutSolve = 2, kCutUpdate = 3, kProlong = 4, kRestrict = 5,
-                  kCoarse = 6, kLayout = 7, kVector = 8 };
+enum KernelKind {
+  kApply = 0,
+  kInterior = 1,
+  kCutSolve = 2,
+  kCutUpdate = 3,
+  kProlong = 4,
+  kRestrict = 5,
+  kCoarse = 6,
+  kLayout = 7,
+  kVector = 8
+};
 
 // ---- device-side building blocks on the internal lattice vectors ------------
 
+template <typename T>
 cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s) {
   const int d = P->H.cfg.dim, k = P->H.cfg.k;
   DevLevel& D = P->lv[l];
+  Vecs<T>& v = vecs<T>(D);
   if (interior) {
     if (D.n_int[colour] == 0) return CMG_OK;
     KTimer t(P, kInterior, l, s);
-    HIP_TRY(cmg::launch_interior_step<double>(d, k, D.kl, D.int_verts[colour], D.n_int[colour], D.x, D.b, s));
-  } else {
-    if (D.cut[colour].n_patch == 0) return CMG_OK;
-    {
-      KTimer t(P, kCutSolve, l, s);
-      HIP_TRY(cmg::launch_cut_solve<double>(d, k, D.kl, D.cut[colour], D.x, D.b, D.dbuf, s));
-    }
-    KTimer t(P, kCutUpdate, l, s);
-    HIP_TRY(cmg::launch_cut_update<double>(D.cut[colour], D.dbuf, D.x, s));
+    HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s));
+    return CMG_OK;
   }
+  const cmg::CutGroupDev& G = cutg<T>(D, colour);
+  if (G.n_patch == 0) return CMG_OK;
+  {
+    KTimer t(P, kCutSolve, l, s);
+    HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s));
+  }
+  KTimer t(P, kCutUpdate, l, s);
+  HIP_TRY(cmg::launch_cut_update<T>(G, v.dbuf, v.x, s));
   return CMG_OK;
 }
 
+template <typename T>
 cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s) {
   const int C = 1 << P->H.cfg.dim;
   std::vector<std::pair<bool, int>> seq;
@@ -229,56 +323,79 @@ cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s) {
   for (int r = 0; r < P->H.cfg.n_c; ++r)
     for (int c = 0; c < C; ++c) seq.push_back({false, c});
   if (post) std::reverse(seq.begin(), seq.end());
-  for (auto [interior, c] : seq) TRY(colour_step(P, l, interior, c, s));
+  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s));
   return CMG_OK;
 }
 
+template <typename T>
 cmg_status coarse(cmg_problem* P, hipStream_t s) {
   DevLevel& D = P->lv[0];
   KTimer t(P, kCoarse, 0, s);
-  HIP_TRY(cmg::launch_coarse<double>(P->coarse_inv, D.kl.dof_node, static_cast<int>(P->H.n_coarse), D.b, D.x, s));
+  HIP_TRY(cmg::launch_coarse<T>(coarse_inv<T>(P), D.kl64.dof_node, static_cast<int>(P->H.n_coarse), vecs<T>(D).b,
+                                vecs<T>(D).x, s));
   return CMG_OK;
 }
 
-// V-cycle on the lattice vectors: lv[L].x = B lv[L].b.
+template <typename T>
+cmg_status zero_active(cmg_problem* P, int l, T* x, hipStream_t s) {
+  KTimer t(P, kLayout, l, s);
+  HIP_TRY(cmg::launch_zero_active<T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, x, s));
+  return CMG_OK;
+}
+
+template <typename T>
+cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s) {
+  KTimer t(P, kApply, l, s);
+  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, s));
+  return CMG_OK;
+}
+
+template <typename T>
+cmg_status prolong_add(cmg_problem* P, int l, hipStream_t s) {
+  KTimer t(P, kProlong, l, s);
+  HIP_TRY(cmg::launch_prolong_add<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]),
+                                     vecs<T>(P->lv[l - 1]).x, vecs<T>(P->lv[l]).x, s));
+  return CMG_OK;
+}
+
+template <typename T>
+cmg_status restrict_(cmg_problem* P, int l, const T* rf, hipStream_t s) {
+  KTimer t(P, kRestrict, l, s);
+  HIP_TRY(cmg::launch_restrict<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]), rf,
+                                  vecs<T>(P->lv[l - 1]).b, s));
+  return CMG_OK;
+}
+
+// V-cycle on the lattice vectors of precision T: x_L = B b_L, zero initial guess.
+template <typename T>
 cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s) {
-  const int d = P->H.cfg.dim, k = P->H.cfg.k;
   const int L = P->H.cfg.n_levels - 1;
   for (int l = L; l >= 1; --l) {
-    DevLevel& D = P->lv[l];
-    {
-      KTimer t(P, kLayout, l, s);
-      HIP_TRY(cmg::launch_zero_active<double>(D.kl.dof_node, D.kl.n_dofs, D.x, s));
-    }
-    TRY(smooth(P, l, false, s));
-    {
-      KTimer t(P, kApply, l, s);
-      HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, D.b, D.r, s));
-    }
-    KTimer t(P, kRestrict, l, s);
-    HIP_TRY(cmg::launch_restrict<double>(d, k, P->lv[l - 1].kl, D.kl, D.r, P->lv[l - 1].b, s));
+    Vecs<T>& v = vecs<T>(P->lv[l]);
+    TRY(zero_active<T>(P, l, v.x, s));
+    TRY(smooth<T>(P, l, false, s));
+    TRY(apply_lat<T>(P, l, v.x, v.b, v.r, s));
+    TRY(restrict_<T>(P, l, v.r, s));
   }
-  TRY(coarse(P, s));
+  TRY(coarse<T>(P, s));
   for (int l = 1; l <= L; ++l) {
-    DevLevel& D = P->lv[l];
-    {
-      KTimer t(P, kProlong, l, s);
-      HIP_TRY(cmg::launch_prolong_add<double>(d, k, P->lv[l - 1].kl, D.kl, P->lv[l - 1].x, D.x, s));
-    }
-    TRY(smooth(P, l, true, s));
+    TRY(prolong_add<T>(P, l, s));
+    TRY(smooth<T>(P, l, true, s));
   }
   return CMG_OK;
 }
 
-cmg_status scatter(cmg_problem* P, int l, const double* src, double* lat, hipStream_t s) {
+template <typename T>
+cmg_status scatter(cmg_problem* P, int l, const double* src, T* lat, hipStream_t s) {
   KTimer t(P, kLayout, l, s);
-  HIP_TRY(cmg::launch_scatter<double, double>(P->lv[l].kl.dof_node, P->lv[l].kl.n_dofs, src, lat, s));
+  HIP_TRY(cmg::launch_scatter<double, T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, src, lat, s));
   return CMG_OK;
 }
 
-cmg_status gather(cmg_problem* P, int l, const double* lat, double* dst, hipStream_t s) {
+template <typename T>
+cmg_status gather(cmg_problem* P, int l, const T* lat, double* dst, hipStream_t s) {
   KTimer t(P, kLayout, l, s);
-  HIP_TRY(cmg::launch_gather<double, double>(P->lv[l].kl.dof_node, P->lv[l].kl.n_dofs, lat, dst, s));
+  HIP_TRY(cmg::launch_gather<T, double>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, lat, dst, s));
   return CMG_OK;
 }
 
@@ -295,6 +412,71 @@ cmg_status dot(cmg_problem* P, const double* x, const double* y, int64_t n, hipS
   return CMG_OK;
 }
 
+// ---- ABI operations in precision T ------------------------------------------
+
+template <typename T>
+cmg_status op_apply(cmg_problem* p, int level, const double* x, double* y, hipStream_t s) {
+  Vecs<T>& v = vecs<T>(p->lv[level]);
+  TRY(scatter<T>(p, level, x, v.x, s));
+  TRY(apply_lat<T>(p, level, v.x, nullptr, v.r, s));
+  return gather<T>(p, level, v.r, y, s);
+}
+
+template <typename T>
+cmg_status op_colour_step(cmg_problem* p, int level, bool interior, int colour, double* x, const double* b,
+                          hipStream_t s) {
+  Vecs<T>& v = vecs<T>(p->lv[level]);
+  TRY(scatter<T>(p, level, x, v.x, s));
+  TRY(scatter<T>(p, level, b, v.b, s));
+  TRY(colour_step<T>(p, level, interior, colour, s));
+  return gather<T>(p, level, v.x, x, s);
+}
+
+template <typename T>
+cmg_status op_smooth(cmg_problem* p, int level, bool post, double* x, const double* b, hipStream_t s) {
+  Vecs<T>& v = vecs<T>(p->lv[level]);
+  TRY(scatter<T>(p, level, x, v.x, s));
+  TRY(scatter<T>(p, level, b, v.b, s));
+  TRY(smooth<T>(p, level, post, s));
+  return gather<T>(p, level, v.x, x, s);
+}
+
+template <typename T>
+cmg_status op_transfer(cmg_problem* p, int level, int dir, const double* x, double* y, hipStream_t s) {
+  Vecs<T>& F = vecs<T>(p->lv[level]);
+  Vecs<T>& C = vecs<T>(p->lv[level - 1]);
+  if (dir == 0) {
+    TRY(scatter<T>(p, level - 1, x, C.x, s));
+    TRY(zero_active<T>(p, level, F.x, s));
+    TRY(prolong_add<T>(p, level, s));
+    return gather<T>(p, level, F.x, y, s);
+  }
+  TRY(scatter<T>(p, level, x, F.r, s));
+  TRY(restrict_<T>(p, level, F.r, s));
+  return gather<T>(p, level - 1, C.b, y, s);
+}
+
+template <typename T>
+cmg_status op_coarse(cmg_problem* p, const double* b, double* x, hipStream_t s) {
+  Vecs<T>& v = vecs<T>(p->lv[0]);
+  TRY(scatter<T>(p, 0, b, v.b, s));
+  TRY(coarse<T>(p, s));
+  return gather<T>(p, 0, v.x, x, s);
+}
+
+template <typename T>
+cmg_status op_vcycle(cmg_problem* p, const double* r, double* z, hipStream_t s) {
+  const int L = p->H.cfg.n_levels - 1;
+  Vecs<T>& v = vecs<T>(p->lv[L]);
+  TRY(scatter<T>(p, L, r, v.b, s));
+  TRY(vcycle_lattice<T>(p, s));
+  return gather<T>(p, L, v.x, z, s);
+}
+
+cmg_status vcycle_current(cmg_problem* p, const double* r, double* z, hipStream_t s) {
+  return p->fp32 ? op_vcycle<float>(p, r, z, s) : op_vcycle<double>(p, r, z, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -308,7 +490,8 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
   if (ls->dim < 2 || ls->dim > 3 || ls->n_shapes < 1 || !ls->centers || !ls->semi || !(ls->box_hi > ls->box_lo))
     return fail(CMG_EINVAL, "bad level set description");
   if (prm->k < 1 || prm->k > 3 || prm->n_levels < 1 || prm->n_levels > 12 || prm->coarse_cells < 1 ||
-      prm->n_c < 0 || prm->quad_n < 2 || prm->quad_n > 64 || prm->ghost_exp_mode < 0 || prm->ghost_exp_mode > 1)
+      prm->n_c < 0 || prm->quad_n < 2 || prm->quad_n > 64 || prm->ghost_exp_mode < 0 || prm->ghost_exp_mode > 1 ||
+      prm->precond_fp32 < 0 || prm->precond_fp32 > 1)
     return fail(CMG_EINVAL, "bad parameters");
   const int64_t fine = static_cast<int64_t>(prm->coarse_cells) << (prm->n_levels - 1);
   if (std::pow(static_cast<double>(prm->k * fine + 1), ls->dim) > 2.0e9)
@@ -353,6 +536,10 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
     return fail(CMG_EHIP, "no HIP device");
   }
   cmg_status st = upload_all(P);
+  if (st == CMG_OK && prm->precond_fp32) {
+    st = ensure_fp32(P);
+    P->fp32 = true;
+  }
   if (st != CMG_OK) {
     std::string msg = g_last_error;
     cmg_destroy(P);
@@ -372,95 +559,71 @@ cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_pro
 
 void cmg_destroy(cmg_problem* p) {
   if (!p) return;
-  for (auto& d : p->lv)
-    for (void* v : d.owned) (void)hipFree(v);
+  if (!p->lv.empty()) (void)hipDeviceSynchronize();
   for (void* v : p->owned) (void)hipFree(v);
   if (p->part_host) (void)hipHostFree(p->part_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
 }
 
+cmg_status cmg_set_precision(cmg_problem* p, int fp32) {
+  TRY(check_device(p));
+  if (fp32 != 0 && fp32 != 1) return fail(CMG_EINVAL, "precision flag must be 0 or 1");
+  if (fp32) TRY(ensure_fp32(p));
+  p->fp32 = fp32 != 0;
+  return CMG_OK;
+}
+
 cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n) {
-  TRY(check_level(p, level, false));
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (level < 0 || level >= p->H.cfg.n_levels) return fail(CMG_EINVAL, "level out of range");
   if (!n) return fail(CMG_EINVAL, "null output");
   *n = p->H.levels[level].n_dofs;
   return CMG_OK;
 }
 
 cmg_status cmg_apply(cmg_problem* p, int level, const double* x, double* y, void* stream) {
-  TRY(check_device(p));
   TRY(check_level(p, level, false));
   if (!x || !y) return fail(CMG_EINVAL, "null vector");
   auto s = static_cast<hipStream_t>(stream);
-  DevLevel& D = p->lv[level];
-  TRY(scatter(p, level, x, D.x, s));
-  HIP_TRY(cmg::launch_apply<double>(p->H.cfg.dim, p->H.cfg.k, D.kl, D.x, nullptr, D.r, s));
-  return gather(p, level, D.r, y, s);
+  return p->fp32 ? op_apply<float>(p, level, x, y, s) : op_apply<double>(p, level, x, y, s);
 }
 
 cmg_status cmg_colour_step(cmg_problem* p, int level, int interior, int colour, double* x, const double* b,
                            void* stream) {
-  TRY(check_device(p));
   TRY(check_level(p, level, true));
   if (colour < 0 || colour >= (1 << p->H.cfg.dim)) return fail(CMG_EINVAL, "colour out of range");
   if (!x || !b) return fail(CMG_EINVAL, "null vector");
   auto s = static_cast<hipStream_t>(stream);
-  DevLevel& D = p->lv[level];
-  TRY(scatter(p, level, x, D.x, s));
-  TRY(scatter(p, level, b, D.b, s));
-  TRY(colour_step(p, level, interior != 0, colour, s));
-  return gather(p, level, D.x, x, s);
+  return p->fp32 ? op_colour_step<float>(p, level, interior != 0, colour, x, b, s)
+                 : op_colour_step<double>(p, level, interior != 0, colour, x, b, s);
 }
 
 cmg_status cmg_smooth(cmg_problem* p, int level, int post, double* x, const double* b, void* stream) {
-  TRY(check_device(p));
   TRY(check_level(p, level, true));
   if (!x || !b) return fail(CMG_EINVAL, "null vector");
   auto s = static_cast<hipStream_t>(stream);
-  DevLevel& D = p->lv[level];
-  TRY(scatter(p, level, x, D.x, s));
-  TRY(scatter(p, level, b, D.b, s));
-  TRY(smooth(p, level, post != 0, s));
-  return gather(p, level, D.x, x, s);
+  return p->fp32 ? op_smooth<float>(p, level, post != 0, x, b, s) : op_smooth<double>(p, level, post != 0, x, b, s);
 }
 
 cmg_status cmg_transfer(cmg_problem* p, int level, int dir, const double* x, double* y, void* stream) {
-  TRY(check_device(p));
   TRY(check_level(p, level, true));
   if (!x || !y || (dir != 0 && dir != 1)) return fail(CMG_EINVAL, "bad transfer arguments");
   auto s = static_cast<hipStream_t>(stream);
-  const int d = p->H.cfg.dim, k = p->H.cfg.k;
-  DevLevel& F = p->lv[level];
-  DevLevel& C = p->lv[level - 1];
-  if (dir == 0) {
-    TRY(scatter(p, level - 1, x, C.x, s));
-    HIP_TRY(cmg::launch_zero_active<double>(F.kl.dof_node, F.kl.n_dofs, F.x, s));
-    HIP_TRY(cmg::launch_prolong_add<double>(d, k, C.kl, F.kl, C.x, F.x, s));
-    return gather(p, level, F.x, y, s);
-  }
-  TRY(scatter(p, level, x, F.r, s));
-  HIP_TRY(cmg::launch_restrict<double>(d, k, C.kl, F.kl, F.r, C.b, s));
-  return gather(p, level - 1, C.b, y, s);
+  return p->fp32 ? op_transfer<float>(p, level, dir, x, y, s) : op_transfer<double>(p, level, dir, x, y, s);
 }
 
 cmg_status cmg_coarse_solve(cmg_problem* p, const double* b, double* x, void* stream) {
   TRY(check_device(p));
-  TRY(check_level(p, 0, false));
   if (!x || !b) return fail(CMG_EINVAL, "null vector");
   auto s = static_cast<hipStream_t>(stream);
-  TRY(scatter(p, 0, b, p->lv[0].b, s));
-  TRY(coarse(p, s));
-  return gather(p, 0, p->lv[0].x, x, s);
+  return p->fp32 ? op_coarse<float>(p, b, x, s) : op_coarse<double>(p, b, x, s);
 }
 
 cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream) {
   TRY(check_device(p));
   if (!r || !z) return fail(CMG_EINVAL, "null argument");
-  auto s = static_cast<hipStream_t>(stream);
-  const int L = p->H.cfg.n_levels - 1;
-  TRY(scatter(p, L, r, p->lv[L].b, s));
-  TRY(vcycle_lattice(p, s));
-  return gather(p, L, p->lv[L].x, z, s);
+  return vcycle_current(p, r, z, static_cast<hipStream_t>(stream));
 }
 
 cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
@@ -470,27 +633,26 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
   auto s = static_cast<hipStream_t>(stream);
   const int L = p->H.cfg.n_levels - 1;
   const int64_t n = p->H.levels[L].n_dofs;
-  const int d = p->H.cfg.dim, k = p->H.cfg.k;
-  DevLevel& D = p->lv[L];
-  HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
-  HIP_TRY(hipMemcpyAsync(p->kr, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (info) *info = cmg_solve_info{0, 0.0, 0.0};
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_fill(n, 0.0, x, s));        // x = 0
+    HIP_TRY(cmg::launch_copy(n, b, p->kr, s));      // r = b
+  }
   double bb;
   TRY(dot(p, b, b, n, s, &bb));
   const double nb = std::sqrt(bb);
-  if (info) *info = cmg_solve_info{0, 0.0, 0.0};
+  if (!std::isfinite(nb)) return fail(CMG_EINVAL, "right-hand side is not finite");
   if (nb == 0.0) return CMG_OK;
-  TRY(cmg_vcycle(p, p->kr, p->kz, s));
-  HIP_TRY(hipMemcpyAsync(p->kp, p->kz, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  TRY(vcycle_current(p, p->kr, p->kz, s));
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_copy(n, p->kz, p->kp, s));  // p = z
+  }
   double rz;
   TRY(dot(p, p->kr, p->kz, n, s, &rz));
-  double rel = 1.0;
   for (int it = 1; it <= maxit; ++it) {
-    TRY(scatter(p, L, p->kp, D.x, s));
-    {
-      KTimer t(p, kApply, L, s);
-      HIP_TRY(cmg::launch_apply<double>(d, k, D.kl, D.x, nullptr, D.r, s));
-    }
-    TRY(gather(p, L, D.r, p->kq, s));
+    TRY(op_apply<double>(p, L, p->kp, p->kq, s));  // q = A p in FP64
     double pq;
     TRY(dot(p, p->kp, p->kq, n, s, &pq));
     if (!(pq > 0.0) || !std::isfinite(pq)) return fail(CMG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
@@ -502,14 +664,14 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
     }
     double rr;
     TRY(dot(p, p->kr, p->kr, n, s, &rr));
-    rel = std::sqrt(rr) / nb;
+    const double rel = std::sqrt(rr) / nb;
     if (info) {
       info->iterations = it;
       info->rel_residual = rel;
       info->n_frac = rel > 0.0 ? it * std::log10(rtol) / std::log10(rel) : it;
     }
     if (rel <= rtol) return CMG_OK;
-    TRY(cmg_vcycle(p, p->kr, p->kz, s));
+    TRY(vcycle_current(p, p->kr, p->kz, s));
     double rz_new;
     TRY(dot(p, p->kr, p->kz, n, s, &rz_new));
     {
@@ -555,7 +717,8 @@ cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host) {
 }
 
 cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed) {
-  TRY(check_level(p, level, false));
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (level < 0 || level >= p->H.cfg.n_levels) return fail(CMG_EINVAL, "level out of range");
   const cmg::HostLevel& h = p->H.levels[level];
   std::vector<int64_t> counts;
   const void* src = nullptr;

@@ -66,3 +66,8 @@ hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, doubl
 hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y += a x
 hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y = x + a y
 }  // namespace cmg
+
+namespace cmg {
+hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s);                    // y = v
+hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t s);             // y = x
+}  // namespace cmg

@@ -625,20 +625,24 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
   return hipGetLastError();
 }
 
-template hipError_t launch_apply<double>(int, int, const KLevel&, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_interior_step<double>(int, int, const KLevel&, const int32_t*, int, double*,
-                                                 const double*, hipStream_t);
-template hipError_t launch_cut_solve<double>(int, int, const KLevel&, const CutGroupDev&, const double*,
-                                             const double*, double*, hipStream_t);
-template hipError_t launch_cut_update<double>(const CutGroupDev&, const double*, double*, hipStream_t);
-template hipError_t launch_prolong_add<double>(int, int, const KLevel&, const KLevel&, const double*, double*,
-                                               hipStream_t);
-template hipError_t launch_restrict<double>(int, int, const KLevel&, const KLevel&, const double*, double*,
-                                            hipStream_t);
-template hipError_t launch_coarse<double>(const double*, const int32_t*, int, const double*, double*, hipStream_t);
-template hipError_t launch_zero_active<double>(const int32_t*, int64_t, double*, hipStream_t);
+#define CMG_INSTANTIATE(T)                                                                                   \
+  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, hipStream_t);                \
+  template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
+                                              hipStream_t);                                                        \
+  template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
+                                          hipStream_t);                                                            \
+  template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, hipStream_t);                         \
+  template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t);    \
+  template hipError_t launch_restrict<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t);       \
+  template hipError_t launch_coarse<T>(const T*, const int32_t*, int, const T*, T*, hipStream_t);                  \
+  template hipError_t launch_zero_active<T>(const int32_t*, int64_t, T*, hipStream_t);
+
+CMG_INSTANTIATE(double)
+CMG_INSTANTIATE(float)
 template hipError_t launch_scatter<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_gather<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
+template hipError_t launch_scatter<double, float>(const int32_t*, int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_gather<float, double>(const int32_t*, int64_t, const float*, double*, hipStream_t);
 
 }  // namespace cmg
 
@@ -689,6 +693,35 @@ hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStrea
 hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(dev::k_xpay, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace cmg
+
+namespace cmg {
+namespace dev {
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double v, double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+}  // namespace dev
+
+hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, v, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y);
   return hipGetLastError();
 }
 

@@ -34,14 +34,14 @@ class LevelSet(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("n_levels", ctypes.c_int), ("coarse_cells", ctypes.c_int),
                 ("gamma_D", ctypes.c_double), ("gamma_g", ctypes.c_double), ("ghost_exp_mode", ctypes.c_int),
-                ("n_c", ctypes.c_int), ("quad_n", ctypes.c_int)]
+                ("n_c", ctypes.c_int), ("quad_n", ctypes.c_int), ("precond_fp32", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("n_frac", ctypes.c_double)]
 
 
-EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
+EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured",
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error"]
 
@@ -62,6 +62,7 @@ def load_library():
         "cmg_setup": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), ctypes.POINTER(P)],
         "cmg_setup_host": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), ctypes.POINTER(P)],
         "cmg_ndofs": [P, I, ctypes.POINTER(ctypes.c_int64)],
+        "cmg_set_precision": [P, I],
         "cmg_apply": [P, I, V, V, V],
         "cmg_colour_step": [P, I, I, I, V, V, V],
         "cmg_smooth": [P, I, I, V, V, V],
@@ -111,7 +112,7 @@ def _stream():
 class Problem:
     """One CutFEM multigrid hierarchy owned by the library."""
 
-    def __init__(self, workload, device: bool = True, quad_n: int = 14):
+    def __init__(self, workload, device: bool = True, quad_n: int = 14, fp32: bool = False):
         lib = load_library()
         d = workload.dim
         self.workload = workload
@@ -120,7 +121,7 @@ class Problem:
         self._semi = (ctypes.c_double * (len(workload.semi) * d))(*[v for s in workload.semi for v in s])
         ls = LevelSet(d, len(workload.centers), self._centers, self._semi, workload.lo, workload.hi)
         prm = Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
-                     workload.ghost_exp_mode, workload.n_c, quad_n)
+                     workload.ghost_exp_mode, workload.n_c, quad_n, int(bool(fp32)))
         h = ctypes.c_void_p()
         fn = lib.cmg_setup if device else lib.cmg_setup_host
         _check(fn(ctypes.byref(ls), ctypes.byref(prm), ctypes.byref(h)))
@@ -137,6 +138,10 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def set_precision(self, fp32: bool):
+        """Run the multigrid kernels in FP32 (True) or FP64 (False); CG stays FP64."""
+        _check(_lib.cmg_set_precision(self._h, int(bool(fp32))))
 
     def _lvl(self, level):
         return self.n_levels - 1 if level is None or level < 0 else level
