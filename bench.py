@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--kernel", default="cut_solve", choices=["cut_solve", "interior_step", "apply"],
                     help="kernel kind whose roofline is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--fp32", action="store_true", help="FP32 multigrid preconditioner inside FP64 CG")
     return ap.parse_args()
 
 
@@ -173,7 +176,7 @@ def main():
         w = w.with_levels(args.levels)
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    P = Problem(w)
+    P = Problem(w, fp32=args.fp32)
     t_setup = time.perf_counter() - t0
     n = P.ndofs()
     print(f"[bench] {w.name}: {n} DoFs, setup {t_setup:.1f}s", file=sys.stderr, flush=True)
@@ -238,7 +241,17 @@ def main():
         "vcycle_dofs_per_s": n / t_v,
         "setup_s": t_setup,
     }
+    if args.fp32:
+        out["dtype"] = "f32 multigrid in f64 CG"
+        out["config"]["precision"] = "fp32 preconditioner, fp64 CG"
     P.close()
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes_each_way"] = src.numel() * 8
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

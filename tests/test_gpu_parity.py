@@ -124,3 +124,87 @@ def test_pcg_solve(case):
     assert abs(info["iterations"] - it) <= 1
     assert info["rel_residual"] <= 1e-8
     assert _rel(x.cpu().numpy(), xr) < 1e-8
+
+
+# ---- mixed precision: FP32 multigrid inside FP64 CG --------------------------
+# FP32 results are compared with the oracle run in float32 (same definition,
+# different summation order).  The tolerance is tied to the size of the FP32
+# effect itself: 10x the oracle's own float32-vs-float64 deviation (+1e-6).
+
+_H32 = {}
+
+
+@pytest.fixture
+def fp32_case(case):
+    """The case with the library switched to the FP32 multigrid for one test."""
+    from oracle.multigrid import Hierarchy
+
+    w, P, levels, mats, prols, H = case
+    if w.name not in _H32:
+        _H32[w.name] = Hierarchy(levels, mats, prols, n_c=w.n_c, dtype=np.float32)
+    P.set_precision(True)
+    try:
+        yield w, P, levels, mats, prols, H, _H32[w.name]
+    finally:
+        P.set_precision(False)
+
+
+def _tol32(ref32, ref64):
+    return 10.0 * _rel(ref32, ref64) + 1e-6
+
+
+def test_fp32_apply_and_transfers(fp32_case):
+    w, P, levels, mats, prols, H, H32 = fp32_case
+    l = len(levels) - 1
+    x = W.random_vector(levels[l].n_dofs, seed=90)
+    y64 = mats[l] @ x
+    y32 = (H32.A[l] @ x.astype(np.float32)).astype(np.float64)
+    assert _rel(P.apply(l, _cuda(x)).cpu().numpy(), y32) < _tol32(y32, y64)
+    xc = W.random_vector(levels[l - 1].n_dofs, seed=91)
+    p64 = prols[l - 1] @ xc
+    p32 = (H32.P[l] @ xc.astype(np.float32)).astype(np.float64)
+    assert _rel(P.prolongate(l, _cuda(xc)).cpu().numpy(), p32) < _tol32(p32, p64)
+
+
+def test_fp32_smoother(fp32_case):
+    w, P, levels, mats, prols, H, H32 = fp32_case
+    l = len(levels) - 1
+    n = levels[l].n_dofs
+    b = W.random_vector(n, seed=92)
+    x0 = W.random_vector(n, seed=93)
+    x64 = x0.copy()
+    H.smooth(l, x64, b)
+    x32 = x0.astype(np.float32)
+    H32.smooth(l, x32, b.astype(np.float32))
+    xg = _cuda(x0)
+    P.smooth(l, False, xg, _cuda(b))
+    x32 = x32.astype(np.float64)
+    assert _rel(xg.cpu().numpy(), x32) < _tol32(x32, x64)
+
+
+def test_fp32_vcycle(fp32_case):
+    w, P, levels, mats, prols, H, H32 = fp32_case
+    r = W.random_vector(levels[-1].n_dofs, seed=94)
+    z64 = H.vcycle(r)
+    z32 = H32.vcycle(r).astype(np.float64)
+    zg = P.vcycle(_cuda(r)).cpu().numpy()
+    print(f"  fp32 V-cycle: oracle32 vs 64 {_rel(z32, z64):.2e}, gpu32 vs oracle32 {_rel(zg, z32):.2e}")
+    assert _rel(zg, z32) < _tol32(z32, z64)
+
+
+def test_fp32_pcg(fp32_case):
+    from oracle import problem as OP
+    from oracle.multigrid import pcg
+
+    w, P, levels, mats, prols, H, H32 = fp32_case
+    b = P.rhs_manufactured()
+    x, info = P.solve(_cuda(b), rtol=1e-8, maxit=300)
+    bo = OP.rhs(w, levels[-1])
+    x64, it64, _ = pcg(mats[-1], bo, H.vcycle, rtol=1e-8, maxit=300)
+    _, it32, _ = pcg(mats[-1], bo, H32.vcycle, rtol=1e-8, maxit=300)
+    err = _rel(x.cpu().numpy(), x64)
+    print(f"  fp32-preconditioned CG: {info['iterations']} its (oracle fp32 {it32}, fp64 {it64}), "
+          f"rel residual {info['rel_residual']:.2e}, error vs FP64 oracle solution {err:.2e}")
+    assert abs(info["iterations"] - it32) <= 1
+    assert info["rel_residual"] <= 1e-8
+    assert err < 1e-6
