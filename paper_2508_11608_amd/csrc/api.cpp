@@ -190,9 +190,11 @@ cmg_status upload_all(cmg_problem* P) {
       G.n_patch = static_cast<int>(g.vertex.size());
       G.n_nodes = static_cast<int64_t>(g.nodes.size());
       if (G.n_patch > 0) {
-        int32_t *off, *nodes;
+        int32_t *off, *nodes, *vert;
         int64_t* ioff;
         double* inv;
+        TRY(upload(own, g.vertex, &vert));
+        G.vertex = vert;
         TRY(upload(own, g.off, &off));
         TRY(upload(own, g.inv_off, &ioff));
         TRY(upload(own, g.nodes, &nodes));

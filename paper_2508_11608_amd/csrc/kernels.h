@@ -29,6 +29,7 @@ struct CutGroupDev {
   const int32_t* off;        // node offsets, n_patch + 1
   const int64_t* inv_off;    // inverse offsets, n_patch + 1
   const int32_t* nodes;      // lattice nodes of the internal DoFs
+  const int32_t* vertex;     // vertex index of every patch
   const void* inv;           // symmetric dense inverses, scalar type of the path
   template <typename T>
   __host__ __device__ const T* inv_t() const { return static_cast<const T*>(inv); }

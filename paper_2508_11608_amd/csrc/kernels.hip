@@ -27,6 +27,7 @@
 //     state at the start of the step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -202,15 +203,16 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   __shared__ double tab[S::T_SIZE];
   load_tables<D, K>(L.tables, tab, S::T_SIZE);
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= L.n_dofs) return;
-  const int32_t node = L.dof_node[i];
-  int I[3];
-  int r = node;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L.n_dofs;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t node = L.dof_node[i];
+    int I[3];
+    int r = node;
 #pragma unroll
-  for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
-  const T ax = row_apply<D, K, T>(L, x, tab, I);
-  y[node] = b ? b[node] - ax : ax;
+    for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
+    const T ax = row_apply<D, K, T>(L, x, tab, I);
+    y[node] = b ? b[node] - ax : ax;
+  }
 }
 
 // Fused colour step over interior patches.
@@ -225,8 +227,11 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   __shared__ T rb[PPB][NP];
   load_tables<D, K>(L.tables, tab, S::T_SIZE);
   const int p = threadIdx.x / NP, i = threadIdx.x % NP;
-  const int gp0 = blockIdx.x * PPB;
   const int NV = L.N + 1;
+  const int ngroups = (nv + PPB - 1) / PPB;
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  const int gp0 = grp * PPB;
+  __syncthreads();  // previous group finished with the LDS buffers
   // stage the closures of all patches of this block
   for (int e = threadIdx.x; e < PPB * NC; e += blockDim.x) {
     const int pp = e / NC, q = e % NC;
@@ -331,40 +336,273 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
     dst = t;
   }
   if (active) x[node] += src[p * NP + i];
+  }
 }
 
-// Cut patches, phase 1: residual on internal nodes and dense local solve.
+// Cut patches, phase 1: residual on the internal nodes and dense local solve,
+// one block per patch.  The patch closure and, on every side that carries a
+// ghost face, the node slab of the neighbouring cell layer are staged in LDS
+// (an extended (4k+1)^d box with the closure at [k, 3k]^d).  The jumps
+// J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost face touching the
+// patch are computed once per face; each internal node then needs only its
+// cell rows (uncut stiffness or cut-cell matrix) and k (k+1)^{d-1} terms per
+// incident ghost face.  The local solve is a GEMV with the symmetric inverse.
+template <int D, int K>
+struct CutShape {
+  static constexpr int E1 = 4 * K + 1;                    // extended box, nodes per direction
+  static constexpr int NE = Pow<E1, D>::v;
+  static constexpr int NF = D * 3 * (1 << (D - 1));       // faces touching a 2^d patch
+  static constexpr int NT = Pow<K + 1, D - 1>::v;         // nodes of a cell face
+  static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;
+};
+
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_cut_solve(KLevel L, CutGroupDev G, const T* __restrict__ x,
-                                                   const T* __restrict__ b, T* __restrict__ dbuf) {
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
+                                                                        const T* __restrict__ x,
+                                                                        const T* __restrict__ b,
+                                                                        T* __restrict__ dbuf) {
   using S = Shape<D, K>;
-  constexpr int NP = S::NP, PPB = S::PPB;
-  __shared__ double tab[S::T_SIZE];
-  __shared__ T rs[PPB][NP];
-  load_tables<D, K>(L.tables, tab, S::T_SIZE);
-  __syncthreads();
-  const int p = threadIdx.x / NP, i = threadIdx.x % NP;
-  const int gp = blockIdx.x * PPB + p;
-  const bool inpatch = p < PPB && gp < G.n_patch;
-  int off = 0, nj = 0;
-  if (inpatch) {
-    off = G.off[gp];
-    nj = G.off[gp + 1] - off;
-  }
-  if (inpatch && i < nj) {
-    const int32_t node = G.nodes[off + i];
-    int I[3];
-    int r = node;
+  using C = CutShape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NE = C::NE, NF = C::NF, NT = C::NT;
+  constexpr int NCELL = 1 << D;
+  __shared__ double tab[S::T_D1 + K * N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
+  __shared__ T xs[NE];
+  __shared__ T Jf[NF][K][NT];
+  __shared__ T rs[S::NP];
+  __shared__ uint8_t cfl[NCELL], cgh[NCELL];
+  __shared__ int32_t ccut[NCELL];
+  __shared__ int needlo[3], needhi[3];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int gp = blockIdx.x;
+  const double* mh = tab;
+  const double* d0 = tab + (S::T_D0 - S::T_MHAT);
+  const double* d1 = tab + (S::T_D1 - S::T_MHAT);
+  const double* gc = tab + (S::T_GC - S::T_MHAT);
+  for (int i = tid; i < S::T_D1 + K * N1 + K - S::T_MHAT; i += nth) tab[i] = L.tables[S::T_MHAT + i];
+  const int off = G.off[gp];
+  const int nj = G.off[gp + 1] - off;
+  const int NV = L.N + 1;
+  int V[3] = {0, 0, 0};
+  {
+    int vr = G.vertex[gp];
 #pragma unroll
-    for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
-    rs[p][i] = b[node] - row_apply<D, K, T>(L, x, tab, I);
+    for (int a = 0; a < D; ++a) { V[a] = vr % NV; vr /= NV; }
+  }
+  if (tid < NCELL) {
+    int c[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      c[a] = V[a] - 1 + ((tid >> a) & 1);
+      in = in && c[a] >= 0 && c[a] < L.N;
+    }
+    uint8_t f = 0, g = 0;
+    int32_t cid = -1;
+    if (in) {
+      const int64_t cl = cell_lin(D, L.N, c);
+      f = L.flags[cl];
+      g = (f & 1) ? L.ghost[cl] : 0;
+      cid = L.cut_id[cl];
+    }
+    cfl[tid] = f;
+    cgh[tid] = g;
+    ccut[tid] = cid;
+  }
+  if (tid < 3) { needlo[tid] = 0; needhi[tid] = 0; }
+  __syncthreads();
+  if (tid < NCELL) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int o = (tid >> a) & 1;
+      if (o == 0 && (cgh[tid] & (1 << (2 * a)))) atomicOr(&needlo[a], 1);
+      if (o == 1 && (cgh[tid] & (1 << (2 * a + 1)))) atomicOr(&needhi[a], 1);
+    }
   }
   __syncthreads();
-  if (inpatch && i < nj) {
-    const T* inv = G.inv_t<T>() + G.inv_off[gp];
-    T s = 0;
-    for (int j = 0; j < nj; ++j) s += inv[(int64_t)j * nj + i] * rs[p][j];
-    dbuf[off + i] = s;
+  // stage x: closure [K, 3K]^D, plus the slabs [0, K-1] / [3K+1, 4K] along a
+  // direction when a ghost face lies on that side of the patch
+  for (int e = tid; e < NE; e += nth) {
+    int q[3];
+    int r = e;
+    int outside = 0, dir_out = -1, lowside = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      q[a] = r % E1;
+      r /= E1;
+      if (q[a] < K || q[a] > 3 * K) { ++outside; dir_out = a; lowside = q[a] < K; }
+    }
+    bool load = outside == 0 || (outside == 1 && (lowside ? needlo[dir_out] : needhi[dir_out]));
+    T v = 0;
+    if (load) {
+      int I[3];
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        I[a] = K * (V[a] - 2) + q[a];
+        in = in && I[a] >= 0 && I[a] < L.nn;
+      }
+      if (in) v = x[lat(D, L.nn, I)];
+    }
+    xs[e] = v;
+  }
+  __syncthreads();
+  // jumps of every ghost face: face (dir, plane 0..2, tangential cell t)
+  for (int task = tid; task < NF * K * NT; task += nth) {
+    const int bt = task % NT;
+    const int m = (task / NT) % K;
+    const int f = task / (NT * K);
+    const int dir = f / (3 << (D - 1));
+    const int plane = (f >> (D - 1)) % 3;
+    const int t = f & ((1 << (D - 1)) - 1);
+    // the patch cell that owns the ghost bit of this face
+    int o = 0, tb = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (a == dir) continue;
+      o |= ((t >> tb) & 1) << a;
+      ++tb;
+    }
+    bool ghost;
+    if (plane == 0) ghost = cgh[o] & (1 << (2 * dir));                   // lower face of layer 0
+    else if (plane == 1) ghost = cgh[o] & (1 << (2 * dir + 1));          // between layers 0 and 1
+    else ghost = cgh[o | (1 << dir)] & (1 << (2 * dir + 1));             // upper face of layer 1
+    if (!ghost) continue;
+    int q[3];
+    {
+      int rb = bt, tb2 = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (a == dir) continue;
+        q[a] = K + K * ((t >> tb2) & 1) + rb % N1;
+        rb /= N1;
+        ++tb2;
+      }
+    }
+    T acc = 0;
+#pragma unroll
+    for (int bd = 0; bd <= K; ++bd) {
+      q[dir] = K * plane + bd;
+      int el = q[0] + E1 * q[1];
+      if (D == 3) el += E1 * E1 * q[2];
+      const T xl = xs[el];
+      q[dir] += K;
+      int eu = q[0] + E1 * q[1];
+      if (D == 3) eu += E1 * E1 * q[2];
+      acc += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * xs[eu];
+    }
+    Jf[f][m][bt] = acc;
+  }
+  __syncthreads();
+  // residual on the internal nodes
+  for (int i = tid; i < nj; i += nth) {
+    const int32_t node = G.nodes[off + i];
+    int pi[3];
+    {
+      int r = node;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        pi[a] = r % L.nn - K * (V[a] - 1);  // 1 .. 2K-1
+        r /= L.nn;
+      }
+    }
+    int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (pi[a] == K) { cc[a][0] = 0; lc[a][0] = K; cc[a][1] = 1; lc[a][1] = 0; nc[a] = 2; }
+      else if (pi[a] < K) { cc[a][0] = 0; lc[a][0] = pi[a]; }
+      else { cc[a][0] = 1; lc[a][0] = pi[a] - K; }
+    }
+    T ax = 0;
+    const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
+    for (int comb = 0; comb < ncomb; ++comb) {
+      int o = 0, il[3];
+      int r = comb;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int sel = r % nc[a];
+        r /= nc[a];
+        o |= cc[a][sel] << a;
+        il[a] = lc[a][sel];
+      }
+      const uint8_t f = cfl[o];
+      if (!(f & 1)) continue;
+      int iloc = il[0] + N1 * il[1];
+      if (D == 3) iloc += N1 * N1 * il[2];
+      T sacc = 0;
+      if (f & 2) {
+        const T* row = L.cut_mats_t<T>() + ((int64_t)ccut[o] * NL + iloc) * NL;
+#pragma unroll
+        for (int bq = 0; bq < NL; ++bq) {
+          int e = 0, st = 1, rb = bq;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            e += (K + K * ((o >> a) & 1) + rb % N1) * st;
+            rb /= N1;
+            st *= E1;
+          }
+          sacc += row[bq] * xs[e];
+        }
+      } else {
+        const double* row = L.tables + S::T_KCELL + iloc * NL;
+#pragma unroll
+        for (int bq = 0; bq < NL; ++bq) {
+          int e = 0, st = 1, rb = bq;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            e += (K + K * ((o >> a) & 1) + rb % N1) * st;
+            rb /= N1;
+            st *= E1;
+          }
+          sacc += (T)row[bq] * xs[e];
+        }
+      }
+      ax += sacc;
+      const uint8_t g = cgh[o];
+      if (g) {
+#pragma unroll
+        for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            if (!(g & (1 << (2 * dir + side)))) continue;
+            const int plane = ((o >> dir) & 1) + side;
+            int t = 0, tb = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              if (a == dir) continue;
+              t |= ((o >> a) & 1) << tb;
+              ++tb;
+            }
+            const int f = (dir * 3 + plane) * (1 << (D - 1)) + t;
+            T gs = 0;
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+              T js = 0;
+              for (int bt = 0; bt < NT; ++bt) {
+                double w = 1.0;
+                int rb = bt;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                  if (a == dir) continue;
+                  w *= mh[il[a] * N1 + rb % N1];
+                  rb /= N1;
+                }
+                js += (T)w * Jf[f][m][bt];
+              }
+              const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
+              gs += (T)sg * js;
+            }
+            ax += gs;
+          }
+      }
+    }
+    rs[i] = b[node] - ax;
+  }
+  __syncthreads();
+  const T* inv = G.inv_t<T>() + G.inv_off[gp];
+  for (int i = tid; i < nj; i += nth) {
+    T acc = 0;
+    for (int j = 0; j < nj; ++j) acc += inv[(int64_t)j * nj + i] * rs[j];
+    dbuf[off + i] = acc;
   }
 }
 
@@ -518,6 +756,10 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
 
+// Grid cap for the grid-stride kernels that stage level tables in LDS: 256
+// CUs x 8 resident 256-thread blocks, so every block loads the tables once.
+constexpr unsigned kMaxResidentBlocks = 2048;
+
 template <typename F>
 hipError_t dispatch(int d, int k, F&& f) {
   if (d == 2 && k == 1) return f(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
@@ -544,7 +786,8 @@ template <typename T>
 hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, hipStream_t s) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(blocks(L.n_dofs)), dim3(256), 0, s, L, x, b, y);
+    const unsigned nb = std::min<unsigned>(blocks(L.n_dofs), kMaxResidentBlocks);
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, x, b, y);
     return hipGetLastError();
   });
 }
@@ -555,8 +798,9 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
   if (nv == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
-    hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(blocks(nv, PPB)), dim3(256), 0, s, L,
-                       verts, nv, x, b);
+    const unsigned nb = std::min<unsigned>(blocks(nv, PPB), kMaxResidentBlocks);
+    hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, verts, nv, x,
+                       b);
     return hipGetLastError();
   });
 }
@@ -566,9 +810,8 @@ hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G,
                             hipStream_t s) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
-    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(blocks(G.n_patch, PPB)), dim3(256), 0, s, L,
-                       G, x, b, dbuf);
+    constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, dbuf);
     return hipGetLastError();
   });
 }
