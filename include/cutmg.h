@@ -151,6 +151,12 @@ cmg_status cmg_timing_read(cmg_problem* p, int kind, int level, int64_t* launche
  * HOST array of cmg_ndofs(finest) doubles. */
 cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host);
 
+/* Load vector of f(x) = sum_q amp[q] cos(pi kappa_q . x + phase[q]) with
+ * homogeneous Dirichlet data (g = 0), finest level, HOST output of
+ * cmg_ndofs(finest) doubles; kappa holds n_modes * dim integers. */
+cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, const double* amp,
+                           const double* phase, double* b_host);
+
 /* Host-side description of a level for tests and diagnostics.
  * what = 0: counts, 8 int64 into buf: n_dofs, n_cells_active, n_cut_cells,
  *           n_interior_patches, n_cut_patches, sum of N_j^2 over cut patches,

@@ -41,3 +41,18 @@ def build(w, with_hierarchy: bool = True, dtype=np.float64, n_levels: int = None
 def rhs(w, level):
     u, f, g = manufactured(w.dim)
     return load_vector(level, shapes_of(w), form_params(w), f, g)
+
+
+def fourier_f(kappa, amp, theta):
+    """f(x) = sum_q a_q cos(pi kappa_q . x + theta_q)."""
+    kappa = np.asarray(kappa, dtype=np.float64)
+
+    def f(x):
+        return np.cos(math.pi * x @ kappa.T + theta) @ amp
+
+    return f
+
+
+def rhs_fourier(w, level, kappa, amp, theta):
+    """Load vector of the Fourier data with homogeneous Dirichlet data."""
+    return load_vector(level, shapes_of(w), form_params(w), fourier_f(kappa, amp, theta), None)

@@ -718,6 +718,16 @@ cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host) {
   return CMG_OK;
 }
 
+cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, const double* amp,
+                           const double* phase, double* b_host) {
+  if (!p || !b_host || n_modes < 0 || (n_modes > 0 && (!kappa || !amp || !phase)))
+    return fail(CMG_EINVAL, "bad Fourier right-hand side");
+  std::vector<double> b;
+  cmg::fourier_rhs(p->H, n_modes, kappa, amp, phase, b);
+  std::memcpy(b_host, b.data(), b.size() * sizeof(double));
+  return CMG_OK;
+}
+
 cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed) {
   if (!p) return fail(CMG_EINVAL, "null problem");
   if (level < 0 || level >= p->H.cfg.n_levels) return fail(CMG_EINVAL, "level out of range");

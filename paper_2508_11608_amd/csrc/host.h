@@ -9,6 +9,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -120,9 +121,15 @@ struct Hierarchy {
 // prefixed by its status name ("EGEOM:", "ENOTSPD:", "EINVAL:").
 std::string build_hierarchy(const Config& cfg, Hierarchy& H);
 
-// Load vector of the manufactured problem u = prod sin(pi x_j), f = d pi^2 u,
-// Dirichlet data g = u through the symmetric Nitsche terms, canonical order.
+// Load vector b_i = (f, phi_i)_Omega + (g, (gamma_D/h) phi_i - d_n phi_i)_Gamma on the
+// finest level, canonical order; g may be empty (homogeneous Dirichlet data).
+void load_vector(const Hierarchy& H, const std::function<double(const double*)>& f,
+                 const std::function<double(const double*)>& g, std::vector<double>& b);
+// Manufactured problem u = prod sin(pi x_j), f = d pi^2 u, Dirichlet data g = u.
 void manufactured_rhs(const Hierarchy& H, std::vector<double>& b);
+// f = sum_q amp_q cos(pi kappa_q . x + phase_q), g = 0 (kappa: n_modes x dim ints).
+void fourier_rhs(const Hierarchy& H, int n_modes, const int* kappa, const double* amp, const double* phase,
+                 std::vector<double>& b);
 
 // Uncut-cell stiffness, element matrix of a cut cell, ghost-face matrix.
 void uncut_cell_matrix(const Config& cfg, const Basis1D& B, double h, std::vector<double>& K);

@@ -20,8 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
-#include <unordered_map>
 
 #include "host.h"
 
@@ -681,17 +681,37 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
 }
 
 void manufactured_rhs(const Hierarchy& H, std::vector<double>& b) {
+  const int d = H.cfg.dim;
+  auto u = [d](const double* x) {
+    double v = 1.0;
+    for (int j = 0; j < d; ++j) v *= std::sin(M_PI * x[j]);
+    return v;
+  };
+  load_vector(H, [&](const double* x) { return d * M_PI * M_PI * u(x); }, u, b);
+}
+
+void fourier_rhs(const Hierarchy& H, int n_modes, const int* kappa, const double* amp, const double* phase,
+                 std::vector<double>& b) {
+  const int d = H.cfg.dim;
+  auto f = [&](const double* x) {
+    double v = 0.0;
+    for (int q = 0; q < n_modes; ++q) {
+      double arg = phase[q];
+      for (int j = 0; j < d; ++j) arg += M_PI * kappa[q * d + j] * x[j];
+      v += amp[q] * std::cos(arg);
+    }
+    return v;
+  };
+  load_vector(H, f, nullptr, b);
+}
+
+void load_vector(const Hierarchy& H, const std::function<double(const double*)>& f,
+                 const std::function<double(const double*)>& u, std::vector<double>& b) {
   const Config& cfg = H.cfg;
   const HostLevel& L = H.levels.back();
   const int d = cfg.dim, k = cfg.k, n1 = k + 1, nl = ipow(n1, d);
   LevelGeom geo{d, k, L.N, L.nn};
   const double h = L.h;
-  auto u = [&](const double* x) {
-    double v = 1.0;
-    for (int j = 0; j < d; ++j) v *= std::sin(M_PI * x[j]);
-    return v;
-  };
-  auto f = [&](const double* x) { return d * M_PI * M_PI * u(x); };
   b.assign(L.n_dofs, 0.0);
   const int ng = k + 3;
   double gx[16], gw[16];
@@ -738,7 +758,7 @@ void manufactured_rhs(const Hierarchy& H, std::vector<double>& b) {
             for (int a = 0; a < nl; ++a) loc[a] += fv * phi(xi, a, -1);
           }
         }
-        if (col.surf) {
+        if (col.surf && u) {
           x[col.e] = col.ts;
           for (int j = 0; j < d; ++j) xi[j] = (x[j] - lo[j]) / h;
           const double gv = u(x) * col.sw;

@@ -42,7 +42,7 @@ class SolveInfo(ctypes.Structure):
 
 
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
-            "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured",
+            "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured", "cmg_rhs_fourier",
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error"]
 
 _lib = None
@@ -71,6 +71,7 @@ def load_library():
         "cmg_vcycle": [P, V, V, V],
         "cmg_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_rhs_manufactured": [P, ctypes.POINTER(ctypes.c_double)],
+        "cmg_rhs_fourier": [P, I, V, V, V, ctypes.POINTER(ctypes.c_double)],
         "cmg_export": [P, I, I, V, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "cmg_timing": [P, ctypes.c_uint],
         "cmg_timing_read": [P, I, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
@@ -214,6 +215,17 @@ class Problem:
     def rhs_manufactured(self) -> np.ndarray:
         b = np.empty(self.ndofs(None), dtype=np.float64)
         _check(_lib.cmg_rhs_manufactured(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return b
+
+    def rhs_fourier(self, kappa, amp, phase) -> np.ndarray:
+        """Load vector of f = sum_q amp_q cos(pi kappa_q . x + phase_q), g = 0 (host array)."""
+        kappa = np.ascontiguousarray(kappa, dtype=np.int32)
+        amp = np.ascontiguousarray(amp, dtype=np.float64)
+        phase = np.ascontiguousarray(phase, dtype=np.float64)
+        b = np.empty(self.ndofs(None), dtype=np.float64)
+        _check(_lib.cmg_rhs_fourier(self._h, len(amp), kappa.ctypes.data_as(ctypes.c_void_p),
+                                    amp.ctypes.data_as(ctypes.c_void_p), phase.ctypes.data_as(ctypes.c_void_p),
+                                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return b
 
     def export(self, level, what: int, dtype) -> np.ndarray:

@@ -121,3 +121,11 @@ def test_manufactured_rhs(pair):
     b = P.rhs_manufactured()
     ref = OP.rhs(w, levels[-1])
     assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fourier_rhs(pair):
+    w, P, levels, _, _ = pair
+    kappa, amp, theta = W.fourier_modes(w.dim, seed=1000)
+    b = P.rhs_fourier(kappa, amp, theta)
+    ref = OP.rhs_fourier(w, levels[-1], kappa, amp, theta)
+    assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -77,3 +77,20 @@ def random_vector(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     rng = np.random.default_rng(seed)
     v = rng.standard_normal((nrhs, n))
     return v[0] if nrhs == 1 else v
+
+
+def fourier_modes(dim: int, seed: int, n_modes: int = 16):
+    """Seeded random smooth Fourier data for f = sum_q a_q cos(pi kappa_q . x + theta_q):
+    kappa_q drawn from {0..4}^d without the zero vector, a_q ~ N(0,1) / (1 + |kappa_q|^2),
+    theta_q ~ U[0, 2 pi).  Returns (kappa (n_modes, dim) int32, a, theta)."""
+    rng = np.random.default_rng(seed)
+    kappa = np.zeros((n_modes, dim), dtype=np.int32)
+    for q in range(n_modes):
+        while True:
+            kq = rng.integers(0, 5, size=dim)
+            if kq.any():
+                break
+        kappa[q] = kq
+    amp = rng.standard_normal(n_modes) / (1.0 + np.sum(kappa.astype(np.float64) ** 2, axis=1))
+    theta = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    return kappa, amp, theta
