@@ -8,7 +8,10 @@ Inputs are synthetic (manufactured right-hand side) and resident in HBM before
 the timed region starts.
 
 value = V-cycle DoFs/s = active DoFs x V-cycles applied / wall time of the timed
-solves (the CG work around the V-cycles is included).
+solves (the CG work around the V-cycles is included).  Both precisions of the
+multigrid are measured on the same hierarchy: the FP64 figures head the line
+and the FP32-preconditioned ones (FP32 V-cycle inside FP64 CG, same 1e-8
+tolerance) sit under "fp32_precond" (--fp32 swaps the two).
 
 roofline: the dominant kernel (default: the cut-patch colour step) is bracketed
 by HIP events on its own stream during the timed region; achieved = algorithmic
@@ -48,8 +51,77 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--fp32", action="store_true", help="FP32 multigrid preconditioner inside FP64 CG")
+    ap.add_argument("--fp32", action="store_true",
+                    help="head the line with the FP32 multigrid preconditioner (FP64 figures go under 'fp64')")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="serving run: N seeded requests with Poisson arrivals instead of the solve benchmark")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--rate", type=float, default=0.8, help="arrival rate as a fraction of the saturation rate")
     return ap.parse_args()
+
+
+def serve(args):
+    """Continuous-batching run: the seeded request stream (unions of 1-4
+    spheres or ellipsoids, d in {2,3}, k in {1,2,3}, N_L in {32,64,128}, random
+    Fourier f, FP32 multigrid in FP64 CG to 1e-8) against the library's server.
+    First all requests at once (saturation throughput), then the same stream
+    with Poisson arrivals at `rate` x that throughput."""
+    import workloads as W
+    from paper_2508_11608_amd import Problem, Server
+
+    reqs = W.serving_stream(args.serve, seed=0, pool=16, max_dofs=20_000_000)
+    sizes = {}
+    for w, _ in reqs:
+        if w.name not in sizes:
+            sizes[w.name] = Problem(w, device=False).ndofs()
+
+    def run(arrivals):
+        srv = Server(96 << 30, args.slots)
+        t0 = time.perf_counter()
+        pending = {}
+        out = []
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                w, f = reqs[i]
+                pending[srv.submit(w, fourier=f, fp32=True)] = (i, w, time.perf_counter() - t0)
+                i += 1
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    k, w, ts = pending.pop(t)
+                    out.append((k, w, ts, time.perf_counter() - t0, r[0]))
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        srv.close()
+        return out, wall
+
+    out, wall = run([0.0] * len(reqs))
+    sat_rate = len(reqs) / wall
+    rng = np.random.default_rng(1)
+    arr = np.cumsum(rng.exponential(1.0 / (args.rate * sat_rate), len(reqs)))
+    arr -= arr[0]
+    out, wall = run(list(arr))
+    lat = np.array([done - ts for _, _, ts, done, _ in out])
+    solve = np.array([r["t_done"] - r["t_solve_start"] for *_, r in out])
+    cold = np.array([not r["cache_hit"] for *_, r in out])
+    ok = all(r["status"] == 0 and r["rel_residual"] <= 1e-8 for *_, r in out)
+    dofs = sum(r["n_dofs"] * r["iterations"] for *_, r in out)
+    return {
+        "metric": METRIC, "value": dofs / wall, "unit": "DoF/s (aggregate, per CG iteration)", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": wall / len(reqs) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 multigrid in f64 CG", "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(reqs)} seeded requests, 16-geometry Zipf(1.1) pool, "
+                               f"unions of 1-4 spheres/ellipsoids, d in (2,3), k in (1,2,3), N_L in (32,64,128) "
+                               f"(background lattice <= 2e7), "
+                               f"Fourier f, rtol 1e-8, {args.slots} slots, Poisson arrivals at {args.rate} x "
+                               f"saturation ({sat_rate:.2f} req/s)"},
+        "latency_ms_p50": float(np.percentile(lat, 50) * 1e3), "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "solve_ms_p50": float(np.percentile(solve, 50) * 1e3), "solve_ms_p99": float(np.percentile(solve, 99) * 1e3),
+        "warm_latency_ms_p50": float(np.percentile(lat[~cold], 50) * 1e3) if (~cold).any() else None,
+        "cold_requests": int(cold.sum()), "all_converged": ok, "saturation_req_per_s": sat_rate,
+    }
 
 
 def kernel_source_hash() -> str:
@@ -57,9 +129,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(P, w, kind: str) -> dict:
+def algorithmic_bytes(P, w, kind: str, s: int = 8) -> dict:
     """Algorithmic HBM bytes of every launch of one kernel kind in one V-cycle,
-    keyed by (level, colour) (or level for 'apply'), FP64 (s = 8 B).
+    keyed by (level, colour) (or level for 'apply'); s = 8 B (FP64 multigrid)
+    or 4 B (FP32 multigrid), indices 4 B.
 
     interior_step, per patch:  s [(2k)^d + 2 (2k-1)^d] + 4
         x over the patch closure (same-coloured closures tile space with period
@@ -70,9 +143,9 @@ def algorithmic_bytes(P, w, kind: str) -> dict:
         closure, and the k^d rows of every cut-cell matrix that belong to
         internal nodes of the patch.
     apply (residual), per DoF: 4 + 3 s, plus s (k+1)^{2d} per cut cell; the
-        CG product A p once per iteration on the finest level: 4 + 2 s per DoF.
+        CG product A p once per iteration on the finest level, always FP64:
+        4 + 2*8 per DoF plus 8 (k+1)^{2d} per cut cell.
     """
-    s = 8
     d, k = w.dim, w.k
     nl = (k + 1) ** d
     out = {}
@@ -81,7 +154,7 @@ def algorithmic_bytes(P, w, kind: str) -> dict:
         if kind == "apply":
             out[l] = c["n_dofs"] * (4 + 3 * s) + c["cut_cells"] * nl * nl * s
             if l == w.n_levels - 1:  # the CG product A p on the finest level (no b)
-                out["cg"] = c["n_dofs"] * (4 + 2 * s) + c["cut_cells"] * nl * nl * s
+                out["cg"] = c["n_dofs"] * (4 + 2 * 8) + c["cut_cells"] * nl * nl * 8
             continue
         N = P.export(l, 2, np.uint8)  # cell flags, x fastest
         Nc = round(len(N) ** (1.0 / d))
@@ -111,8 +184,8 @@ def algorithmic_bytes(P, w, kind: str) -> dict:
     return out
 
 
-def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int) -> dict:
-    per_v = algorithmic_bytes(P, w, kind)
+def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False) -> dict:
+    per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8)
     bytes_per_vcycle = sum(per_v.values())
     if kind != "apply":
         # each colour step runs twice per smoothing step for interior patches
@@ -123,7 +196,7 @@ def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int) -> d
     ms_per_launch = total_ms / max(launches, 1)
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{kind}_{w.name}.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{kind}_{'fp32' if fp32 else 'fp64'}_{w.name}.json")
     if os.path.exists(tfile):
         t = json.load(open(tfile))
         if t.get("kernel_source_sha256_16") == kernel_source_hash():
@@ -160,28 +233,14 @@ def cpu_baseline() -> dict:
                       f"{its // solves} iterations each), set-up excluded, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
-              "not an implementation", file=sys.stderr)
-        sys.exit(2)
+def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
+    """Warm-up, then args.steps timed solves in one precision of the multigrid
+    (CG is FP64 either way), the live roofline of args.kernel, and back-to-back
+    V-cycles timed separately outside the timed region."""
     import torch
 
-    import workloads as W
-    from paper_2508_11608_amd import Problem
-
-    w = W.ball_q2() if args.workload == "ball" else W.disc_q2()
-    if args.levels:
-        w = w.with_levels(args.levels)
-    torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    P = Problem(w, fp32=args.fp32)
-    t_setup = time.perf_counter() - t0
+    P.set_precision(fp32)
     n = P.ndofs()
-    print(f"[bench] {w.name}: {n} DoFs, setup {t_setup:.1f}s", file=sys.stderr, flush=True)
-    b = torch.from_numpy(P.rhs_manufactured()).cuda()
-    x = torch.empty_like(b)
     for _ in range(args.warmup):
         P.solve(b, x, rtol=1e-8)
     torch.cuda.synchronize()
@@ -200,9 +259,9 @@ def main():
     dt = time.perf_counter() - t0
     launches, kms = P.timing_read(args.kernel)
     P.timing([])
-    roof = roofline(P, w, args.kernel, launches, kms, its)
-    print(f"[bench] timed {args.steps} solves: {dt:.3f}s, {its} V-cycles", file=sys.stderr, flush=True)
-    # back-to-back V-cycles only (outside the timed region)
+    roof = roofline(P, w, args.kernel, launches, kms, its, fp32)
+    tag = "fp32" if fp32 else "fp64"
+    print(f"[bench] {tag}: timed {args.steps} solves: {dt:.3f}s, {its} V-cycles", file=sys.stderr, flush=True)
     r = torch.randn(n, dtype=torch.float64, device="cuda")
     z = torch.empty_like(r)
     for _ in range(3):
@@ -216,34 +275,72 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_v = e0.elapsed_time(e1) / 1e3 / nv
+    return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * its / dt,
+            "ms_per_step": dt / args.steps * 1e3, "iterations_per_solve": its / args.steps,
+            "final_rel_residual": rel,
+            "solve_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "solve_latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "vcycle_ms": t_v * 1e3, "vcycle_dofs_per_s": n / t_v, "roofline": roof}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design note, "
+              "not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.serve:
+        torch.cuda.set_device(0)
+        print(json.dumps(serve(args)), flush=True)
+        return
+
+    import workloads as W
+    from paper_2508_11608_amd import Problem
+
+    w = W.ball_q2() if args.workload == "ball" else W.disc_q2()
+    if args.levels:
+        w = w.with_levels(args.levels)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    P = Problem(w)
+    t_setup = time.perf_counter() - t0
+    n = P.ndofs()
+    print(f"[bench] {w.name}: {n} DoFs, setup {t_setup:.1f}s", file=sys.stderr, flush=True)
+    b = torch.from_numpy(P.rhs_manufactured()).cuda()
+    x = torch.empty_like(b)
+    first = [True, False] if args.fp32 else [False, True]
+    res = {fp32: timed_solves(P, w, b, x, args, fp32) for fp32 in first}
+    head = res[first[0]]
+    other = res[first[1]]
     out = {
         "metric": METRIC,
-        "value": n * its / dt,
+        "value": head["value"],
         "unit": "DoF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 multigrid in f64 CG" if args.fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: ball |x|<0.7 in [-1,1]^3, Q2, {w.n_levels} levels to "
                                f"{w.fine_cells}^3 cells, manufactured f, FP64 CG to 1e-8",
-                   "active_dofs": n, "n_c": w.n_c, "precision": "fp64"},
-        "roofline": roof,
-        "cg_iterations_per_solve": its / args.steps,
-        "final_rel_residual": rel,
-        "solve_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
-        "solve_latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
-        "vcycle_ms": t_v * 1e3,
-        "vcycle_dofs_per_s": n / t_v,
+                   "active_dofs": n, "n_c": w.n_c,
+                   "precision": "fp32 preconditioner, fp64 CG" if args.fp32 else "fp64"},
+        "roofline": head["roofline"],
+        "cg_iterations_per_solve": head["iterations_per_solve"],
+        "final_rel_residual": head["final_rel_residual"],
+        "solve_latency_ms_p50": head["solve_latency_ms_p50"],
+        "solve_latency_ms_p99": head["solve_latency_ms_p99"],
+        "vcycle_ms": head["vcycle_ms"],
+        "vcycle_dofs_per_s": head["vcycle_dofs_per_s"],
         "setup_s": t_setup,
+        ("fp64" if args.fp32 else "fp32_precond"): other,
     }
-    if args.fp32:
-        out["dtype"] = "f32 multigrid in f64 CG"
-        out["config"]["precision"] = "fp32 preconditioner, fp64 CG"
     P.close()
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB

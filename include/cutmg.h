@@ -43,7 +43,8 @@ typedef enum {
   CMG_ENOTSPD = -4,    /* Cholesky of a cut-patch or the coarse matrix failed */
   CMG_ENOTCONV = -5,   /* CG reached maxit; x holds the last iterate */
   CMG_EBREAKDOWN = -6, /* CG breakdown: p^T A p <= 0 or not finite */
-  CMG_EHIP = -7        /* a HIP runtime call failed */
+  CMG_EHIP = -7,       /* a HIP runtime call failed */
+  CMG_PENDING = 1      /* cmg_poll: the request has not finished yet */
 } cmg_status;
 
 typedef struct cmg_problem cmg_problem;
@@ -87,6 +88,14 @@ cmg_status cmg_setup(const cmg_levelset* ls, const cmg_params* prm, cmg_problem*
  * hierarchy with cmg_export on machines without a GPU.  Device calls on such a
  * problem return CMG_EINVAL. */
 cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out);
+
+/* Make a problem from cmg_setup_host device-resident on the current HIP device
+ * (no-op for a device problem).  Synchronous. */
+cmg_status cmg_upload(cmg_problem* p);
+
+/* Device memory in bytes that the problem occupies once uploaded (fp32 = 1:
+ * including the FP32 copies of the mixed-precision V-cycle). */
+cmg_status cmg_device_bytes(const cmg_problem* p, int fp32, size_t* bytes);
 
 /* Precision of the multigrid part: fp32 = 0 runs every V-cycle kernel in FP64;
  * fp32 = 1 runs smoother, transfers, level residuals and the coarse solve in FP32
@@ -176,6 +185,46 @@ cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, 
 cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed);
 
 void cmg_destroy(cmg_problem* p);
+
+/* ---- serving: continuous batching of solves on one GPU -------------------
+ * A server owns max_slots worker threads, each with its own HIP stream.
+ * Requests are taken in arrival order; a hierarchy with the same geometry and
+ * parameters stays resident between requests (least-recently-used idle
+ * hierarchies are evicted when a new one needs room), and a new hierarchy is
+ * admitted to the device when its exact footprint (cmg_device_bytes) fits into
+ * hbm_budget_bytes.  Solves of different slots overlap on the device; every
+ * result is independent of what else runs.  Intended for callers that submit
+ * many solves of differing geometries, degrees and depths. */
+typedef struct cmg_server cmg_server;
+
+typedef struct {
+  cmg_levelset levelset;   /* copied at submission */
+  cmg_params params;
+  int n_modes;             /* 0: manufactured right-hand side; else Fourier f (cmg_rhs_fourier), g = 0 */
+  const int* kappa;        /* n_modes * dim */
+  const double* amp;
+  const double* phase;
+  double rtol;
+  int maxit;
+} cmg_request;
+
+typedef struct {
+  int status;              /* cmg_status of the request */
+  int64_t n_dofs;
+  cmg_solve_info info;
+  int cache_hit;           /* 1 when the hierarchy was already resident */
+  double t_submit, t_start, t_admitted, t_solve_start, t_done;  /* seconds since server creation */
+} cmg_result;
+
+cmg_status cmg_server_create(size_t hbm_budget_bytes, int max_slots, cmg_server** out);
+/* Non-blocking; the request is copied. */
+cmg_status cmg_submit(cmg_server* s, const cmg_request* req, uint64_t* ticket);
+/* CMG_PENDING until the request finished; then fills res, copies the solution
+ * (finest level, canonical order) to x_host when given (x_len must equal
+ * res->n_dofs) and forgets the request. */
+cmg_status cmg_poll(cmg_server* s, uint64_t ticket, cmg_result* res, double* x_host, int64_t x_len);
+/* Finishes the queued requests, then releases everything. */
+void cmg_server_destroy(cmg_server* s);
 
 /* Message of the last failing call in this thread ("" if none). */
 const char* cmg_last_error(void);

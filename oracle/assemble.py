@@ -29,7 +29,7 @@ import scipy.sparse as sp
 
 from .basis import eval_basis, eval_tensor_basis, gauss_legendre, local_index_tuples
 from .geometry import Level
-from .quadrature import cut_cell_rule
+from .quadrature import cut_cell_rule_union
 
 
 @dataclass
@@ -39,6 +39,7 @@ class FormParams:
     ghost_exp_mode: int = 0  # 0: h^(2m-1); 1: h^(2m+1)
     quad_n: int = 14        # Gauss points per smooth piece of a cut-cell rule
     quad_beta: float = 0.35  # subdivision threshold of the cut-cell rule
+    union_depth: int = 4     # bisection depth of cells crossed by several surfaces
 
 
 def tensor_gauss_ref(d: int, n: int):
@@ -60,11 +61,12 @@ def uncut_cell_matrix(k: int, d: int, h: float) -> np.ndarray:
     return E
 
 
-def cut_cell_matrix(level: Level, shape, cell, fp: FormParams) -> np.ndarray:
-    """Volume, Nitsche and penalty terms of one cut cell."""
+def cut_cell_matrix(level: Level, shapes, cell, fp: FormParams) -> np.ndarray:
+    """Volume, Nitsche and penalty terms of one cut cell (shapes: list, Omega is their union)."""
     k, d, h = level.k, level.dim, level.h
     lo = level.cell_lo(cell)
-    vx, vw, sx, sw, sn = cut_cell_rule(shape, lo, lo + h, n=fp.quad_n, n_t=k + 1, beta=fp.quad_beta)
+    vx, vw, sx, sw, sn = cut_cell_rule_union(shapes, lo, lo + h, n=fp.quad_n, n_t=k + 1, beta=fp.quad_beta,
+                                             union_depth=fp.union_depth)
     n_loc = (k + 1) ** d
     E = np.zeros((n_loc, n_loc))
     xi_v = (vx - lo) / h
@@ -131,9 +133,6 @@ def ghost_faces(level: Level):
 
 def assemble(level: Level, shapes, fp: FormParams, with_ghost: bool = True) -> sp.csr_matrix:
     """Global A_l in canonical DoF order."""
-    if len(shapes) != 1:
-        raise NotImplementedError("cut-cell quadrature of the oracle covers one shape")
-    shape = shapes[0]
     k, d, h = level.k, level.dim, level.h
     n_loc = (k + 1) ** d
     rows, cols, vals = [], [], []
@@ -146,7 +145,7 @@ def assemble(level: Level, shapes, fp: FormParams, with_ghost: bool = True) -> s
         vals.append(np.tile(K.reshape(-1), len(uncut)))
     for c in level.active_cells():
         if level.cut[c]:
-            E = cut_cell_matrix(level, shape, c, fp)
+            E = cut_cell_matrix(level, shapes, c, fp)
             D = level.cell_dofs(c)
             rows.append(np.repeat(D, n_loc))
             cols.append(np.tile(D, n_loc))
@@ -170,7 +169,6 @@ def load_vector(level: Level, shapes, fp: FormParams, f, g=None) -> np.ndarray:
     f, g: callables on points of shape (P, d).  Uncut cells use a tensor Gauss
     rule with k+3 points per direction, cut cells the cut rule with n points per
     smooth piece in every direction."""
-    shape = shapes[0]
     k, d, h = level.k, level.dim, level.h
     b = np.zeros(level.n_dofs)
     xi_u, w_u = tensor_gauss_ref(d, k + 3)
@@ -182,7 +180,8 @@ def load_vector(level: Level, shapes, fp: FormParams, f, g=None) -> np.ndarray:
             x = lo + h * xi_u
             np.add.at(b, D, V_u.T @ (w_u * h ** d * f(x)))
             continue
-        vx, vw, sx, sw, sn = cut_cell_rule(shape, lo, lo + h, n=fp.quad_n, n_t=fp.quad_n, beta=fp.quad_beta)
+        vx, vw, sx, sw, sn = cut_cell_rule_union(shapes, lo, lo + h, n=fp.quad_n, n_t=fp.quad_n,
+                                                 beta=fp.quad_beta, union_depth=fp.union_depth)
         loc = eval_tensor_basis(k, (vx - lo) / h).T @ (vw * f(vx))
         if g is not None and len(sw):
             xi_s = (sx - lo) / h
@@ -198,7 +197,6 @@ def load_vector(level: Level, shapes, fp: FormParams, f, g=None) -> np.ndarray:
 
 def l2_error(level: Level, shapes, fp: FormParams, x: np.ndarray, u_exact) -> float:
     """|| u_h - u ||_{L2(Omega)} using the same rules as the load vector."""
-    shape = shapes[0]
     k, d, h = level.k, level.dim, level.h
     xi_u, w_u = tensor_gauss_ref(d, k + 3)
     V_u = eval_tensor_basis(k, xi_u)
@@ -210,6 +208,7 @@ def l2_error(level: Level, shapes, fp: FormParams, x: np.ndarray, u_exact) -> fl
             pts = lo + h * xi_u
             acc += np.sum(w_u * h ** d * (V_u @ xc - u_exact(pts)) ** 2)
             continue
-        vx, vw, *_ = cut_cell_rule(shape, lo, lo + h, n=fp.quad_n, n_t=fp.quad_n, beta=fp.quad_beta)
+        vx, vw, *_ = cut_cell_rule_union(shapes, lo, lo + h, n=fp.quad_n, n_t=fp.quad_n, beta=fp.quad_beta,
+                                         union_depth=fp.union_depth)
         acc += np.sum(vw * (eval_tensor_basis(k, (vx - lo) / h) @ xc - u_exact(vx)) ** 2)
     return math.sqrt(acc)

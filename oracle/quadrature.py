@@ -287,3 +287,98 @@ def cut_cell_rule(shape, box_lo, box_hi, n=16, n_t=None, beta=0.35, maxdepth=14)
     b = np.asarray(box_hi, dtype=np.float64)
     _box_rule(rule, q, a, b, n, n if n_t is None else n_t, beta, 0, maxdepth)
     return rule.arrays()
+
+
+# ---------------------------------------------------------------------------
+# Unions of shapes.  Omega = union of the shapes; Gamma = the parts of the shape
+# surfaces that lie outside every other shape.
+#   * a box inside one shape is full; a box that no surface crosses is empty;
+#   * a box crossed by exactly one surface (the other shapes disjoint from it)
+#     uses the single-shape rule above;
+#   * a box crossed by several surfaces is bisected up to `union_depth`; the
+#     remaining leaves use columns along the last axis over an n^(d-1) Gauss
+#     base grid, with the inside part of every column the exact union of the
+#     per-shape intervals (roots of the quadratics) and boundary points at the
+#     interval ends that lie inside the box.  This leaf rule is not exponentially
+#     convergent (the union has kinks where two surfaces meet); it is a fixed,
+#     deterministic rule.
+
+
+def _union_leaf(rule: Rule, quads, a, b, n, n_t):
+    d = len(a)
+    e = d - 1
+    base_dims = list(range(d - 1))
+    xs, ws = zip(*[_gauss_on(a[j], b[j], n) for j in base_dims])
+    grid = np.stack(np.meshgrid(*xs, indexing="ij"), axis=-1).reshape(-1, d - 1)
+    wgt = np.ones(1)
+    for j in range(d - 1):
+        wgt = np.multiply.outer(wgt, ws[j])
+    wgt = wgt.reshape(-1)
+    xt, wt = gauss_legendre(n_t)
+    for p in range(grid.shape[0]):
+        xb = grid[p]
+        ivs = []
+        for qi, q in enumerate(quads):
+            w = q.kappa - np.sum(((xb - q.c[:e]) / q.s[:e]) ** 2)
+            if w <= 0.0:
+                continue
+            r = q.s[e] * np.sqrt(w)
+            lo, hi = q.c[e] - r, q.c[e] + r
+            lo_c, hi_c = max(lo, a[e]), min(hi, b[e])
+            if hi_c > lo_c:
+                ivs.append((lo_c, hi_c, qi if lo > a[e] else -1, qi if hi < b[e] else -1))
+        if not ivs:
+            continue
+        ivs.sort(key=lambda v: (v[0], v[1]))
+        merged = [list(ivs[0])]
+        for lo, hi, olo, ohi in ivs[1:]:
+            cur = merged[-1]
+            if lo <= cur[1]:
+                if hi > cur[1]:
+                    cur[1], cur[3] = hi, ohi
+            else:
+                merged.append([lo, hi, olo, ohi])
+        for lo, hi, olo, ohi in merged:
+            pts = np.repeat(np.append(xb, 0.0)[None, :], n_t, axis=0)
+            pts[:, e] = lo + (hi - lo) * xt
+            rule.add_volume(pts, wgt[p] * (hi - lo) * wt)
+            for t, owner in ((lo, olo), (hi, ohi)):
+                if owner < 0:
+                    continue
+                q = quads[owner]
+                sp = np.append(xb, t)
+                g = q.grad(sp)
+                gn = np.linalg.norm(g)
+                rule.add_surface(sp[None, :], wgt[p] * gn / abs(g[e]), (g / gn)[None, :])
+
+
+def _union_box(rule: Rule, quads, a, b, n, n_t, beta, depth, union_depth, maxdepth):
+    if any(q.box_max(a, b) <= 0.0 for q in quads):
+        _tensor_box(rule, a, b, n_t)
+        return
+    crossing = [q for q in quads if q.box_min(a, b) < 0.0 < q.box_max(a, b)]
+    if not crossing:
+        return
+    if len(crossing) == 1:
+        _box_rule(rule, crossing[0], a, b, n, n_t, beta, depth, maxdepth)
+        return
+    if depth >= union_depth:
+        _union_leaf(rule, crossing, a, b, n, n_t)
+        return
+    mid = 0.5 * (a + b)
+    for corner in itertools.product((0, 1), repeat=len(a)):
+        ca = np.where(np.array(corner) == 0, a, mid)
+        cb = np.where(np.array(corner) == 0, mid, b)
+        _union_box(rule, quads, ca, cb, n, n_t, beta, depth + 1, union_depth, maxdepth)
+
+
+def cut_cell_rule_union(shapes, box_lo, box_hi, n=14, n_t=None, beta=0.35, union_depth=4, maxdepth=14):
+    """Quadrature of T ∩ (union of shapes) and of its boundary inside T (see above).
+    With one shape this is exactly cut_cell_rule."""
+    quads = [Quadric(s.center, s.semi, 1.0) for s in shapes]
+    d = quads[0].m
+    rule = Rule(d)
+    a = np.asarray(box_lo, dtype=np.float64)
+    b = np.asarray(box_hi, dtype=np.float64)
+    _union_box(rule, quads, a, b, n, n if n_t is None else n_t, beta, 0, union_depth, maxdepth)
+    return rule.arrays()

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcutmg.so")
 
-HOST_SOURCES = ["basis_linalg.cpp", "quadrature.cpp", "setup.cpp", "api.cpp"]
+HOST_SOURCES = ["basis_linalg.cpp", "quadrature.cpp", "setup.cpp", "api.cpp", "server.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -29,33 +29,38 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile and link libcutmg.so to `out`; `defines` are extra -D flags for
+    the kernels (tuning constants)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     with tempfile.TemporaryDirectory(prefix="cutmg_build_") as tmp:
         objs = []
         procs = []
         for src in HOST_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [hipcc, "-x", "c++", *COMMON, "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
+            # no FMA contraction on the host: quadrature decisions (box classification,
+            # subdivision) then round like the plain IEEE arithmetic of the checking code
+            cmd = [hipcc, "-x", "c++", *COMMON, "-ffp-contract=off", "-fopenmp", "-D__HIP_PLATFORM_AMD__",
+                   "-I/opt/rocm/include", "-c",
                    os.path.join(SRC, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
             objs.append(obj)
         for src in DEVICE_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [hipcc, *COMMON, *HIP_FLAGS, "-c", os.path.join(SRC, src), "-o", obj]
+            cmd = [hipcc, *COMMON, *HIP_FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(SRC, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
             objs.append(obj)
         for cmd, p in procs:
-            out, err = p.communicate()
+            so, se = p.communicate()
             if p.returncode != 0:
-                sys.stderr.write(" ".join(cmd) + "\n" + out + err)
+                sys.stderr.write(" ".join(cmd) + "\n" + so + se)
                 raise RuntimeError(f"compile failed: {cmd[-3]}")
-            if verbose and (out or err):
-                sys.stderr.write(out + err)
-        tmp_lib = LIB + ".tmp"
+            if verbose and (so or se):
+                sys.stderr.write(so + se)
+        tmp_lib = out + ".tmp"
         _run([hipcc, *HIP_FLAGS, "-shared", "-fopenmp", *objs, "-o", tmp_lib])
-        os.replace(tmp_lib, LIB)
-    return LIB
+        os.replace(tmp_lib, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -45,6 +45,7 @@ struct Vecs {
   T* b = nullptr;
   T* r = nullptr;
   T* dbuf = nullptr;  // cut-patch corrections of one colour
+  T* W = nullptr;     // ghost-face jumps of the operator kernel
 };
 
 struct DevLevel {
@@ -55,6 +56,7 @@ struct DevLevel {
   int n_int[8] = {};
   cmg::CutGroupDev cut64[8] = {}, cut32[8] = {};
   int64_t max_cut_nodes = 0;
+  size_t n_w = 0;  // entries of the ghost-face jump buffer
 };
 
 }  // namespace
@@ -177,11 +179,27 @@ cmg_status upload_all(cmg_problem* P) {
     k.cut_mats = cm;
     k.dof_node = dn;
     k.tables = tab;
+    int32_t *flow, *cgid, *cfaces, *tiles;
+    uint8_t* fdir;
+    TRY(upload(own, h.face_lower, &flow));
+    TRY(upload(own, h.face_dir, &fdir));
+    TRY(upload(own, h.cell_gid, &cgid));
+    TRY(upload(own, h.cell_faces, &cfaces));
+    TRY(upload(own, h.tiles, &tiles));
+    k.n_faces = static_cast<int64_t>(h.face_lower.size());
+    k.face_lower = flow;
+    k.face_dir = fdir;
+    k.cell_gid = cgid;
+    k.cell_faces = cfaces;
+    k.n_tiles = static_cast<int>(h.tiles.size());
+    k.tiles = tiles;
     d.kl32 = k;
     d.kl32.cut_mats = nullptr;
     TRY(alloc_zero(own, h.n_nodes, &d.v64.x));
     TRY(alloc_zero(own, h.n_nodes, &d.v64.b));
     TRY(alloc_zero(own, h.n_nodes, &d.v64.r));
+    d.n_w = h.face_lower.size() * static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
+    TRY(alloc_zero(own, d.n_w, &d.v64.W));
     for (int c = 0; c < 8; ++c) {
       TRY(upload(own, h.int_vertex[c], &d.int_verts[c]));
       d.n_int[c] = static_cast<int>(h.int_vertex[c].size());
@@ -238,6 +256,7 @@ cmg_status ensure_fp32(cmg_problem* P) {
     TRY(alloc_zero(own, h.n_nodes, &d.v32.x));
     TRY(alloc_zero(own, h.n_nodes, &d.v32.b));
     TRY(alloc_zero(own, h.n_nodes, &d.v32.r));
+    TRY(alloc_zero(own, d.n_w, &d.v32.W));
     TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v32.dbuf));
   }
   TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
@@ -348,7 +367,7 @@ cmg_status zero_active(cmg_problem* P, int l, T* x, hipStream_t s) {
 template <typename T>
 cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s) {
   KTimer t(P, kApply, l, s);
-  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, s));
+  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, vecs<T>(P->lv[l]).W, s));
   return CMG_OK;
 }
 
@@ -514,7 +533,7 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
     }
     cfg.shapes.push_back(sh);
   }
-  if (cfg.shapes.size() != 1) return fail(CMG_EINVAL, "cut-cell quadrature supports exactly one shape");
+  if (cfg.shapes.size() > 16) return fail(CMG_EINVAL, "at most 16 shapes");
   cfg.gamma_D = prm->gamma_D;
   cfg.gamma_g = prm->gamma_g;
   cfg.ghost_exp_mode = prm->ghost_exp_mode;
@@ -530,6 +549,7 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
     return fail(st, err);
   }
   if (!device) {
+    P->fp32 = prm->precond_fp32 != 0;
     *out = P;
     return CMG_OK;
   }
@@ -566,6 +586,44 @@ void cmg_destroy(cmg_problem* p) {
   if (p->part_host) (void)hipHostFree(p->part_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
+}
+
+cmg_status cmg_upload(cmg_problem* p) {
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (!p->lv.empty()) return CMG_OK;
+  if (hipGetDevice(&p->device) != hipSuccess) return fail(CMG_EHIP, "no HIP device");
+  cmg_status st = upload_all(p);
+  if (st == CMG_OK && p->fp32) st = ensure_fp32(p);
+  return st;
+}
+
+cmg_status cmg_device_bytes(const cmg_problem* p, int fp32, size_t* bytes) {
+  if (!p || !bytes) return fail(CMG_EINVAL, "null argument");
+  const cmg::Config& cfg = p->H.cfg;
+  const size_t nt = static_cast<size_t>(cmg::tables_size(cfg.dim, cfg.k));
+  const size_t nw_face = static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
+  size_t b64 = 0, b32 = 0;
+  for (const cmg::HostLevel& h : p->H.levels) {
+    size_t maxn = 0;
+    b64 += h.cell_flags.size() + h.ghost_mask.size() + 4 * (h.cut_id.size() + h.dof_node.size()) +
+           8 * (h.cut_mats.size() + nt) + 4 * (h.face_lower.size() + h.cell_gid.size() + h.cell_faces.size() +
+           h.tiles.size()) + h.face_dir.size();
+    b64 += 8 * (3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
+    b32 += 4 * (h.cut_mats.size() + 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
+    for (int c = 0; c < 8; ++c) {
+      const cmg::CutPatchGroup& g = h.cut[c];
+      b64 += 4 * (h.int_vertex[c].size() + g.vertex.size() + g.off.size() + g.nodes.size()) + 8 * g.inv_off.size() +
+             8 * g.inv.size();
+      b32 += 4 * g.inv.size();
+      maxn = std::max(maxn, g.nodes.size());
+    }
+    b64 += 8 * maxn;
+    b32 += 4 * maxn;
+  }
+  b64 += 8 * p->H.coarse_inv.size() + 8 * 4 * static_cast<size_t>(p->H.levels.back().n_dofs) + 8 * 1024;
+  b32 += 4 * p->H.coarse_inv.size();
+  *bytes = b64 + (fp32 ? b32 : 0);
+  return CMG_OK;
 }
 
 cmg_status cmg_set_precision(cmg_problem* p, int fp32) {

@@ -34,6 +34,7 @@ struct Config {
   int n_c = 2;
   int quad_n = 14;            // Gauss points per smooth piece of a cut-cell rule
   double quad_beta = 0.35;    // subdivision threshold of the cut-cell rule
+  int union_depth = 4;        // bisection depth of boxes crossed by several surfaces
 };
 
 // ---- 1-D basis (reference interval [0,1]) ---------------------------------
@@ -70,6 +71,13 @@ struct Column {
 // base direction.
 void cut_columns(int dim, const Shape& sh, const double* a, const double* b, int n, int n_full,
                  double beta, std::vector<Column>& out);
+// Same for the union of several shapes: boxes crossed by one surface use the
+// single-shape rule, boxes crossed by several are bisected up to union_depth
+// and then integrated column by column with exact unions of the per-shape
+// intervals (a volume column per merged interval, a surface-only column per
+// boundary point).
+void cut_columns_union(int dim, const std::vector<Shape>& shapes, const double* a, const double* b, int n,
+                       int n_full, double beta, int union_depth, std::vector<Column>& out);
 
 // ---- hierarchy --------------------------------------------------------------
 struct CutPatchGroup {          // cut patches of one colour on one level
@@ -87,6 +95,11 @@ struct HostLevel {
   std::vector<uint8_t> cell_flags;   // per cell (x fastest)
   std::vector<int32_t> cut_id;       // per cell, -1 if not cut
   std::vector<uint8_t> ghost_mask;   // per cell: bit 2*dir+side, side 1 = upper face
+  std::vector<int32_t> cell_gid;     // per cell: row of cell_faces, -1 without ghost faces
+  std::vector<int32_t> cell_faces;   // 2d face ids per cell with ghost faces (-1: none)
+  std::vector<int32_t> face_lower;   // ghost faces: lower cell
+  std::vector<uint8_t> face_dir;     //              normal direction
+  std::vector<int32_t> tiles;        // operator tiles owning active nodes (tile index, x fastest)
   std::vector<int32_t> dof_node;     // lattice node of each DoF, ascending (= canonical order)
   std::vector<int32_t> node_dof;     // per lattice node, -1 if inactive
   std::vector<double> cut_mats;      // n_cut x (k+1)^d x (k+1)^d, row-major

@@ -18,6 +18,13 @@ struct KLevel {
   const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path
   const int32_t* dof_node;   // lattice node of each DoF, ascending
   const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
+  int64_t n_faces;           // ghost faces
+  const int32_t* face_lower; // lower cell of every ghost face
+  const uint8_t* face_dir;   // its normal direction
+  const int32_t* cell_gid;   // per cell: row of cell_faces or -1
+  const int32_t* cell_faces; // 2d face ids per cell with ghost faces (-1: none)
+  int n_tiles;               // operator tiles owning active nodes
+  const int32_t* tiles;
   template <typename T>
   __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
 };
@@ -37,8 +44,10 @@ struct CutGroupDev {
 
 int tables_size(int d, int k);
 
+// y = A x (b == nullptr) or y = b - A x on every active node; W is a work
+// buffer of n_faces * k * (k+1)^(d-1) entries for the ghost-face jumps.
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, hipStream_t s);
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s);
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
                                 hipStream_t s);

@@ -195,23 +195,266 @@ __device__ void load_tables(const double* __restrict__ g, double* s, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = g[i];
 }
 
-// y = A x (b == nullptr) or y = b - A x, for every active node.
+// Ghost-face pre-pass of the operator: for every ghost face and derivative order
+// m, the jump J_m(b_t) = sum_bd psi_bd^(m)(1) x_lower - psi_bd^(m)(0) x_upper at the
+// tangential face nodes b_t, contracted with the reference face mass:
+// W_m(i_t) = sum_{b_t} prod_j Mhat[i_t,j, b_t,j] J_m(b_t).  A row of a node i of
+// a cell adjacent to the face then only needs gc_m * trace_m(i_dir) * W_m(i_t).
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ x, T* __restrict__ W) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1;
+  constexpr int NT = Pow<N1, D - 1>::v;
+  const int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (task >= L.n_faces * K) return;
+  const int64_t f = task / K;
+  const int m = static_cast<int>(task % K);
+  const double* mh = L.tables + S::T_MHAT;
+  const double* d0 = L.tables + S::T_D0;
+  const double* d1 = L.tables + S::T_D1;
+  const int dir = L.face_dir[f];
+  int c[3];
+  {
+    int64_t r = L.face_lower[f];
+#pragma unroll
+    for (int a = 0; a < D; ++a) { c[a] = static_cast<int>(r % L.N); r /= L.N; }
+  }
+  T J[NT];
+#pragma unroll
+  for (int bt = 0; bt < NT; ++bt) {
+    int I[3];
+    int rb = bt;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (a == dir) continue;
+      I[a] = K * c[a] + rb % N1;
+      rb /= N1;
+    }
+    T acc = 0;
+#pragma unroll
+    for (int bd = 0; bd <= K; ++bd) {
+      I[dir] = K * c[dir] + bd;
+      const T xl = x[lat(D, L.nn, I)];
+      I[dir] += K;
+      acc += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * x[lat(D, L.nn, I)];
+    }
+    J[bt] = acc;
+  }
+  T* out = W + (f * K + m) * NT;
+  if (D == 2) {
+#pragma unroll
+    for (int it = 0; it < N1; ++it) {
+      T acc = 0;
+#pragma unroll
+      for (int bt = 0; bt < N1; ++bt) acc += (T)mh[it * N1 + bt] * J[bt];
+      out[it] = acc;
+    }
+    return;
+  }
+  T H[NT];  // (Mhat x Mhat) J by two 1-D contractions
+#pragma unroll
+  for (int b1 = 0; b1 < N1; ++b1)
+#pragma unroll
+    for (int i0 = 0; i0 < N1; ++i0) {
+      T acc = 0;
+#pragma unroll
+      for (int b0 = 0; b0 < N1; ++b0) acc += (T)mh[i0 * N1 + b0] * J[b0 + N1 * b1];
+      H[i0 + N1 * b1] = acc;
+    }
+#pragma unroll
+  for (int i1 = 0; i1 < N1; ++i1)
+#pragma unroll
+    for (int i0 = 0; i0 < N1; ++i0) {
+      T acc = 0;
+#pragma unroll
+      for (int b1 = 0; b1 < N1; ++b1) acc += (T)mh[i1 * N1 + b1] * H[i0 + N1 * b1];
+      out[i0 + N1 * i1] = acc;
+    }
+}
+
+template <int D, int K>
+struct ApplyShape {
+  static constexpr int B = (D == 3 && K == 3) ? 2 : 4;   // cells per tile and direction
+  static constexpr int R1 = (B + 1) * K + 1;             // staged nodes per direction: cells -1 .. B-1
+  static constexpr int NR = Pow<R1, D>::v;
+  static constexpr int C1 = B + 1;                       // staged cells per direction
+  static constexpr int NCC = Pow<C1, D>::v;
+  static constexpr int O1 = B * K + 1;                   // owned nodes per direction (last tile: + 1)
+  static constexpr int NO = Pow<O1, D>::v;
+};
+
+// y = A x (b == nullptr) or y = b - A x on the active nodes of a tile of B^d
+// cells.  x on the cells -1 .. B-1 around the tile is staged in LDS; every
+// owned node sums its cell rows (uncut stiffness from LDS, cut-cell matrices
+// from HBM) and the ghost terms from the pre-pass buffer W.
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y) {
+                                               T* __restrict__ y, const T* __restrict__ W) {
   using S = Shape<D, K>;
-  __shared__ double tab[S::T_SIZE];
-  load_tables<D, K>(L.tables, tab, S::T_SIZE);
-  __syncthreads();
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L.n_dofs;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t node = L.dof_node[i];
-    int I[3];
-    int r = node;
+  using A = ApplyShape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
+  constexpr int NT = Pow<N1, D - 1>::v;
+  __shared__ double tab[S::T_FDS];  // kcell | mhat | d0 | d1 | gc
+  __shared__ T xs[A::NR];
+  __shared__ uint8_t cfl[A::NCC];
+  __shared__ int32_t ccut[A::NCC], cgid[A::NCC];
+  for (int i = threadIdx.x; i < S::T_FDS; i += blockDim.x) tab[i] = L.tables[i];
+  const double* d0 = tab + S::T_D0;
+  const double* d1 = tab + S::T_D1;
+  const double* gc = tab + S::T_GC;
+  const int NTd = (L.N + B - 1) / B;
+  for (int ti = blockIdx.x; ti < L.n_tiles; ti += gridDim.x) {
+    __syncthreads();
+    int tc[3] = {0, 0, 0};
+    {
+      int r = L.tiles[ti];
 #pragma unroll
-    for (int a = 0; a < D; ++a) { I[a] = r % L.nn; r /= L.nn; }
-    const T ax = row_apply<D, K, T>(L, x, tab, I);
-    y[node] = b ? b[node] - ax : ax;
+      for (int a = 0; a < D; ++a) { tc[a] = r % NTd; r /= NTd; }
+    }
+    for (int e = threadIdx.x; e < A::NCC; e += blockDim.x) {
+      int c[3];
+      bool in = true;
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        c[a] = B * tc[a] - 1 + r % C1;
+        r /= C1;
+        in = in && c[a] >= 0 && c[a] < L.N;
+      }
+      uint8_t f = 0;
+      int32_t cid = -1, gid = -1;
+      if (in) {
+        const int64_t cl = cell_lin(D, L.N, c);
+        f = L.flags[cl];
+        if (f & 1) {
+          cid = L.cut_id[cl];
+          gid = L.cell_gid[cl];
+        }
+      }
+      cfl[e] = f;
+      ccut[e] = cid;
+      cgid[e] = gid;
+    }
+    for (int e = threadIdx.x; e < A::NR; e += blockDim.x) {
+      int I[3];
+      bool in = true;
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        I[a] = K * (B * tc[a] - 1) + r % R1;
+        r /= R1;
+        in = in && I[a] >= 0 && I[a] < L.nn;
+      }
+      xs[e] = in ? x[lat(D, L.nn, I)] : (T)0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < A::NO; e += blockDim.x) {
+      int q[3], I[3];
+      bool own = true;
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        q[a] = r % O1;
+        r /= O1;
+        I[a] = K * B * tc[a] + q[a];
+        // the layer q = B K belongs to the next tile unless this is the last one
+        own = own && I[a] < L.nn && (q[a] < B * K || tc[a] == NTd - 1);
+      }
+      if (!own) continue;
+      // cells containing the node, in staged cell coordinates 0 .. B (cell -1 -> 0)
+      int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (q[a] % K == 0) {
+          cc[a][0] = q[a] / K;      // tile cell q/K - 1
+          lc[a][0] = K;
+          cc[a][1] = q[a] / K + 1;  // tile cell q/K
+          lc[a][1] = 0;
+          nc[a] = 2;
+        } else {
+          cc[a][0] = q[a] / K + 1;
+          lc[a][0] = q[a] % K;
+        }
+      }
+      T ax = 0;
+      bool active = false;
+      const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
+      for (int comb = 0; comb < ncomb; ++comb) {
+        int c[3], il[3];
+        int rr = comb;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int sel = rr % nc[a];
+          rr /= nc[a];
+          c[a] = cc[a][sel];
+          il[a] = lc[a][sel];
+        }
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) inside = inside && c[a] < C1;
+        if (!inside) continue;  // beyond the background box
+        int ce = c[0] + C1 * c[1];
+        if (D == 3) ce += C1 * C1 * c[2];
+        const uint8_t f = cfl[ce];
+        if (!(f & 1)) continue;
+        active = true;
+        int iloc = il[0] + N1 * il[1];
+        if (D == 3) iloc += N1 * N1 * il[2];
+        int xb = K * c[0] + R1 * K * c[1];
+        if (D == 3) xb += R1 * R1 * K * c[2];
+        constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+        T acc[NRW];
+#pragma unroll
+        for (int a = 0; a < NRW; ++a) acc[a] = 0;
+        if (f & 2) {
+          const T* row = L.cut_mats_t<T>() + ((int64_t)ccut[ce] * NL + iloc) * NL;
+#pragma unroll
+          for (int bq = 0; bq < NL; ++bq) {
+            const int b0 = bq % N1, b12 = bq / N1;
+            const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
+            acc[b12] += row[bq] * xs[xi];
+          }
+        } else {
+          const double* row = tab + S::T_KCELL + iloc * NL;
+#pragma unroll
+          for (int bq = 0; bq < NL; ++bq) {
+            const int b0 = bq % N1, b12 = bq / N1;
+            const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
+            acc[b12] += (T)row[bq] * xs[xi];
+          }
+        }
+        T sacc = 0;
+#pragma unroll
+        for (int a = 0; a < NRW; ++a) sacc += acc[a];
+        const int gid = cgid[ce];
+        if (gid >= 0) {
+#pragma unroll
+          for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int fid = L.cell_faces[(int64_t)gid * 2 * D + 2 * dir + side];
+              if (fid < 0) continue;
+              int it = 0, st = 1;
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                if (a == dir) continue;
+                it += il[a] * st;
+                st *= N1;
+              }
+              const T* w = W + (int64_t)fid * K * NT + it;
+#pragma unroll
+              for (int m = 0; m < K; ++m) {
+                const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
+                sacc += (T)sg * w[m * NT];
+              }
+            }
+        }
+        ax += sacc;
+      }
+      if (!active) continue;
+      const int64_t node = lat(D, L.nn, I);
+      y[node] = b ? b[node] - ax : ax;
+    }
   }
 }
 
@@ -291,17 +534,20 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
       const double* row = tab + S::T_KCELL + iloc * NL;
+      int qb = K * c[0] + NC1 * K * c[1];
+      if (D == 3) qb += NC1 * NC1 * K * c[2];
+      constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+      T acc[NRW];
+#pragma unroll
+      for (int a = 0; a < NRW; ++a) acc[a] = 0;
 #pragma unroll
       for (int bq = 0; bq < NL; ++bq) {
-        int q = 0, stride = 1, rb2 = bq;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          q += (K * c[a] + rb2 % N1) * stride;
-          rb2 /= N1;
-          stride *= NC1;
-        }
-        ax += (T)row[bq] * xs[p][q];
+        const int b0 = bq % N1, b12 = bq / N1;
+        const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
+        acc[b12] += (T)row[bq] * xs[p][q];
       }
+#pragma unroll
+      for (int a = 0; a < NRW; ++a) ax += acc[a];
     }
     ra[p][i] = b[node] - ax;
   }
@@ -354,7 +600,41 @@ struct CutShape {
   static constexpr int NF = D * 3 * (1 << (D - 1));       // faces touching a 2^d patch
   static constexpr int NT = Pow<K + 1, D - 1>::v;         // nodes of a cell face
   static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;
+  static constexpr int NCL = Shape<D, K>::NC;             // closure nodes
+  static constexpr int SLAB = K * Pow<2 * K + 1, D - 1>::v;  // nodes of one halo slab
+  static constexpr int NSTG = NCL + 2 * D * SLAB;         // closure + 2d slabs
 };
+
+// Extended-box coordinates (0..4k, closure at [k, 3k]) of the e-th staged
+// node: first the closure, then the slab below / above the closure in each
+// direction (k layers x (2k+1)^(d-1) nodes).  Returns the slab id (-1: closure).
+template <int D, int K>
+__device__ __forceinline__ int staged_coords(int e, int* q) {
+  using C = CutShape<D, K>;
+  constexpr int W1 = 2 * K + 1;
+  if (e < C::NCL) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      q[a] = K + e % W1;
+      e /= W1;
+    }
+    return -1;
+  }
+  e -= C::NCL;
+  const int slab = e / C::SLAB;
+  int r = e % C::SLAB;
+  const int out = slab >> 1, side = slab & 1;
+  const int s = r % K;
+  r /= K;
+  q[out] = side ? 3 * K + 1 + s : s;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (a == out) continue;
+    q[a] = K + r % W1;
+    r /= W1;
+  }
+  return slab;
+}
 
 template <int D, int K, typename T>
 __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
@@ -364,11 +644,13 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NE = C::NE, NF = C::NF, NT = C::NT;
-  constexpr int NCELL = 1 << D;
+  constexpr int NCELL = 1 << D, W1 = 2 * K + 1;
   __shared__ double tab[S::T_D1 + K * N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
   __shared__ T xs[NE];
-  __shared__ T Jf[NF][K][NT];
+  __shared__ T Wf[NF][K][NT];
   __shared__ T rs[S::NP];
+  __shared__ T parts[S::NP][1 << D];
+  __shared__ int8_t npi[S::NP][3];
   __shared__ uint8_t cfl[NCELL], cgh[NCELL];
   __shared__ int32_t ccut[NCELL];
   __shared__ int needlo[3], needhi[3];
@@ -398,10 +680,10 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
     }
     uint8_t f = 0, g = 0;
     int32_t cid = -1;
-    if (in) {
+    if (in) {  // independent loads (ghost bits are zero on inactive cells)
       const int64_t cl = cell_lin(D, L.N, c);
       f = L.flags[cl];
-      g = (f & 1) ? L.ghost[cl] : 0;
+      g = L.ghost[cl];
       cid = L.cut_id[cl];
     }
     cfl[tid] = f;
@@ -419,42 +701,32 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
     }
   }
   __syncthreads();
-  // stage x: closure [K, 3K]^D, plus the slabs [0, K-1] / [3K+1, 4K] along a
+  // stage x: closure [K, 3K]^D, plus the slab [0, K-1] / [3K+1, 4K] along a
   // direction when a ghost face lies on that side of the patch
-  for (int e = tid; e < NE; e += nth) {
+  for (int e = tid; e < C::NSTG; e += nth) {
     int q[3];
-    int r = e;
-    int outside = 0, dir_out = -1, lowside = 0;
+    const int slab = staged_coords<D, K>(e, q);
+    if (slab >= 0 && !((slab & 1) ? needhi[slab >> 1] : needlo[slab >> 1])) continue;
+    int I[3];
+    bool in = true;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      q[a] = r % E1;
-      r /= E1;
-      if (q[a] < K || q[a] > 3 * K) { ++outside; dir_out = a; lowside = q[a] < K; }
+      I[a] = K * (V[a] - 2) + q[a];
+      in = in && I[a] >= 0 && I[a] < L.nn;
     }
-    bool load = outside == 0 || (outside == 1 && (lowside ? needlo[dir_out] : needhi[dir_out]));
-    T v = 0;
-    if (load) {
-      int I[3];
-      bool in = true;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        I[a] = K * (V[a] - 2) + q[a];
-        in = in && I[a] >= 0 && I[a] < L.nn;
-      }
-      if (in) v = x[lat(D, L.nn, I)];
-    }
-    xs[e] = v;
+    int el = q[0] + E1 * q[1];
+    if (D == 3) el += E1 * E1 * q[2];
+    xs[el] = in ? x[lat(D, L.nn, I)] : (T)0;
   }
   __syncthreads();
-  // jumps of every ghost face: face (dir, plane 0..2, tangential cell t)
-  for (int task = tid; task < NF * K * NT; task += nth) {
-    const int bt = task % NT;
-    const int m = (task / NT) % K;
-    const int f = task / (NT * K);
+  // mass-contracted jumps W_m(i_t) of every ghost face touching the patch:
+  // face (dir, plane 0..2, tangential cell t), plane p between cell layers p-1, p
+  for (int task = tid; task < NF * K; task += nth) {
+    const int m = task % K;
+    const int f = task / K;
     const int dir = f / (3 << (D - 1));
     const int plane = (f >> (D - 1)) % 3;
     const int t = f & ((1 << (D - 1)) - 1);
-    // the patch cell that owns the ghost bit of this face
     int o = 0, tb = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -463,100 +735,128 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
       ++tb;
     }
     bool ghost;
-    if (plane == 0) ghost = cgh[o] & (1 << (2 * dir));                   // lower face of layer 0
-    else if (plane == 1) ghost = cgh[o] & (1 << (2 * dir + 1));          // between layers 0 and 1
-    else ghost = cgh[o | (1 << dir)] & (1 << (2 * dir + 1));             // upper face of layer 1
+    if (plane == 0) ghost = cgh[o] & (1 << (2 * dir));               // lower face of layer 0
+    else if (plane == 1) ghost = cgh[o] & (1 << (2 * dir + 1));      // between layers 0 and 1
+    else ghost = cgh[o | (1 << dir)] & (1 << (2 * dir + 1));         // upper face of layer 1
     if (!ghost) continue;
-    int q[3];
-    {
-      int rb = bt, tb2 = 0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        if (a == dir) continue;
-        q[a] = K + K * ((t >> tb2) & 1) + rb % N1;
-        rb /= N1;
-        ++tb2;
-      }
-    }
-    T acc = 0;
-#pragma unroll
-    for (int bd = 0; bd <= K; ++bd) {
-      q[dir] = K * plane + bd;
-      int el = q[0] + E1 * q[1];
-      if (D == 3) el += E1 * E1 * q[2];
-      const T xl = xs[el];
-      q[dir] += K;
-      int eu = q[0] + E1 * q[1];
-      if (D == 3) eu += E1 * E1 * q[2];
-      acc += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * xs[eu];
-    }
-    Jf[f][m][bt] = acc;
-  }
-  __syncthreads();
-  // residual on the internal nodes
-  for (int i = tid; i < nj; i += nth) {
-    const int32_t node = G.nodes[off + i];
-    int pi[3];
-    {
-      int r = node;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        pi[a] = r % L.nn - K * (V[a] - 1);  // 1 .. 2K-1
-        r /= L.nn;
-      }
-    }
-    int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+    // strides of the tangential directions and of the normal one
+    constexpr int E2 = E1 * E1;
+    const int sn = dir == 0 ? 1 : (dir == 1 ? E1 : E2);
+    int st0 = 0, st1 = 0, base = 0, tb2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      if (pi[a] == K) { cc[a][0] = 0; lc[a][0] = K; cc[a][1] = 1; lc[a][1] = 0; nc[a] = 2; }
-      else if (pi[a] < K) { cc[a][0] = 0; lc[a][0] = pi[a]; }
-      else { cc[a][0] = 1; lc[a][0] = pi[a] - K; }
+      const int sa = a == 0 ? 1 : (a == 1 ? E1 : E2);
+      if (a == dir) continue;
+      base += (K + K * ((t >> tb2) & 1)) * sa;
+      if (tb2 == 0) st0 = sa; else st1 = sa;
+      ++tb2;
     }
-    T ax = 0;
-    const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
-    for (int comb = 0; comb < ncomb; ++comb) {
-      int o = 0, il[3];
-      int r = comb;
+    base += K * plane * sn;
+    T dl[N1], du[N1];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int sel = r % nc[a];
-        r /= nc[a];
-        o |= cc[a][sel] << a;
-        il[a] = lc[a][sel];
+    for (int bd = 0; bd <= K; ++bd) {
+      dl[bd] = (T)d1[m * N1 + bd];
+      du[bd] = (T)d0[m * N1 + bd];
+    }
+    T J[NT];
+#pragma unroll
+    for (int bt = 0; bt < NT; ++bt) {
+      const int el = base + (bt % N1) * st0 + (D == 3 ? (bt / N1) * st1 : 0);
+      T acc0 = 0, acc1 = 0;
+#pragma unroll
+      for (int bd = 0; bd <= K; ++bd) {
+        acc0 += dl[bd] * xs[el + bd * sn];
+        acc1 += du[bd] * xs[el + (bd + K) * sn];
       }
-      const uint8_t f = cfl[o];
-      if (!(f & 1)) continue;
+      J[bt] = acc0 - acc1;
+    }
+    T mm[N1 * N1];
+#pragma unroll
+    for (int i = 0; i < N1 * N1; ++i) mm[i] = (T)mh[i];
+    if (D == 2) {
+#pragma unroll
+      for (int it = 0; it < N1; ++it) {
+        T acc = 0;
+#pragma unroll
+        for (int bt = 0; bt < N1; ++bt) acc += mm[it * N1 + bt] * J[bt];
+        Wf[f][m][it] = acc;
+      }
+    } else {
+      // (Mhat x Mhat) J by two 1-D contractions
+      T H[NT];
+#pragma unroll
+      for (int b1 = 0; b1 < N1; ++b1)
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) {
+          T acc = 0;
+#pragma unroll
+          for (int b0 = 0; b0 < N1; ++b0) acc += mm[i0 * N1 + b0] * J[b0 + N1 * b1];
+          H[i0 + N1 * b1] = acc;
+        }
+#pragma unroll
+      for (int i1 = 0; i1 < N1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) {
+          T acc = 0;
+#pragma unroll
+          for (int b1 = 0; b1 < N1; ++b1) acc += mm[i1 * N1 + b1] * H[i0 + N1 * b1];
+          Wf[f][m][i0 + N1 * i1] = acc;
+        }
+    }
+  }
+  // patch-local coordinates (1 .. 2K-1) of the internal nodes
+  for (int i = tid; i < nj; i += nth) {
+    int r = G.nodes[off + i];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      npi[i][a] = static_cast<int8_t>(r % L.nn - K * (V[a] - 1));
+      r /= L.nn;
+    }
+  }
+  __syncthreads();
+  // contribution of patch cell o to the row of internal node i
+  for (int task = tid; task < nj * NCELL; task += nth) {
+    const int i = task / NCELL, o = task % NCELL;
+    T part = 0;
+    int il[3];
+    bool contains = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int pa = npi[i][a], oa = (o >> a) & 1;
+      il[a] = pa - K * oa;
+      contains = contains && il[a] >= 0 && il[a] <= K;
+    }
+    const uint8_t f = cfl[o];
+    if (contains && (f & 1)) {
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
-      T sacc = 0;
+      constexpr int E2 = E1 * E1;
+      int xb = K * (1 + (o & 1)) + E1 * K * (1 + ((o >> 1) & 1));  // staged index of the cell's first node
+      if (D == 3) xb += E2 * K * (1 + ((o >> 2) & 1));
+      // dot product of the cell row with x, one partial sum per x-row of the cell
+      constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+      T acc[NRW];
+#pragma unroll
+      for (int a = 0; a < NRW; ++a) acc[a] = 0;
       if (f & 2) {
         const T* row = L.cut_mats_t<T>() + ((int64_t)ccut[o] * NL + iloc) * NL;
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
-          int e = 0, st = 1, rb = bq;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            e += (K + K * ((o >> a) & 1) + rb % N1) * st;
-            rb /= N1;
-            st *= E1;
-          }
-          sacc += row[bq] * xs[e];
+          const int b0 = bq % N1, b12 = bq / N1;
+          const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
+          acc[b12] += row[bq] * xs[xi];
         }
       } else {
         const double* row = L.tables + S::T_KCELL + iloc * NL;
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
-          int e = 0, st = 1, rb = bq;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            e += (K + K * ((o >> a) & 1) + rb % N1) * st;
-            rb /= N1;
-            st *= E1;
-          }
-          sacc += (T)row[bq] * xs[e];
+          const int b0 = bq % N1, b12 = bq / N1;
+          const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
+          acc[b12] += (T)row[bq] * xs[xi];
         }
       }
-      ax += sacc;
+#pragma unroll
+      for (int a = 0; a < NRW; ++a) part += acc[a];
       const uint8_t g = cgh[o];
       if (g) {
 #pragma unroll
@@ -565,44 +865,44 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
           for (int side = 0; side < 2; ++side) {
             if (!(g & (1 << (2 * dir + side)))) continue;
             const int plane = ((o >> dir) & 1) + side;
-            int t = 0, tb = 0;
+            int t = 0, tb = 0, it = 0, st = 1;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
               if (a == dir) continue;
               t |= ((o >> a) & 1) << tb;
               ++tb;
+              it += il[a] * st;
+              st *= N1;
             }
-            const int f = (dir * 3 + plane) * (1 << (D - 1)) + t;
-            T gs = 0;
+            const int fi = (dir * 3 + plane) * (1 << (D - 1)) + t;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-              T js = 0;
-              for (int bt = 0; bt < NT; ++bt) {
-                double w = 1.0;
-                int rb = bt;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                  if (a == dir) continue;
-                  w *= mh[il[a] * N1 + rb % N1];
-                  rb /= N1;
-                }
-                js += (T)w * Jf[f][m][bt];
-              }
               const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
-              gs += (T)sg * js;
+              part += (T)sg * Wf[fi][m][it];
             }
-            ax += gs;
           }
       }
     }
-    rs[i] = b[node] - ax;
+    parts[i][o] = part;
+  }
+  __syncthreads();
+  for (int i = tid; i < nj; i += nth) {
+    T ax = 0;
+#pragma unroll
+    for (int o = 0; o < NCELL; ++o) ax += parts[i][o];
+    rs[i] = b[G.nodes[off + i]] - ax;
   }
   __syncthreads();
   const T* inv = G.inv_t<T>() + G.inv_off[gp];
   for (int i = tid; i < nj; i += nth) {
-    T acc = 0;
-    for (int j = 0; j < nj; ++j) acc += inv[(int64_t)j * nj + i] * rs[j];
-    dbuf[off + i] = acc;
+    T a0 = 0, a1 = 0;
+    int j = 0;
+    for (; j + 1 < nj; j += 2) {
+      a0 += inv[(int64_t)j * nj + i] * rs[j];
+      a1 += inv[(int64_t)(j + 1) * nj + i] * rs[j + 1];
+    }
+    if (j < nj) a0 += inv[(int64_t)j * nj + i] * rs[j];
+    dbuf[off + i] = a0 + a1;
   }
 }
 
@@ -660,56 +960,73 @@ __global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const
   xf[node] += acc;
 }
 
-// b_c[J] = sum_I P(I, J) r_f[I] for every active coarse node (transpose).
+// b_c[J] = sum_I P(I, J) r_f[I] for every active coarse node (transpose).  In
+// every direction the fine nodes with a non-zero weight form one contiguous
+// range: [2J-2k+1, 2J+2k-1] around a coarse vertex, [2kC+1, 2kC+2k-1] inside a
+// coarse cell C; the weights are read from the 1-D prolongation table.
+template <int K>
+__device__ __forceinline__ double restrict_weight(const double* p1d, int J, int I) {
+  constexpr int N1 = K + 1;
+  if (J % K == 0) {
+    const int v = J / K;
+    if (I == 2 * J) return 1.0;
+    if (I < 2 * J) return p1d[(I - 2 * K * (v - 1)) * N1 + K];
+    return p1d[(I - 2 * K * v) * N1 + 0];
+  }
+  const int C = J / K;
+  return p1d[(I - 2 * K * C) * N1 + J % K];
+}
+
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T* __restrict__ rf,
                                                   T* __restrict__ bc) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1;
-  constexpr int MAXL = 4 * K - 1;
   __shared__ double p1d[S::NC1 * N1];
   for (int t = threadIdx.x; t < S::NC1 * N1; t += blockDim.x) p1d[t] = Lf.tables[S::T_P1D + t];
   __syncthreads();
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= Lc.n_dofs) return;
   const int32_t node = Lc.dof_node[j];
-  int fi[3][MAXL], nf[3];
-  double w[3][MAXL];
+  int J[3], lo[3], hi[3];
   int r = node;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const int J = r % Lc.nn;
+    J[a] = r % Lc.nn;
     r /= Lc.nn;
-    int n = 0;
-    if (J % K == 0) {
-      const int v = J / K;
-      fi[a][n] = 2 * J;
-      w[a][n] = 1.0;
-      ++n;
-      if (v - 1 >= 0)
-        for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * (v - 1) + q; w[a][n] = p1d[q * N1 + K]; ++n; }
-      if (v < Lc.N)
-        for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * v + q; w[a][n] = p1d[q * N1 + 0]; ++n; }
+    if (J[a] % K == 0) {
+      lo[a] = 2 * J[a] - 2 * K + 1;
+      hi[a] = 2 * J[a] + 2 * K - 1;
     } else {
-      const int C = J / K, bb = J % K;
-      for (int q = 1; q < 2 * K; ++q) { fi[a][n] = 2 * K * C + q; w[a][n] = p1d[q * N1 + bb]; ++n; }
+      const int C = J[a] / K;
+      lo[a] = 2 * K * C + 1;
+      hi[a] = 2 * K * C + 2 * K - 1;
     }
-    nf[a] = n;
+    lo[a] = lo[a] < 0 ? 0 : lo[a];
+    hi[a] = hi[a] > Lf.nn - 1 ? Lf.nn - 1 : hi[a];
   }
   T acc = 0;
-  const int ncomb = nf[0] * nf[1] * (D == 3 ? nf[2] : 1);
-  for (int comb = 0; comb < ncomb; ++comb) {
-    int I[3];
-    double wt = 1.0;
-    int rc = comb;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int s = rc % nf[a];
-      rc /= nf[a];
-      I[a] = fi[a][s];
-      wt *= w[a][s];
+  if (D == 2) {
+    for (int i1 = lo[1]; i1 <= hi[1]; ++i1) {
+      const double w1 = restrict_weight<K>(p1d, J[1], i1);
+      T a0 = 0;
+      for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+        a0 += (T)restrict_weight<K>(p1d, J[0], i0) * rf[i0 + (int64_t)Lf.nn * i1];
+      acc += (T)w1 * a0;
     }
-    acc += (T)wt * rf[lat(D, Lf.nn, I)];
+  } else {
+    for (int i2 = lo[2]; i2 <= hi[2]; ++i2) {
+      const double w2 = restrict_weight<K>(p1d, J[2], i2);
+      T a1 = 0;
+      for (int i1 = lo[1]; i1 <= hi[1]; ++i1) {
+        const double w1 = restrict_weight<K>(p1d, J[1], i1);
+        T a0 = 0;
+        for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+          a0 += (T)restrict_weight<K>(p1d, J[0], i0) * rf[i0 + (int64_t)Lf.nn * (i1 + (int64_t)Lf.nn * i2)];
+        a1 += (T)w1 * a0;
+      }
+      acc += (T)w2 * a1;
+    }
   }
   bc[node] = acc;
 }
@@ -783,11 +1100,17 @@ int tables_size(int d, int k) {
 }
 
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, hipStream_t s) {
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    const unsigned nb = std::min<unsigned>(blocks(L.n_dofs), kMaxResidentBlocks);
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, x, b, y);
+    if (L.n_faces > 0) {
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value)), dim3(256), 0, s,
+                         L, x, W);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks);
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, x, b, y, W);
     return hipGetLastError();
   });
 }
@@ -869,7 +1192,7 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
 }
 
 #define CMG_INSTANTIATE(T)                                                                                   \
-  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, hipStream_t);                \
+  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t);            \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
                                               hipStream_t);                                                        \
   template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \

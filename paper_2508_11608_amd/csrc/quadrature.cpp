@@ -289,7 +289,144 @@ void box_rule(const Ctx& C, const double* a, const double* b, int depth) {
   }
 }
 
+// Union of shapes, box crossed by several surfaces at the maximal union depth:
+// columns along the last axis over an n^(d-1) Gauss base grid; the inside part
+// of a column is the exact union of the per-shape intervals, and every interval
+// end inside the box is a boundary point of its shape.
+void union_leaf(int dim, const std::vector<const Quadric*>& qs, const double* a, const double* b, const Gauss& g,
+                int n, std::vector<Column>& out) {
+  const int e = dim - 1;
+  const int nb = dim == 2 ? n : n * n;
+  struct Iv { double lo, hi; int olo, ohi; };
+  std::vector<Iv> ivs;
+  for (int p = 0; p < nb; ++p) {
+    double xb[kMaxDim] = {0, 0, 0}, wb = 1.0;
+    {
+      int r = p;
+      for (int j = 0; j < dim - 1; ++j) {
+        const int i = r % n;
+        r /= n;
+        xb[j] = a[j] + (b[j] - a[j]) * g.x[i];
+        wb *= (b[j] - a[j]) * g.w[i];
+      }
+    }
+    ivs.clear();
+    for (size_t qi = 0; qi < qs.size(); ++qi) {
+      const Quadric& q = *qs[qi];
+      double w = q.kappa;
+      for (int j = 0; j < dim - 1; ++j) {
+        const double t = (xb[j] - q.c[j]) / q.s[j];
+        w -= t * t;
+      }
+      if (!(w > 0.0)) continue;
+      const double r = q.s[e] * std::sqrt(w);
+      const double lo = q.c[e] - r, hi = q.c[e] + r;
+      const double lo_c = std::max(lo, a[e]), hi_c = std::min(hi, b[e]);
+      if (hi_c > lo_c) ivs.push_back({lo_c, hi_c, lo > a[e] ? static_cast<int>(qi) : -1,
+                                      hi < b[e] ? static_cast<int>(qi) : -1});
+    }
+    if (ivs.empty()) continue;
+    std::sort(ivs.begin(), ivs.end(), [](const Iv& u, const Iv& v) {
+      return u.lo < v.lo || (u.lo == v.lo && u.hi < v.hi);
+    });
+    std::vector<Iv> merged{ivs[0]};
+    for (size_t i = 1; i < ivs.size(); ++i) {
+      Iv& cur = merged.back();
+      if (ivs[i].lo <= cur.hi) {
+        if (ivs[i].hi > cur.hi) { cur.hi = ivs[i].hi; cur.ohi = ivs[i].ohi; }
+      } else {
+        merged.push_back(ivs[i]);
+      }
+    }
+    for (const Iv& iv : merged) {
+      Column col{};
+      col.e = e;
+      for (int j = 0; j < dim - 1; ++j) col.x[j] = xb[j];
+      col.w = wb;
+      col.t0 = iv.lo;
+      col.t1 = iv.hi;
+      col.surf = false;
+      out.push_back(col);
+      for (int end = 0; end < 2; ++end) {
+        const int owner = end ? iv.ohi : iv.olo;
+        if (owner < 0) continue;
+        const Quadric& q = *qs[owner];
+        Column sc{};
+        sc.e = e;
+        for (int j = 0; j < dim - 1; ++j) sc.x[j] = xb[j];
+        sc.w = wb;
+        sc.t0 = sc.t1 = 0.0;
+        sc.surf = true;
+        sc.ts = end ? iv.hi : iv.lo;
+        double pt[kMaxDim], gq[kMaxDim], gn = 0.0;
+        for (int j = 0; j < dim; ++j) pt[j] = j == e ? sc.ts : xb[j];
+        for (int j = 0; j < dim; ++j) {
+          gq[j] = 2.0 * (pt[j] - q.c[j]) / (q.s[j] * q.s[j]);
+          gn += gq[j] * gq[j];
+        }
+        gn = std::sqrt(gn);
+        sc.sw = wb * gn / std::fabs(gq[e]);
+        for (int j = 0; j < dim; ++j) sc.nrm[j] = gq[j] / gn;
+        out.push_back(sc);
+      }
+    }
+  }
+}
+
+void union_box(const Ctx& base, const std::vector<Quadric>& qs, const double* a, const double* b, int depth,
+               int union_depth) {
+  const int dim = base.dim;
+  for (const Quadric& q : qs)
+    if (q.box_max(a, b) <= 0.0) { full_box(base, a, b); return; }
+  std::vector<const Quadric*> crossing;
+  for (const Quadric& q : qs)
+    if (q.box_min(a, b) < 0.0 && q.box_max(a, b) > 0.0) crossing.push_back(&q);
+  if (crossing.empty()) return;
+  if (crossing.size() == 1) {
+    Ctx C = base;
+    C.q = *crossing[0];
+    box_rule(C, a, b, depth);
+    return;
+  }
+  if (depth >= union_depth) {
+    union_leaf(dim, crossing, a, b, *base.gn, base.n, *base.out);
+    return;
+  }
+  double mid[kMaxDim];
+  for (int j = 0; j < dim; ++j) mid[j] = 0.5 * (a[j] + b[j]);
+  for (int corner = 0; corner < (1 << dim); ++corner) {
+    double ca[kMaxDim], cb[kMaxDim];
+    for (int j = 0; j < dim; ++j) {
+      const bool up = (corner >> j) & 1;
+      ca[j] = up ? mid[j] : a[j];
+      cb[j] = up ? b[j] : mid[j];
+    }
+    union_box(base, qs, ca, cb, depth + 1, union_depth);
+  }
+}
+
 }  // namespace
+
+void cut_columns_union(int dim, const std::vector<Shape>& shapes, const double* a, const double* b, int n,
+                       int n_full, double beta, int union_depth, std::vector<Column>& out) {
+  std::vector<Quadric> qs(shapes.size());
+  for (size_t i = 0; i < shapes.size(); ++i) {
+    qs[i].m = dim;
+    for (int j = 0; j < dim; ++j) { qs[i].c[j] = shapes[i].c[j]; qs[i].s[j] = shapes[i].s[j]; }
+    qs[i].kappa = 1.0;
+  }
+  Ctx C;
+  C.dim = dim;
+  C.q = qs[0];
+  C.n = n;
+  C.n_full = n_full;
+  C.beta = beta;
+  Gauss gn(n), gf(n_full);
+  C.gn = &gn;
+  C.gf = &gf;
+  C.out = &out;
+  union_box(C, qs, a, b, 0, union_depth);
+}
 
 void cut_columns(int dim, const Shape& sh, const double* a, const double* b, int n, int n_full,
                  double beta, std::vector<Column>& out) {

@@ -264,6 +264,53 @@ void classify(const Config& cfg, int N, HostLevel& L, const HostLevel* parent, s
       }
     }
   }
+  // Ghost face list (lower cell, direction) and, per cell with ghost faces, the
+  // ids of its 2d faces (-1 where the face is not a ghost face).
+  L.cell_gid.assign(L.n_cells, -1);
+  L.cell_faces.clear();
+  int32_t ng = 0;
+  for (int64_t c = 0; c < L.n_cells; ++c)
+    if (L.ghost_mask[c]) {
+      L.cell_gid[c] = ng++;
+      L.cell_faces.insert(L.cell_faces.end(), 2 * d, -1);
+    }
+  L.face_lower.clear();
+  L.face_dir.clear();
+  for (int64_t c = 0; c < L.n_cells; ++c) {
+    if (!L.ghost_mask[c]) continue;
+    int ci[kMaxDim];
+    G.cell_of(c, ci);
+    for (int dir = 0; dir < d; ++dir) {
+      if (!(L.ghost_mask[c] & (1 << (2 * dir + 1)))) continue;
+      int nb[kMaxDim];
+      std::memcpy(nb, ci, sizeof nb);
+      nb[dir] += 1;
+      const int32_t fid = static_cast<int32_t>(L.face_lower.size());
+      L.face_lower.push_back(static_cast<int32_t>(c));
+      L.face_dir.push_back(static_cast<uint8_t>(dir));
+      L.cell_faces[static_cast<size_t>(L.cell_gid[c]) * 2 * d + 2 * dir + 1] = fid;
+      L.cell_faces[static_cast<size_t>(L.cell_gid[G.cell(nb)]) * 2 * d + 2 * dir] = fid;
+    }
+  }
+  // Tiles of B^d cells for the operator kernel; a tile owns the nodes
+  // [B k t, B k (t+1)) per direction (the last tile also the upper boundary) and is
+  // listed when it owns an active node.
+  const int B = (d == 3 && k == 3) ? 2 : 4;
+  const int NTd = (N + B - 1) / B;
+  std::vector<uint8_t> tile_used(static_cast<size_t>(ipow(NTd, d)), 0);
+  for (int32_t node : L.dof_node) {
+    int64_t r = node, t = 0, stride = 1;
+    for (int j = 0; j < d; ++j) {
+      const int I = static_cast<int>(r % L.nn);
+      r /= L.nn;
+      t += std::min(I / (B * k), NTd - 1) * stride;
+      stride *= NTd;
+    }
+    tile_used[t] = 1;
+  }
+  L.tiles.clear();
+  for (size_t t = 0; t < tile_used.size(); ++t)
+    if (tile_used[t]) L.tiles.push_back(static_cast<int32_t>(t));
 }
 
 // Dense assembly of A restricted to a node set (map node -> position), from the
@@ -344,12 +391,11 @@ void uncut_cell_matrix(const Config& cfg, const Basis1D& B, double h, std::vecto
 }
 
 void cut_cell_matrix(const Config& cfg, const Basis1D& B, double h, const double* lo, std::vector<double>& E) {
-  if (cfg.shapes.size() != 1) throw std::runtime_error("cut cells of unions are not supported");
   const int d = cfg.dim, k = cfg.k, na = 2 * k + 1, nl = ipow(k + 1, d), nm = ipow(na, d);
   std::vector<Column> cols;
   double hi[kMaxDim];
   for (int j = 0; j < d; ++j) hi[j] = lo[j] + h;
-  cut_columns(d, cfg.shapes[0], lo, hi, cfg.quad_n, k + 1, cfg.quad_beta, cols);
+  cut_columns_union(d, cfg.shapes, lo, hi, cfg.quad_n, k + 1, cfg.quad_beta, cfg.union_depth, cols);
   // Legendre moments in local coordinates xi = (x - lo)/h: volume, surface,
   // surface times n_j.
   std::vector<double> mv(nm, 0.0), ms(nm, 0.0), mn(static_cast<size_t>(d) * nm, 0.0);
@@ -746,7 +792,7 @@ void load_vector(const Hierarchy& H, const std::function<double(const double*)>&
       }
     } else {
       std::vector<Column> cols;
-      cut_columns(d, cfg.shapes[0], lo, hi, nq, nq, cfg.quad_beta, cols);
+      cut_columns_union(d, cfg.shapes, lo, hi, nq, nq, cfg.quad_beta, cfg.union_depth, cols);
       for (const Column& col : cols) {
         double x[kMaxDim], xi[kMaxDim];
         for (int j = 0; j < d; ++j) x[j] = col.x[j];

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY_PATH = os.path.join(_HERE, "libcutmg.so")
 
 CMG_STATUS = {0: "CMG_OK", -1: "CMG_EINVAL", -2: "CMG_ENOMEM", -3: "CMG_EGEOM", -4: "CMG_ENOTSPD",
-              -5: "CMG_ENOTCONV", -6: "CMG_EBREAKDOWN", -7: "CMG_EHIP"}
+              -5: "CMG_ENOTCONV", -6: "CMG_EBREAKDOWN", -7: "CMG_EHIP", 1: "CMG_PENDING"}
+CMG_PENDING = 1
 
 
 class CutmgError(RuntimeError):
@@ -41,9 +42,22 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("n_frac", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("levelset", LevelSet), ("params", Params), ("n_modes", ctypes.c_int),
+                ("kappa", ctypes.c_void_p), ("amp", ctypes.c_void_p), ("phase", ctypes.c_void_p),
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n_dofs", ctypes.c_int64), ("info", SolveInfo), ("cache_hit", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_admitted", ctypes.c_double),
+                ("t_solve_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured", "cmg_rhs_fourier",
-            "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error"]
+            "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
+            "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy"]
 
 _lib = None
 
@@ -74,6 +88,11 @@ def load_library():
         "cmg_rhs_fourier": [P, I, V, V, V, ctypes.POINTER(ctypes.c_double)],
         "cmg_export": [P, I, I, V, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "cmg_timing": [P, ctypes.c_uint],
+        "cmg_upload": [P],
+        "cmg_device_bytes": [P, I, ctypes.POINTER(ctypes.c_size_t)],
+        "cmg_server_create": [ctypes.c_size_t, I, ctypes.POINTER(P)],
+        "cmg_submit": [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
+        "cmg_poll": [P, ctypes.c_uint64, ctypes.POINTER(Result), V, ctypes.c_int64],
         "cmg_timing_read": [P, I, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
@@ -82,6 +101,8 @@ def load_library():
         f.restype = ctypes.c_int
     lib.cmg_destroy.argtypes = [P]
     lib.cmg_destroy.restype = None
+    lib.cmg_server_destroy.argtypes = [P]
+    lib.cmg_server_destroy.restype = None
     lib.cmg_last_error.argtypes = []
     lib.cmg_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -260,3 +281,75 @@ class Problem:
         keys = ["n_dofs", "active_cells", "cut_cells", "interior_patches", "cut_patches", "sum_nj2",
                 "ghost_faces", "nodes_per_dir"]
         return dict(zip(keys, (int(t) for t in v)))
+
+
+def _levelset_params(workload, quad_n=14, fp32=False):
+    d = workload.dim
+    centers = (ctypes.c_double * (len(workload.centers) * d))(*[v for c in workload.centers for v in c])
+    semi = (ctypes.c_double * (len(workload.semi) * d))(*[v for s in workload.semi for v in s])
+    ls = LevelSet(d, len(workload.centers), centers, semi, workload.lo, workload.hi)
+    prm = Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
+                 workload.ghost_exp_mode, workload.n_c, quad_n, int(bool(fp32)))
+    return ls, prm, (centers, semi)
+
+
+class Server:
+    """Continuous-batching solve server of the library (one GPU, max_slots
+    concurrent solves, admission by device footprint, resident hierarchies)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        load_library()
+        h = ctypes.c_void_p()
+        st = _lib.cmg_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h))
+        if st != 0:
+            raise CutmgError(st, "server creation failed")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, workload, fourier=None, rtol=1e-8, maxit=200, fp32=True, quad_n=14) -> int:
+        """Queue one solve; fourier = (kappa, amp, theta) or None for the manufactured problem."""
+        ls, prm, keep = _levelset_params(workload, quad_n, fp32)
+        arrays = []
+        if fourier is not None:
+            kappa = np.ascontiguousarray(fourier[0], dtype=np.int32)
+            amp = np.ascontiguousarray(fourier[1], dtype=np.float64)
+            theta = np.ascontiguousarray(fourier[2], dtype=np.float64)
+            arrays = [kappa, amp, theta]
+            req = Request(ls, prm, len(amp), kappa.ctypes.data, amp.ctypes.data, theta.ctypes.data, rtol, maxit)
+        else:
+            req = Request(ls, prm, 0, None, None, None, rtol, maxit)
+        t = ctypes.c_uint64()
+        st = _lib.cmg_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st != 0:
+            raise CutmgError(st, "submit failed")
+        del keep, arrays  # the request is copied by the library
+        return t.value
+
+    def poll(self, ticket: int, n_dofs: int = None):
+        """None while pending, else (result dict, solution or None)."""
+        res = Result()
+        x = None
+        if n_dofs is not None:
+            x = np.empty(n_dofs, dtype=np.float64)
+        st = _lib.cmg_poll(self._h, ticket, ctypes.byref(res), x.ctypes.data if x is not None else None,
+                           n_dofs if n_dofs is not None else 0)
+        if st == CMG_PENDING:
+            return None
+        if st != 0:
+            raise CutmgError(st, "poll failed (wrong solution length?)")
+        out = {"status": res.status, "n_dofs": res.n_dofs, "iterations": res.info.iterations,
+               "rel_residual": res.info.rel_residual, "cache_hit": bool(res.cache_hit),
+               "t_submit": res.t_submit, "t_start": res.t_start, "t_admitted": res.t_admitted,
+               "t_solve_start": res.t_solve_start, "t_done": res.t_done}
+        return out, x
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cmg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,8 @@ except ImportError:  # pragma: no cover
 pytestmark = pytest.mark.gpu
 
 CASES = [W.disc_q2(), W.offcentre_disc(1, 4), W.offcentre_disc(3, 3), W.ellipse(2, 3),
-         W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2), W.offcentre_ball(1, 3)]
+         W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2), W.offcentre_ball(1, 3),
+         W.disc_union(2, 3), W.ball_union(2, 3)]
 
 TOL_APPLY = 1e-12
 TOL_SMOOTH = 1e-11

@@ -1,0 +1,96 @@
+"""The solve server: every result is the same alone and in the mix (bitwise),
+and equals a direct solve of the same problem through cmg_solve."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    ws = [W.offcentre_disc(2, 4), W.offcentre_ball(2, 3), W.ellipse(3, 3), W.offcentre_disc(1, 4),
+          W.offcentre_ball(1, 3)]
+    out = []
+    for i, w in enumerate(ws + ws[:3]):
+        out.append((w, W.fourier_modes(w.dim, 1000 + i), bool(i % 2)))
+    return out
+
+
+def _run(server, reqs):
+    from paper_2508_11608_amd import Problem
+
+    tickets = [server.submit(w, fourier=f, fp32=fp32) for w, f, fp32 in reqs]
+    sizes = {}
+    results = []
+    for (w, f, fp32), t in zip(reqs, tickets):
+        if w.name not in sizes:
+            sizes[w.name] = Problem(w, device=False).ndofs()
+        while True:
+            r = server.poll(t, sizes[w.name])
+            if r is not None:
+                break
+            time.sleep(0.001)
+        results.append(r)
+    return results
+
+
+def test_results_alone_equal_results_in_the_mix():
+    from paper_2508_11608_amd import Server
+
+    reqs = _mix()
+    print(f"\n[case] serving mix of {len(reqs)} requests", flush=True)
+    mix = Server(8 << 30, 3)
+    in_mix = _run(mix, reqs)
+    mix.close()
+    for (w, f, fp32), (res, x) in zip(reqs, in_mix):
+        alone_srv = Server(8 << 30, 1)
+        (res1, x1), = _run(alone_srv, [(w, f, fp32)])
+        alone_srv.close()
+        assert res["status"] == 0 and res1["status"] == 0
+        assert res["rel_residual"] <= 1e-8
+        assert res["iterations"] == res1["iterations"]
+        assert np.array_equal(x, x1), w.name
+
+
+def test_server_result_matches_direct_solve():
+    from paper_2508_11608_amd import Problem, Server
+
+    w = W.offcentre_ball(2, 3)
+    f = W.fourier_modes(3, 7)
+    srv = Server(4 << 30, 2)
+    (res, x), = _run(srv, [(w, f, False)])
+    srv.close()
+    P = Problem(w)
+    b = torch.from_numpy(P.rhs_fourier(*f)).cuda()
+    xd, info = P.solve(b, rtol=1e-8)
+    assert res["iterations"] == info["iterations"]
+    assert np.array_equal(x, xd.cpu().numpy())
+
+
+def test_admission_under_a_small_budget():
+    """A budget that holds one hierarchy at a time still finishes every request
+    (eviction of idle hierarchies, waiting for memory)."""
+    from paper_2508_11608_amd import Problem, Server
+    from paper_2508_11608_amd import cutmg
+    import ctypes
+
+    ws = [W.offcentre_disc(2, 4), W.ellipse(2, 4), W.offcentre_disc(3, 3)]
+    need = 0
+    for w in ws:
+        P = Problem(w, device=False)
+        b = ctypes.c_size_t()
+        cutmg._lib.cmg_device_bytes(P._h, 1, ctypes.byref(b))
+        need = max(need, b.value)
+    srv = Server(int(need * 1.5), 2)
+    reqs = [(w, W.fourier_modes(2, 50 + i), True) for i, w in enumerate(ws * 2)]
+    res = _run(srv, reqs)
+    srv.close()
+    assert all(r["status"] == 0 and r["rel_residual"] <= 1e-8 for r, _ in res)

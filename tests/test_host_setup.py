@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def _workloads():
     return [W.disc_q2(), W.offcentre_disc(3, 3), W.offcentre_disc(1, 4), W.ellipse(2, 3),
-            W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2)]
+            W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2),
+            W.disc_union(2, 3), W.ball_union(2, 2), W.sphere_union_8(2, 2)]
 
 
 @pytest.fixture(scope="module", params=_workloads(), ids=lambda w: w.name)
@@ -61,7 +62,7 @@ def test_dof_numbering(pair):
 
 def test_cut_cell_matrices(pair):
     w, P, levels, _, _ = pair
-    shape = OP.shapes_of(w)[0]
+    shapes = OP.shapes_of(w)
     fp = OP.form_params(w)
     nl = (w.k + 1) ** w.dim
     for l in (0, len(levels) - 1):
@@ -71,7 +72,7 @@ def test_cut_cell_matrices(pair):
         assert len(cells) == E.shape[0]
         step = max(1, len(cells) // 25)
         for i in range(0, len(cells), step):
-            ref = cut_cell_matrix(lev, shape, cells[i], fp)
+            ref = cut_cell_matrix(lev, shapes, cells[i], fp)
             assert np.abs(E[i] - ref).max() <= 2e-13 * np.abs(ref).max(), (l, cells[i])
 
 
@@ -110,14 +111,26 @@ def test_patches_and_local_inverses(pair):
 
 
 def test_coarse_inverse(pair):
+    """Residual of the library's inverse against the oracle's A_0.  A computed
+    inverse leaves |A_0 X - I| of order eps * cond(A_0), and cond(A_0) reaches
+    ~6e8 for the eight-sphere union at Q3 (tiny cut fractions), so the bound is
+    the larger of 1e-9 and 2 eps cond_2(A_0)."""
     w, P, levels, mats, H = pair
     inv = P.export(0, 4, np.float64).reshape(levels[0].n_dofs, -1)
-    ref = np.linalg.inv(mats[0].toarray())
-    assert np.abs(inv - ref).max() <= 1e-10 * np.abs(ref).max()
+    A0 = mats[0].toarray()
+    bound = max(1e-9, 2 * np.finfo(float).eps * np.linalg.cond(A0))
+    assert np.abs(A0 @ inv - np.eye(len(A0))).max() <= bound
+
+
+def _skip_many_shapes(w):
+    if len(w.centers) > 2:
+        pytest.skip("load-vector parity of unions is covered by the two-shape cases; the oracle's "
+                    "load vector of the eight-shape union takes minutes")
 
 
 def test_manufactured_rhs(pair):
     w, P, levels, _, _ = pair
+    _skip_many_shapes(w)
     b = P.rhs_manufactured()
     ref = OP.rhs(w, levels[-1])
     assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
@@ -125,6 +138,7 @@ def test_manufactured_rhs(pair):
 
 def test_fourier_rhs(pair):
     w, P, levels, _, _ = pair
+    _skip_many_shapes(w)
     kappa, amp, theta = W.fourier_modes(w.dim, seed=1000)
     b = P.rhs_fourier(kappa, amp, theta)
     ref = OP.rhs_fourier(w, levels[-1], kappa, amp, theta)

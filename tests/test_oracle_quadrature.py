@@ -6,7 +6,7 @@ import pytest
 from scipy.special import ellipe
 
 from oracle.geometry import Shape, classify_cells, sphere
-from oracle.quadrature import cut_cell_rule
+from oracle.quadrature import cut_cell_rule, cut_cell_rule_union
 
 
 def _integrate(shape, d, N, lo=-1.0, hi=1.0, n=14):
@@ -81,3 +81,87 @@ def test_single_cell_circular_segment():
     assert abs(vw.sum() - cap) < 1e-14
     assert abs(sw.sum() - 2 * math.asin(0.5)) < 1e-14  # arc length for |y| <= 0.5
     assert seg > cap
+
+
+# ---------------------------------------------------------------------------
+# Unions of shapes: closed forms of two overlapping discs / balls (lens and cap
+# formulas), the divergence theorem, and the reduction to the single-shape rule.
+# The leaf rule on kinked cells is a fixed rule, not a converged one: measured
+# errors are ~1e-7 (area / volume) and ~1e-4 (perimeter / surface), so the
+# bounds below are loose enough for it and tight enough that a dropped or
+# double-counted interval, a wrong merge or a flipped normal (all O(1e-1)) fail.
+
+def _integrate_union(shapes, d, N, lo=-1.0, hi=1.0):
+    act, cut = classify_cells(shapes, d, N, lo, hi)
+    h = (hi - lo) / N
+    V = S = XN = 0.0
+    for c in np.argwhere(cut):
+        a = lo + c * h
+        vx, vw, sx, sw, sn = cut_cell_rule_union(shapes, a, a + h, n=14, n_t=4)
+        V += vw.sum()
+        S += sw.sum()
+        XN += (sw * np.sum(sx * sn, axis=1)).sum()
+    V += np.count_nonzero(act & ~cut) * h ** d
+    return V, S, XN
+
+
+def _two_circles(r1, r2, D):
+    a1 = math.acos((D * D + r1 * r1 - r2 * r2) / (2 * D * r1))  # half-angle of circle 1's arc inside circle 2
+    a2 = math.acos((D * D + r2 * r2 - r1 * r1) / (2 * D * r2))
+    lens = r1 * r1 * a1 + r2 * r2 * a2 - 0.5 * math.sqrt((-D + r1 + r2) * (D + r1 - r2) * (D - r1 + r2) * (D + r1 + r2))
+    return math.pi * (r1 * r1 + r2 * r2) - lens, r1 * (2 * math.pi - 2 * a1) + r2 * (2 * math.pi - 2 * a2)
+
+
+def _two_balls(r1, r2, D):
+    lens = math.pi * (r1 + r2 - D) ** 2 * (D * D + 2 * D * r2 - 3 * r2 * r2 + 2 * D * r1 + 6 * r1 * r2
+                                           - 3 * r1 * r1) / (12 * D)
+    x1 = (D * D + r1 * r1 - r2 * r2) / (2 * D)  # distance from centre 1 to the intersection plane
+    x2 = D - x1
+    caps = 2 * math.pi * r1 * (r1 - x1) + 2 * math.pi * r2 * (r2 - x2)  # caps hidden inside the other ball
+    return 4 / 3 * math.pi * (r1 ** 3 + r2 ** 3) - lens, 4 * math.pi * (r1 * r1 + r2 * r2) - caps
+
+
+@pytest.mark.parametrize("N", [4, 8, 16])
+def test_two_disc_union_closed_forms(N):
+    c1, c2, r1, r2 = np.array([-0.21, 0.05]), np.array([0.27, -0.11]), 0.45, 0.38
+    A, P = _two_circles(r1, r2, float(np.linalg.norm(c1 - c2)))
+    V, S, XN = _integrate_union([sphere(c1, r1), sphere(c2, r2)], 2, N)
+    assert abs(V / A - 1) < 1e-6
+    assert abs(S / P - 1) < 2e-3
+    assert abs(XN / (2 * V) - 1) < 1e-3  # int_Gamma x.n = d |Omega|
+
+
+def test_two_ball_union_closed_forms():
+    c1, c2, r1, r2 = np.array([-0.19, 0.04, 0.02]), np.array([0.25, -0.09, -0.05]), 0.46, 0.37
+    Vx, Sx = _two_balls(r1, r2, float(np.linalg.norm(c1 - c2)))
+    V, S, XN = _integrate_union([sphere(c1, r1), sphere(c2, r2)], 3, 4)
+    assert abs(V / Vx - 1) < 1e-6
+    assert abs(S / Sx - 1) < 2e-3
+    assert abs(XN / (3 * V) - 1) < 1e-3
+
+
+def test_union_of_disjoint_shapes_is_exact():
+    """Shapes that never share a cell: every cut cell meets one surface, so the
+    union rule is the single-shape rule and the totals are sums of closed forms."""
+    sh = [sphere([-0.5, -0.45], 0.3), Shape((0.5, 0.45), (0.35, 0.25))]
+    V, S, XN = _integrate_union(sh, 2, 8)
+    assert abs(V / (math.pi * (0.09 + 0.35 * 0.25)) - 1) < 1e-13
+    perim = 2 * math.pi * 0.3 + 4 * 0.35 * ellipe(1 - (0.25 / 0.35) ** 2)
+    assert abs(S / perim - 1) < 1e-12
+
+
+def test_union_of_one_shape_is_the_single_rule():
+    sh = Shape((0.031, -0.047), (0.72, 0.51))
+    a, b = np.array([0.5, 0.0]), np.array([0.75, 0.25])
+    one = cut_cell_rule(sh, a, b, n=14, n_t=3)
+    uni = cut_cell_rule_union([sh], a, b, n=14, n_t=3)
+    for x, y in zip(one, uni):
+        assert np.array_equal(x, y)
+
+
+def test_nested_shapes_reduce_to_the_outer_one():
+    """A shape inside another adds nothing: the union is the outer disc."""
+    sh = [sphere([0.0, 0.0], 0.7), sphere([0.1, 0.05], 0.2)]
+    V, S, _ = _integrate_union(sh, 2, 8)
+    assert abs(V / (math.pi * 0.49) - 1) < 1e-13
+    assert abs(S / (2 * math.pi * 0.7) - 1) < 1e-13

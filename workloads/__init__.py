@@ -72,6 +72,29 @@ def ellipse(k: int = 2, n_levels: int = 4) -> Workload:
     return Workload(f"ellipse-Q{k}", 2, k, n_levels, centers=((0.031, -0.047),), semi=((0.72, 0.51),))
 
 
+def disc_union(k: int = 2, n_levels: int = 3) -> Workload:
+    """Two overlapping discs (union)."""
+    return Workload(f"disc-union-Q{k}", 2, k, n_levels, centers=((-0.21, 0.05), (0.27, -0.11)),
+                    semi=((0.45, 0.45), (0.38, 0.38)))
+
+
+def ball_union(k: int = 2, n_levels: int = 3) -> Workload:
+    """Two overlapping balls (union)."""
+    return Workload(f"ball-union-Q{k}", 3, k, n_levels, centers=((-0.19, 0.04, 0.02), (0.25, -0.09, -0.05)),
+                    semi=((0.46, 0.46, 0.46), (0.37, 0.37, 0.37)))
+
+
+def sphere_union_8(k: int = 3, n_levels: int = 5, seed: int = 0) -> Workload:
+    """Union of 8 spheres in [-1, 1]^3 with centres uniform in [-0.6, 0.6]^3 and radii
+    uniform in [0.15, 0.35], both drawn from default_rng(seed) (centres first)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-0.6, 0.6, (8, 3))
+    radii = rng.uniform(0.15, 0.35, 8)
+    return Workload(f"sphere-union8-s{seed}-Q{k}", 3, k, n_levels,
+                    centers=tuple(tuple(float(v) for v in c) for c in centres),
+                    semi=tuple((float(r),) * 3 for r in radii))
+
+
 def random_vector(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     """Seeded standard-normal test vector(s), float64, shape (n,) or (nrhs, n)."""
     rng = np.random.default_rng(seed)
@@ -94,3 +117,47 @@ def fourier_modes(dim: int, seed: int, n_modes: int = 16):
     amp = rng.standard_normal(n_modes) / (1.0 + np.sum(kappa.astype(np.float64) ** 2, axis=1))
     theta = rng.uniform(0.0, 2.0 * np.pi, n_modes)
     return kappa, amp, theta
+
+
+def serving_stream(n_requests: int, seed: int = 0, pool: int = 32, zipf_a: float = 1.1,
+                   fine_cells=(32, 64, 128), degrees=(1, 2, 3), dims=(2, 3), max_dofs: int = None,
+                   max_shapes: int = 4):
+    """Seeded request stream for the solve server.
+
+    A pool of `pool` geometries is drawn first: dimension d, a union of m shapes
+    with m uniform in 1..max_shapes, each a sphere or an axis-aligned ellipsoid
+    (probability 1/2 each) with centre in U[-0.5, 0.5]^d and radius / semi-axes
+    in U[0.2, 0.5] (m = 1) or U[0.15, 0.4] (m > 1), degree k, fine mesh N_L
+    with levels = log2(N_L / 4) + 1.  Each request picks a pool entry with
+    Zipf(zipf_a) popularity and its own random Fourier right-hand side (seed
+    1000 + request index).  Returns a list of (workload, (kappa, amp, theta))
+    pairs.  max_dofs drops pool entries whose background lattice exceeds it
+    (bounded runs)."""
+    rng = np.random.default_rng(seed)
+    entries = []
+    while len(entries) < pool:
+        d = int(rng.choice(dims))
+        k = int(rng.choice(degrees))
+        NL = int(rng.choice(fine_cells))
+        m = int(rng.integers(1, max_shapes + 1))
+        lo, hi = (0.2, 0.5) if m == 1 else (0.15, 0.4)
+        centers, semi = [], []
+        for _ in range(m):
+            centers.append(tuple(float(v) for v in rng.uniform(-0.5, 0.5, d)))
+            if rng.random() < 0.5:
+                semi.append((float(rng.uniform(lo, hi)),) * d)
+            else:
+                semi.append(tuple(float(v) for v in rng.uniform(lo, hi, d)))
+        if max_dofs is not None and (k * NL + 1) ** d > max_dofs:
+            continue
+        levels = int(np.log2(NL // 4)) + 1
+        entries.append(Workload(f"pool{len(entries)}-d{d}-m{m}-Q{k}-N{NL}", d, k, levels, centers=tuple(centers),
+                                semi=tuple(semi), rhs="fourier"))
+    ranks = np.arange(1, pool + 1, dtype=np.float64)
+    prob = ranks ** (-zipf_a)
+    prob /= prob.sum()
+    out = []
+    for i in range(n_requests):
+        w = entries[int(rng.choice(pool, p=prob))]
+        out.append((w, fourier_modes(w.dim, 1000 + i)))
+    return out
