@@ -36,6 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DOMAINS = {"ball": "ball |x|<0.7", "disc": "disc |x|<0.7",
+           "union8": "union of 8 spheres (centres U[-0.6,0.6]^3, radii U[0.15,0.35], seed 0)"}
 METRIC = "V-cycle DoFs/s FP64 vs FP32-precond at 1e-8 rel residual; p50/p99 solve latency"
 
 
@@ -44,10 +46,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ball", choices=["ball", "disc"])
+    ap.add_argument("--workload", default="ball", choices=["ball", "disc", "union8"],
+                    help="ball: |x|<0.7, Q2, 128^3; disc: |x|<0.7, Q2, 32^2; union8: 8 seeded spheres, Q3, 64^3")
     ap.add_argument("--levels", type=int, default=None, help="override the level count (smaller runs)")
     ap.add_argument("--kernel", default="cut_solve", choices=["cut_solve", "interior_step", "apply"],
                     help="kernel kind whose roofline is reported")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides per solve (up to 8): seeded Fourier loads, one multi-column PCG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
@@ -67,15 +72,11 @@ def serve(args):
     First all requests at once (saturation throughput), then the same stream
     with Poisson arrivals at `rate` x that throughput."""
     import workloads as W
-    from paper_2508_11608_amd import Problem, Server
+    from paper_2508_11608_amd import Server
 
     reqs = W.serving_stream(args.serve, seed=0, pool=16, max_dofs=20_000_000)
-    sizes = {}
-    for w, _ in reqs:
-        if w.name not in sizes:
-            sizes[w.name] = Problem(w, device=False).ndofs()
 
-    def run(arrivals):
+    def run(arrivals, tag):
         srv = Server(96 << 30, args.slots)
         t0 = time.perf_counter()
         pending = {}
@@ -92,17 +93,19 @@ def serve(args):
                 if r is not None:
                     k, w, ts = pending.pop(t)
                     out.append((k, w, ts, time.perf_counter() - t0, r[0]))
+                    print(f"[serve {tag}] {len(out)}/{len(reqs)} request {k} {w.name}: status {r[0]['status']}, "
+                          f"{r[0]['iterations']} its, {out[-1][3] - ts:.3f} s", file=sys.stderr, flush=True)
             time.sleep(0.0005)
         wall = time.perf_counter() - t0
         srv.close()
         return out, wall
 
-    out, wall = run([0.0] * len(reqs))
+    out, wall = run([0.0] * len(reqs), "saturation")
     sat_rate = len(reqs) / wall
     rng = np.random.default_rng(1)
     arr = np.cumsum(rng.exponential(1.0 / (args.rate * sat_rate), len(reqs)))
     arr -= arr[0]
-    out, wall = run(list(arr))
+    out, wall = run(list(arr), "poisson")
     lat = np.array([done - ts for _, _, ts, done, _ in out])
     solve = np.array([r["t_done"] - r["t_solve_start"] for *_, r in out])
     cold = np.array([not r["cache_hit"] for *_, r in out])
@@ -129,10 +132,11 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(P, w, kind: str, s: int = 8) -> dict:
+def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1) -> dict:
     """Algorithmic HBM bytes of every launch of one kernel kind in one V-cycle,
     keyed by (level, colour) (or level for 'apply'); s = 8 B (FP64 multigrid)
-    or 4 B (FP32 multigrid), indices 4 B.
+    or 4 B (FP32 multigrid), indices 4 B.  With m columns the matrix and index
+    terms count once and the vector terms m times (shown for m = 1 below).
 
     interior_step, per patch:  s [(2k)^d + 2 (2k-1)^d] + 4
         x over the patch closure (same-coloured closures tile space with period
@@ -152,9 +156,9 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8) -> dict:
     for l in range(1, w.n_levels):
         c = P.counts(l)
         if kind == "apply":
-            out[l] = c["n_dofs"] * (4 + 3 * s) + c["cut_cells"] * nl * nl * s
+            out[l] = c["n_dofs"] * (4 + 3 * s * m) + c["cut_cells"] * nl * nl * s
             if l == w.n_levels - 1:  # the CG product A p on the finest level (no b)
-                out["cg"] = c["n_dofs"] * (4 + 2 * 8) + c["cut_cells"] * nl * nl * 8
+                out["cg"] = c["n_dofs"] * (4 + 2 * 8 * m) + c["cut_cells"] * nl * nl * 8
             continue
         N = P.export(l, 2, np.uint8)  # cell flags, x fastest
         Nc = round(len(N) ** (1.0 / d))
@@ -164,7 +168,7 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8) -> dict:
             if kind == "interior_step":
                 nv = len(P.export(l, 16 + col, np.int32))
                 if nv:
-                    out[(l, col)] = nv * (s * ((2 * k) ** d + 2 * (2 * k - 1) ** d) + 4)
+                    out[(l, col)] = nv * (s * m * ((2 * k) ** d + 2 * (2 * k - 1) ** d) + 4)
                 continue
             off = P.export(l, 24 + col, np.int32)
             verts = P.export(l, 48 + col, np.int32)
@@ -179,13 +183,14 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8) -> dict:
                 ok = np.all((ci >= 0) & (ci < Nc), axis=1)
                 idx = tuple(ci[ok][:, i] for i in reversed(range(d)))
                 ncut[ok] += cut[idx]
-            b = (s * nj ** 2 + nj * (4 + 2 * s) + 12 + s * (2 * k) ** d + s * k ** d * nl * ncut).sum()
+            b = (s * nj ** 2 + nj * (4 + 2 * s * m) + 12 + s * m * (2 * k) ** d + s * k ** d * nl * ncut).sum()
             out[(l, col)] = int(b)
     return out
 
 
-def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False) -> dict:
-    per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8)
+def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False,
+             ncol: int = 1) -> dict:
+    per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8, ncol)
     bytes_per_vcycle = sum(per_v.values())
     if kind != "apply":
         # each colour step runs twice per smoothing step for interior patches
@@ -231,6 +236,58 @@ def cpu_baseline() -> dict:
     return {"value": n * its / dt, "unit": "DoF/s", "cores": 1, "kind": "oracle",
             "sample": f"{solves} FP64 PCG solves to 1e-8 on the same ball at 32^3 cells (4 levels, {n} DoFs, "
                       f"{its // solves} iterations each), set-up excluded, {dt:.1f} s"}
+
+
+def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
+    """Multi-column variant: args.steps solves of all columns of B at once
+    (independent PCG per column sharing multi-column V-cycles).  value counts
+    DoFs x columns x V-cycle applications per second."""
+    import torch
+
+    P.set_precision(fp32)
+    n = P.ndofs()
+    nrhs = B.shape[0]
+    X = torch.empty_like(B)
+    for _ in range(args.warmup):
+        P.solve_multi(B, X, rtol=1e-8)
+    torch.cuda.synchronize()
+    P.timing([args.kernel])
+    vcyc = 0
+    lat = []
+    infos = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, infos = P.solve_multi(B, X, rtol=1e-8)
+        lat.append(time.perf_counter() - ts)
+        vcyc += max(i["iterations"] for i in infos)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms = P.timing_read(args.kernel)
+    P.timing([])
+    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs)
+    tag = "fp32" if fp32 else "fp64"
+    print(f"[bench] {tag} x{nrhs}: timed {args.steps} solves: {dt:.3f}s, {vcyc} multi V-cycles", file=sys.stderr,
+          flush=True)
+    R = torch.randn(B.shape, dtype=torch.float64, device="cuda")
+    Z = torch.empty_like(R)
+    for _ in range(2):
+        P.vcycle_multi(R, Z)
+    torch.cuda.synchronize()
+    nv = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(nv):
+        P.vcycle_multi(R, Z)
+    e1.record()
+    torch.cuda.synchronize()
+    t_v = e0.elapsed_time(e1) / 1e3 / nv
+    return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * nrhs * vcyc / dt,
+            "ms_per_step": dt / args.steps * 1e3, "iterations_per_column": [i["iterations"] for i in infos],
+            "final_rel_residual": max(i["rel_residual"] for i in infos),
+            "solve_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "solve_latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "vcycle_ms": t_v * 1e3, "vcycle_dofs_per_s": n * nrhs / t_v, "roofline": roof}
 
 
 def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
@@ -299,7 +356,7 @@ def main():
     import workloads as W
     from paper_2508_11608_amd import Problem
 
-    w = W.ball_q2() if args.workload == "ball" else W.disc_q2()
+    w = {"ball": W.ball_q2, "disc": W.disc_q2, "union8": W.sphere_union_8}[args.workload]()
     if args.levels:
         w = w.with_levels(args.levels)
     torch.cuda.set_device(0)
@@ -311,13 +368,20 @@ def main():
     b = torch.from_numpy(P.rhs_manufactured()).cuda()
     x = torch.empty_like(b)
     first = [True, False] if args.fp32 else [False, True]
-    res = {fp32: timed_solves(P, w, b, x, args, fp32) for fp32 in first}
+    if args.nrhs > 1:
+        if args.nrhs > 8:
+            raise SystemExit("at most 8 right-hand sides")
+        B = torch.from_numpy(np.stack([P.rhs_fourier(*W.fourier_modes(w.dim, seed=1000 + c))
+                                       for c in range(args.nrhs)])).cuda()
+        res = {fp32: timed_multi_solves(P, w, B, args, fp32) for fp32 in first}
+    else:
+        res = {fp32: timed_solves(P, w, b, x, args, fp32) for fp32 in first}
     head = res[first[0]]
     other = res[first[1]]
     out = {
         "metric": METRIC,
         "value": head["value"],
-        "unit": "DoF/s",
+        "unit": "DoF/s" if args.nrhs == 1 else "DoF*rhs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -327,12 +391,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 multigrid in f64 CG" if args.fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: ball |x|<0.7 in [-1,1]^3, Q2, {w.n_levels} levels to "
-                               f"{w.fine_cells}^3 cells, manufactured f, FP64 CG to 1e-8",
-                   "active_dofs": n, "n_c": w.n_c,
+        "config": {"workload": f"{w.name}: {DOMAINS[args.workload]} in [-1,1]^{w.dim}, Q{w.k}, {w.n_levels} "
+                               f"levels to {w.fine_cells}^{w.dim} cells, "
+                               + (f"{args.nrhs} seeded Fourier right-hand sides per solve (independent PCG per "
+                                  f"column, shared multi-column V-cycles)" if args.nrhs > 1 else "manufactured f")
+                               + ", FP64 CG to 1e-8",
+                   "active_dofs": n, "n_c": w.n_c, "nrhs": args.nrhs,
                    "precision": "fp32 preconditioner, fp64 CG" if args.fp32 else "fp64"},
         "roofline": head["roofline"],
-        "cg_iterations_per_solve": head["iterations_per_solve"],
+        "cg_iterations_per_solve": head.get("iterations_per_solve", head.get("iterations_per_column")),
         "final_rel_residual": head["final_rel_residual"],
         "solve_latency_ms_p50": head["solve_latency_ms_p50"],
         "solve_latency_ms_p99": head["solve_latency_ms_p99"],

@@ -141,6 +141,29 @@ cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream);
 cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
                      void* stream);
 
+/* Several right-hand sides at once (1 <= nrhs <= 8).  Column c of r, z, b and x
+ * starts at c * n_L (n_L = cmg_ndofs of the finest level), canonical order.
+ *
+ * cmg_vcycle_multi: z_c = B r_c for every column.  In FP64 the columns run
+ * through the same kernels as cmg_vcycle (one grid row per column) and the
+ * results equal nrhs single V-cycles bit for bit.  In FP32 (cmg_set_precision)
+ * the cut-patch local solves read each inverse once for all columns and apply
+ * it on the matrix cores (16x16x4 FP32 MFMA, FP32 accumulation), so the
+ * result differs from single V-cycles by rounding only.
+ *
+ * cmg_solve_multi: nrhs independent PCG recurrences (own alpha, beta and
+ * stopping test per column) that share one multi-column V-cycle and one
+ * multi-column FP64 operator product per iteration; a converged column is
+ * frozen (alpha = 0) while the others continue.  info (nrhs entries, may be
+ * NULL) holds each column's iterations and final relative residual.  Returns
+ * CMG_ENOTCONV if any column misses rtol within maxit.
+ *
+ * The first call allocates multi-column work vectors (8 columns on every
+ * level) and, in FP32, a tiled copy of the cut-patch inverses. */
+cmg_status cmg_vcycle_multi(cmg_problem* p, int nrhs, const double* r, double* z, void* stream);
+cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x, double rtol, int maxit,
+                           cmg_solve_info* info, void* stream);
+
 /* Kernel timing for measurements.  While kind_mask is non-zero, every kernel
  * launch of a kind whose bit is set is bracketed by HIP events on its stream.
  * Kinds: 0 operator apply / residual, 1 interior colour step, 2 cut colour

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cutmg.h"
@@ -52,6 +53,8 @@ struct DevLevel {
   cmg::KLevel kl64{}, kl32{};
   Vecs<double> v64;
   Vecs<float> v32;
+  Vecs<double> m64;  // multi-column work vectors (kMaxCols columns), allocated on first use
+  Vecs<float> m32;
   int32_t* int_verts[8] = {};
   int n_int[8] = {};
   cmg::CutGroupDev cut64[8] = {}, cut32[8] = {};
@@ -69,6 +72,10 @@ struct cmg_problem {
   float* coarse32 = nullptr;
   bool fp32_ready = false;
   bool fp32 = false;  // precision of the V-cycle
+  bool m64_ready = false, m32_ready = false, tiles_ready = false;
+  // multi-column Krylov vectors (kMaxCols columns of the finest level, compact)
+  double *mkr = nullptr, *mkz = nullptr, *mkp = nullptr, *mkq = nullptr, *mpart = nullptr;
+  double* mpart_host = nullptr;
   // Krylov vectors (compact, finest level)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *part = nullptr;
   double* part_host = nullptr;
@@ -99,6 +106,12 @@ template <>
 Vecs<double>& vecs<double>(DevLevel& D) { return D.v64; }
 template <>
 Vecs<float>& vecs<float>(DevLevel& D) { return D.v32; }
+template <typename T>
+Vecs<T>& mvecs(DevLevel& D);
+template <>
+Vecs<double>& mvecs<double>(DevLevel& D) { return D.m64; }
+template <>
+Vecs<float>& mvecs<float>(DevLevel& D) { return D.m32; }
 template <typename T>
 cmg::CutGroupDev& cutg(DevLevel& D, int c);
 template <>
@@ -158,6 +171,7 @@ cmg_status upload_all(cmg_problem* P) {
     k.N = h.N;
     k.nn = h.nn;
     k.n_dofs = h.n_dofs;
+    k.n_nodes = h.n_nodes;
     uint8_t *flags, *ghost;
     int32_t *cut_id, *dn;
     double *cm, *tab;
@@ -264,6 +278,78 @@ cmg_status ensure_fp32(cmg_problem* P) {
   return CMG_OK;
 }
 
+// Multi-column work vectors of precision T on every level (kMaxCols columns),
+// and the multi-column Krylov vectors, on first use.
+template <typename T>
+cmg_status ensure_multi(cmg_problem* P) {
+  bool& ready = std::is_same<T, float>::value ? P->m32_ready : P->m64_ready;
+  if (ready) return CMG_OK;
+  if (std::is_same<T, float>::value) TRY(ensure_fp32(P));
+  auto& own = P->owned;
+  const size_t C = cmg::kMaxCols;
+  for (size_t l = 0; l < P->lv.size(); ++l) {
+    const cmg::HostLevel& h = P->H.levels[l];
+    DevLevel& d = P->lv[l];
+    Vecs<T>& v = mvecs<T>(d);
+    TRY(alloc_zero(own, C * h.n_nodes, &v.x));
+    TRY(alloc_zero(own, C * h.n_nodes, &v.b));
+    TRY(alloc_zero(own, C * h.n_nodes, &v.r));
+    TRY(alloc_zero(own, C * d.n_w, &v.W));
+    TRY(alloc_zero(own, C * static_cast<size_t>(d.max_cut_nodes), &v.dbuf));
+  }
+  if (!P->mkr) {
+    const size_t n = static_cast<size_t>(P->H.levels.back().n_dofs);
+    for (double** v : {&P->mkr, &P->mkz, &P->mkp, &P->mkq}) TRY(alloc_zero(own, C * n, v));
+    TRY(alloc_zero(own, C * static_cast<size_t>(P->nblk), &P->mpart));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->mpart_host), C * P->nblk * sizeof(double),
+                          hipHostMallocDefault));
+  }
+  ready = true;
+  return CMG_OK;
+}
+
+// FP32 cut-patch inverses in the tile order of the matrix-core local solve:
+// per patch, row blocks of 16 x column blocks of 4, each tile 64 floats with
+// lane l = row l%16 + 16 * column l/16, zero beyond the patch size.
+cmg_status ensure_tiles(cmg_problem* P) {
+  if (P->tiles_ready) return CMG_OK;
+  TRY(ensure_fp32(P));
+  auto& own = P->owned;
+  for (size_t l = 0; l < P->lv.size(); ++l) {
+    for (int c = 0; c < 8; ++c) {
+      const cmg::CutPatchGroup& g = P->H.levels[l].cut[c];
+      cmg::CutGroupDev& G = P->lv[l].cut32[c];
+      if (G.n_patch == 0) continue;
+      std::vector<int64_t> toff(G.n_patch + 1, 0);
+      for (int p = 0; p < G.n_patch; ++p) {
+        const int64_t nj = g.off[p + 1] - g.off[p];
+        toff[p + 1] = toff[p] + ((nj + 15) / 16) * ((nj + 3) / 4) * 64;
+      }
+      std::vector<float> tiles(static_cast<size_t>(toff[G.n_patch]), 0.f);
+      for (int p = 0; p < G.n_patch; ++p) {
+        const int nj = g.off[p + 1] - g.off[p];
+        const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
+        const double* inv = g.inv.data() + g.inv_off[p];
+        for (int rb = 0; rb < nrb; ++rb)
+          for (int kb = 0; kb < nkb; ++kb)
+            for (int ln = 0; ln < 64; ++ln) {
+              const int i = rb * 16 + ln % 16, j = kb * 4 + ln / 16;
+              if (i < nj && j < nj)
+                tiles[toff[p] + (static_cast<int64_t>(rb) * nkb + kb) * 64 + ln] = static_cast<float>(inv[i * nj + j]);
+            }
+      }
+      float* dt;
+      int64_t* doff;
+      TRY(upload(own, tiles, &dt));
+      TRY(upload(own, toff, &doff));
+      G.inv_tiles = dt;
+      G.tile_off = doff;
+    }
+  }
+  P->tiles_ready = true;
+  return CMG_OK;
+}
+
 cmg_status check_device(const cmg_problem* p) {
   if (!p) return fail(CMG_EINVAL, "null problem");
   if (p->lv.empty()) return fail(CMG_EINVAL, "problem was set up on the host only");
@@ -313,110 +399,129 @@ enum KernelKind {
 };
 
 // ---- device-side building blocks on the internal lattice vectors ------------
+// ncol = 1: the single-column work vectors; ncol > 1: the first ncol columns of
+// the multi-column work vectors (kMaxCols columns, n_nodes apart).
 
 template <typename T>
-cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s) {
+Vecs<T>& work(DevLevel& D, int ncol) {
+  return ncol > 1 ? mvecs<T>(D) : vecs<T>(D);
+}
+
+template <typename T>
+cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s, int ncol = 1) {
   const int d = P->H.cfg.dim, k = P->H.cfg.k;
   DevLevel& D = P->lv[l];
-  Vecs<T>& v = vecs<T>(D);
+  Vecs<T>& v = work<T>(D, ncol);
   if (interior) {
     if (D.n_int[colour] == 0) return CMG_OK;
     KTimer t(P, kInterior, l, s);
-    HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s));
+    HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s, ncol));
     return CMG_OK;
   }
   const cmg::CutGroupDev& G = cutg<T>(D, colour);
   if (G.n_patch == 0) return CMG_OK;
   {
     KTimer t(P, kCutSolve, l, s);
-    HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s));
+    if constexpr (std::is_same<T, float>::value) {
+      if (ncol > 1 && G.inv_tiles) {
+        HIP_TRY(cmg::launch_cut_solve_mfma(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, ncol, s));
+      } else {
+        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+      }
+    } else {
+      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+    }
   }
   KTimer t(P, kCutUpdate, l, s);
-  HIP_TRY(cmg::launch_cut_update<T>(G, v.dbuf, v.x, s));
+  HIP_TRY(cmg::launch_cut_update<T>(G, v.dbuf, v.x, D.kl64.n_nodes, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s) {
+cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s, int ncol = 1) {
   const int C = 1 << P->H.cfg.dim;
   std::vector<std::pair<bool, int>> seq;
   for (int c = 0; c < C; ++c) seq.push_back({true, c});
   for (int r = 0; r < P->H.cfg.n_c; ++r)
     for (int c = 0; c < C; ++c) seq.push_back({false, c});
   if (post) std::reverse(seq.begin(), seq.end());
-  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s));
+  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status coarse(cmg_problem* P, hipStream_t s) {
+cmg_status coarse(cmg_problem* P, hipStream_t s, int ncol = 1) {
   DevLevel& D = P->lv[0];
   KTimer t(P, kCoarse, 0, s);
-  HIP_TRY(cmg::launch_coarse<T>(coarse_inv<T>(P), D.kl64.dof_node, static_cast<int>(P->H.n_coarse), vecs<T>(D).b,
-                                vecs<T>(D).x, s));
+  HIP_TRY(cmg::launch_coarse<T>(coarse_inv<T>(P), D.kl64.dof_node, static_cast<int>(P->H.n_coarse),
+                                work<T>(D, ncol).b, work<T>(D, ncol).x, D.kl64.n_nodes, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status zero_active(cmg_problem* P, int l, T* x, hipStream_t s) {
+cmg_status zero_active(cmg_problem* P, int l, T* x, hipStream_t s, int ncol = 1) {
   KTimer t(P, kLayout, l, s);
-  HIP_TRY(cmg::launch_zero_active<T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, x, s));
+  HIP_TRY(cmg::launch_zero_active<T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, x, P->lv[l].kl64.n_nodes, s,
+                                     ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s) {
+cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s, int ncol = 1) {
   KTimer t(P, kApply, l, s);
-  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, vecs<T>(P->lv[l]).W, s));
+  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], ncol).W, s,
+                               ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status prolong_add(cmg_problem* P, int l, hipStream_t s) {
+cmg_status prolong_add(cmg_problem* P, int l, hipStream_t s, int ncol = 1) {
   KTimer t(P, kProlong, l, s);
   HIP_TRY(cmg::launch_prolong_add<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]),
-                                     vecs<T>(P->lv[l - 1]).x, vecs<T>(P->lv[l]).x, s));
+                                     work<T>(P->lv[l - 1], ncol).x, work<T>(P->lv[l], ncol).x, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status restrict_(cmg_problem* P, int l, const T* rf, hipStream_t s) {
+cmg_status restrict_(cmg_problem* P, int l, const T* rf, hipStream_t s, int ncol = 1) {
   KTimer t(P, kRestrict, l, s);
   HIP_TRY(cmg::launch_restrict<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]), rf,
-                                  vecs<T>(P->lv[l - 1]).b, s));
+                                  work<T>(P->lv[l - 1], ncol).b, s, ncol));
   return CMG_OK;
 }
 
 // V-cycle on the lattice vectors of precision T: x_L = B b_L, zero initial guess.
 template <typename T>
-cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s) {
+cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s, int ncol = 1) {
   const int L = P->H.cfg.n_levels - 1;
   for (int l = L; l >= 1; --l) {
-    Vecs<T>& v = vecs<T>(P->lv[l]);
-    TRY(zero_active<T>(P, l, v.x, s));
-    TRY(smooth<T>(P, l, false, s));
-    TRY(apply_lat<T>(P, l, v.x, v.b, v.r, s));
-    TRY(restrict_<T>(P, l, v.r, s));
+    Vecs<T>& v = work<T>(P->lv[l], ncol);
+    TRY(zero_active<T>(P, l, v.x, s, ncol));
+    TRY(smooth<T>(P, l, false, s, ncol));
+    TRY(apply_lat<T>(P, l, v.x, v.b, v.r, s, ncol));
+    TRY(restrict_<T>(P, l, v.r, s, ncol));
   }
-  TRY(coarse<T>(P, s));
+  TRY(coarse<T>(P, s, ncol));
   for (int l = 1; l <= L; ++l) {
-    TRY(prolong_add<T>(P, l, s));
-    TRY(smooth<T>(P, l, true, s));
+    TRY(prolong_add<T>(P, l, s, ncol));
+    TRY(smooth<T>(P, l, true, s, ncol));
   }
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status scatter(cmg_problem* P, int l, const double* src, T* lat, hipStream_t s) {
+cmg_status scatter(cmg_problem* P, int l, const double* src, T* lat, hipStream_t s, int ncol = 1) {
   KTimer t(P, kLayout, l, s);
-  HIP_TRY(cmg::launch_scatter<double, T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, src, lat, s));
+  HIP_TRY(cmg::launch_scatter<double, T>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, src, lat,
+                                         P->lv[l].kl64.n_nodes, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status gather(cmg_problem* P, int l, const T* lat, double* dst, hipStream_t s) {
+cmg_status gather(cmg_problem* P, int l, const T* lat, double* dst, hipStream_t s, int ncol = 1) {
   KTimer t(P, kLayout, l, s);
-  HIP_TRY(cmg::launch_gather<T, double>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, lat, dst, s));
+  HIP_TRY(cmg::launch_gather<T, double>(P->lv[l].kl64.dof_node, P->lv[l].kl64.n_dofs, lat, dst,
+                                        P->lv[l].kl64.n_nodes, s, ncol));
   return CMG_OK;
 }
 
@@ -430,6 +535,24 @@ cmg_status dot(cmg_problem* P, const double* x, const double* y, int64_t n, hipS
   double acc = 0.0;
   for (int i = 0; i < P->nblk; ++i) acc += P->part_host[i];
   *out = acc;
+  return CMG_OK;
+}
+
+// Column-wise dot products of ncol columns of n entries (multi-column buffers).
+cmg_status dot_cols(cmg_problem* P, const double* x, const double* y, int64_t n, int ncol, hipStream_t s,
+                    double* out) {
+  {
+    KTimer t(P, kVector, P->H.cfg.n_levels - 1, s);
+    HIP_TRY(cmg::launch_dot_partial(x, y, n, P->mpart, P->nblk, s, ncol));
+  }
+  HIP_TRY(hipMemcpyAsync(P->mpart_host, P->mpart, static_cast<size_t>(ncol) * P->nblk * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < ncol; ++c) {
+    double acc = 0.0;
+    for (int i = 0; i < P->nblk; ++i) acc += P->mpart_host[c * P->nblk + i];
+    out[c] = acc;
+  }
   return CMG_OK;
 }
 
@@ -496,6 +619,38 @@ cmg_status op_vcycle(cmg_problem* p, const double* r, double* z, hipStream_t s) 
 
 cmg_status vcycle_current(cmg_problem* p, const double* r, double* z, hipStream_t s) {
   return p->fp32 ? op_vcycle<float>(p, r, z, s) : op_vcycle<double>(p, r, z, s);
+}
+
+// ncol columns: z = B r with the multi-column work vectors (prepared by the caller).
+template <typename T>
+cmg_status op_vcycle_multi(cmg_problem* p, int ncol, const double* r, double* z, hipStream_t s) {
+  const int L = p->H.cfg.n_levels - 1;
+  Vecs<T>& v = work<T>(p->lv[L], ncol);
+  TRY(scatter<T>(p, L, r, v.b, s, ncol));
+  TRY(vcycle_lattice<T>(p, s, ncol));
+  return gather<T>(p, L, v.x, z, s, ncol);
+}
+
+cmg_status vcycle_multi_current(cmg_problem* p, int ncol, const double* r, double* z, hipStream_t s) {
+  return p->fp32 ? op_vcycle_multi<float>(p, ncol, r, z, s) : op_vcycle_multi<double>(p, ncol, r, z, s);
+}
+
+// ncol columns: y = A x in FP64 on the finest level.
+cmg_status op_apply_multi(cmg_problem* p, int ncol, const double* x, double* y, hipStream_t s) {
+  const int L = p->H.cfg.n_levels - 1;
+  Vecs<double>& v = work<double>(p->lv[L], ncol);
+  TRY(scatter<double>(p, L, x, v.x, s, ncol));
+  TRY(apply_lat<double>(p, L, v.x, nullptr, v.r, s, ncol));
+  return gather<double>(p, L, v.r, y, s, ncol);
+}
+
+cmg_status prepare_multi(cmg_problem* p) {
+  TRY(ensure_multi<double>(p));
+  if (p->fp32) {
+    TRY(ensure_multi<float>(p));
+    TRY(ensure_tiles(p));
+  }
+  return CMG_OK;
 }
 
 }  // namespace
@@ -584,6 +739,7 @@ void cmg_destroy(cmg_problem* p) {
   if (!p->lv.empty()) (void)hipDeviceSynchronize();
   for (void* v : p->owned) (void)hipFree(v);
   if (p->part_host) (void)hipHostFree(p->part_host);
+  if (p->mpart_host) (void)hipHostFree(p->mpart_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -741,6 +897,91 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
     rz = rz_new;
   }
   return fail(CMG_ENOTCONV, "CG did not converge within maxit");
+}
+
+cmg_status cmg_vcycle_multi(cmg_problem* p, int nrhs, const double* r, double* z, void* stream) {
+  TRY(check_device(p));
+  if (!r || !z || nrhs < 1 || nrhs > cmg::kMaxCols) return fail(CMG_EINVAL, "bad multi-column V-cycle arguments");
+  TRY(prepare_multi(p));
+  return vcycle_multi_current(p, nrhs, r, z, static_cast<hipStream_t>(stream));
+}
+
+cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x, double rtol, int maxit,
+                           cmg_solve_info* info, void* stream) {
+  TRY(check_device(p));
+  if (!b || !x || !(rtol > 0.0) || maxit < 1 || nrhs < 1 || nrhs > cmg::kMaxCols)
+    return fail(CMG_EINVAL, "bad multi-column solve arguments");
+  TRY(prepare_multi(p));
+  auto s = static_cast<hipStream_t>(stream);
+  const int L = p->H.cfg.n_levels - 1;
+  const int64_t n = p->H.levels[L].n_dofs;
+  const int64_t nt = n * nrhs;
+  if (info)
+    for (int c = 0; c < nrhs; ++c) info[c] = cmg_solve_info{0, 0.0, 0.0};
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_fill(nt, 0.0, x, s));       // x = 0
+    HIP_TRY(cmg::launch_copy(nt, b, p->mkr, s));    // r = b
+  }
+  double nb[cmg::kMaxCols], rz[cmg::kMaxCols], tmp[cmg::kMaxCols];
+  bool done[cmg::kMaxCols];
+  TRY(dot_cols(p, b, b, n, nrhs, s, tmp));
+  bool all_done = true;
+  for (int c = 0; c < nrhs; ++c) {
+    nb[c] = std::sqrt(tmp[c]);
+    if (!std::isfinite(nb[c])) return fail(CMG_EINVAL, "right-hand side is not finite");
+    done[c] = nb[c] == 0.0;
+    all_done = all_done && done[c];
+  }
+  if (all_done) return CMG_OK;
+  TRY(vcycle_multi_current(p, nrhs, p->mkr, p->mkz, s));
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_copy(nt, p->mkz, p->mkp, s));  // p = z
+  }
+  TRY(dot_cols(p, p->mkr, p->mkz, n, nrhs, s, rz));
+  for (int it = 1; it <= maxit; ++it) {
+    TRY(op_apply_multi(p, nrhs, p->mkp, p->mkq, s));  // q = A p in FP64
+    TRY(dot_cols(p, p->mkp, p->mkq, n, nrhs, s, tmp));
+    cmg::ColCoef alpha{}, malpha{};
+    for (int c = 0; c < nrhs; ++c) {
+      if (done[c]) continue;  // a converged column keeps x and r (alpha = 0)
+      if (!(tmp[c] > 0.0) || !std::isfinite(tmp[c])) return fail(CMG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+      alpha.v[c] = rz[c] / tmp[c];
+      malpha.v[c] = -alpha.v[c];
+    }
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_axpy_cols(n, alpha, p->mkp, x, nrhs, s));
+      HIP_TRY(cmg::launch_axpy_cols(n, malpha, p->mkq, p->mkr, nrhs, s));
+    }
+    TRY(dot_cols(p, p->mkr, p->mkr, n, nrhs, s, tmp));
+    all_done = true;
+    for (int c = 0; c < nrhs; ++c) {
+      if (done[c]) continue;
+      const double rel = std::sqrt(tmp[c]) / nb[c];
+      if (info) {
+        info[c].iterations = it;
+        info[c].rel_residual = rel;
+        info[c].n_frac = rel > 0.0 ? it * std::log10(rtol) / std::log10(rel) : it;
+      }
+      done[c] = rel <= rtol;
+      all_done = all_done && done[c];
+    }
+    if (all_done) return CMG_OK;
+    TRY(vcycle_multi_current(p, nrhs, p->mkr, p->mkz, s));
+    TRY(dot_cols(p, p->mkr, p->mkz, n, nrhs, s, tmp));
+    cmg::ColCoef beta{};
+    for (int c = 0; c < nrhs; ++c) {
+      beta.v[c] = done[c] ? 0.0 : tmp[c] / rz[c];
+      rz[c] = tmp[c];
+    }
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_xpay_cols(n, beta, p->mkz, p->mkp, nrhs, s));
+    }
+  }
+  return fail(CMG_ENOTCONV, "CG did not converge within maxit for every column");
 }
 
 cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {

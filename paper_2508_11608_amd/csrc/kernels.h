@@ -12,6 +12,7 @@ struct KLevel {
   int N;                     // cells per direction
   int nn;                    // lattice nodes per direction, k N + 1
   int64_t n_dofs;
+  int64_t n_nodes;           // lattice nodes, nn^d (the column stride of lattice vectors)
   const uint8_t* flags;      // per cell: bit 0 active, bit 1 cut
   const int32_t* cut_id;     // per cell: index of its cut-cell matrix or -1
   const uint8_t* ghost;      // per cell: bit 2*dir+side marks a ghost face
@@ -38,41 +39,69 @@ struct CutGroupDev {
   const int32_t* nodes;      // lattice nodes of the internal DoFs
   const int32_t* vertex;     // vertex index of every patch
   const void* inv;           // symmetric dense inverses, scalar type of the path
+  const float* inv_tiles;    // FP32 inverses in MFMA tile order (see k_cut_solve_mfma), or null
+  const int64_t* tile_off;   // tile offsets, n_patch + 1, or null
   template <typename T>
   __host__ __device__ const T* inv_t() const { return static_cast<const T*>(inv); }
 };
 
+constexpr int kMaxCols = 8;  // columns (right-hand sides) of one multi-column launch
+
+// Per-column coefficients of the column-wise vector kernels.
+struct ColCoef {
+  double v[kMaxCols];
+};
+
 int tables_size(int d, int k);
 
-// y = A x (b == nullptr) or y = b - A x on every active node; W is a work
-// buffer of n_faces * k * (k+1)^(d-1) entries for the ghost-face jumps.
+// Every multigrid launcher works on ncol columns at once (blockIdx.y = column):
+// lattice vectors of a level are ncol blocks of KLevel::n_nodes entries, the
+// ghost-face work buffer ncol blocks of n_faces k (k+1)^(d-1) entries, the
+// cut-patch correction buffer ncol blocks of CutGroupDev::n_nodes entries, and
+// compact (DoF-ordered) vectors ncol blocks of n entries.
+
+// y = A x (b == nullptr) or y = b - A x on every active node; W is the work
+// buffer for the ghost-face jumps.
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s);
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s,
+                        int ncol = 1);
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
-                                hipStream_t s);
+                                hipStream_t s, int ncol = 1);
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s);
+                            hipStream_t s, int ncol = 1);
+// FP32, ncol <= kMaxCols columns, local solves on the matrix cores (needs inv_tiles).
+hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,
+                                 float* dbuf, int ncol, hipStream_t s);
 template <typename T>
-hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, hipStream_t s);
+hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, int64_t ldx, hipStream_t s, int ncol = 1);
 template <typename T>
-hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s);
+hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s,
+                              int ncol = 1);
 template <typename T>
-hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s);
+hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s,
+                           int ncol = 1);
 template <typename T>
-hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, hipStream_t s);
+hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, int64_t ld, hipStream_t s,
+                         int ncol = 1);
 template <typename T>
-hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, hipStream_t s);
+hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, int64_t ld, hipStream_t s, int ncol = 1);
 template <typename TS, typename TD>
-hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, hipStream_t s);
+hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, int64_t ld, hipStream_t s,
+                          int ncol = 1);
 template <typename TS, typename TD>
-hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, hipStream_t s);
+hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, int64_t ld, hipStream_t s,
+                         int ncol = 1);
 
 }  // namespace cmg
 
 namespace cmg {
-hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s);
+// part[c * nblk + i]: partial sums of column c (ncol columns of n entries)
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s,
+                              int ncol = 1);
+hipError_t launch_axpy_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s);
+hipError_t launch_xpay_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s);
 hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y += a x
 hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y = x + a y
 }  // namespace cmg

@@ -205,6 +205,8 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   using S = Shape<D, K>;
   constexpr int N1 = S::N1;
   constexpr int NT = Pow<N1, D - 1>::v;
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  W += blockIdx.y * L.n_faces * K * NT;
   const int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (task >= L.n_faces * K) return;
   const int64_t f = task / K;
@@ -299,6 +301,10 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   __shared__ uint8_t cfl[A::NCC];
   __shared__ int32_t ccut[A::NCC], cgid[A::NCC];
   for (int i = threadIdx.x; i < S::T_FDS; i += blockDim.x) tab[i] = L.tables[i];
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  if (b) b += blockIdx.y * L.n_nodes;
+  y += blockIdx.y * L.n_nodes;
+  W += blockIdx.y * L.n_faces * K * NT;
   const double* d0 = tab + S::T_D0;
   const double* d1 = tab + S::T_D1;
   const double* gc = tab + S::T_GC;
@@ -468,49 +474,74 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   __shared__ T xs[PPB][NC];
   __shared__ T ra[PPB][NP];
   __shared__ T rb[PPB][NP];
+  __shared__ int64_t pbase[PPB];  // lattice index of each patch's closure corner (-1: no patch)
   load_tables<D, K>(L.tables, tab, S::T_SIZE);
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  b += blockIdx.y * L.n_nodes;
   const int p = threadIdx.x / NP, i = threadIdx.x % NP;
   const int NV = L.N + 1;
+  const int64_t nn = L.nn, nn2 = nn * nn;
   const int ngroups = (nv + PPB - 1) / PPB;
-  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-  const int gp0 = grp * PPB;
-  __syncthreads();  // previous group finished with the LDS buffers
-  // stage the closures of all patches of this block
-  for (int e = threadIdx.x; e < PPB * NC; e += blockDim.x) {
-    const int pp = e / NC, q = e % NC;
-    T v = 0;
-    if (gp0 + pp < nv) {
-      int vr = verts[gp0 + pp];
-      int J[3];
-      int rq = q;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int Va = vr % NV;
-        vr /= NV;
-        J[a] = K * Va - K + rq % NC1;
-        rq /= NC1;
-      }
-      v = x[lat(D, L.nn, J)];
-    }
-    xs[pp][q] = v;
-  }
-  __syncthreads();
-  const bool active = p < PPB && gp0 + p < nv;
+  // lattice offset of the thread's internal node from the closure corner
   int pi[3] = {0, 0, 0};
-  int64_t node = 0;
-  if (active) {
-    int vr = verts[gp0 + p];
-    int J[3];
+  int64_t ioff = 0;
+  {
     int ri = i;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const int Va = vr % NV;
-      vr /= NV;
       pi[a] = ri % NP1 + 1;
       ri /= NP1;
-      J[a] = K * Va - K + pi[a];
     }
-    node = lat(D, L.nn, J);
+    ioff = pi[0] + nn * pi[1] + (D == 3 ? nn2 * pi[2] : 0);
+  }
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  const int gp0 = grp * PPB;
+  __syncthreads();  // previous group finished with the LDS buffers
+  if (threadIdx.x < PPB) {
+    int64_t base = -1;
+    if (gp0 + (int)threadIdx.x < nv) {
+      int vr = verts[gp0 + threadIdx.x];
+      int J[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        J[a] = K * (vr % NV) - K;
+        vr /= NV;
+      }
+      base = lat(D, L.nn, J);
+    }
+    pbase[threadIdx.x] = base;
+  }
+  __syncthreads();
+  // stage the closures of all patches of this block: all loads first, then the LDS stores
+  {
+    constexpr int NST = PPB * NC, NIT = (NST + 255) / 256;
+    T v[NIT];
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      v[u] = 0;
+      if (e < NST) {
+        const int pp = e / NC, q = e % NC;
+        const int64_t base = pbase[pp];
+        if (base >= 0) {
+          const int q0 = q % NC1, q1 = (q / NC1) % NC1, q2 = q / (NC1 * NC1);
+          v[u] = x[base + q0 + nn * q1 + (D == 3 ? nn2 * q2 : 0)];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < NST) xs[e / NC][e % NC] = v[u];
+    }
+  }
+  __syncthreads();
+  const bool active = p < PPB && gp0 + p < nv;
+  int64_t node = 0;
+  T bnode = 0;
+  if (active) {
+    node = pbase[p] + ioff;
+    bnode = b[node];
     // residual with the Cartesian stiffness: cells of the patch containing the node
     int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
 #pragma unroll
@@ -549,7 +580,7 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
 #pragma unroll
       for (int a = 0; a < NRW; ++a) ax += acc[a];
     }
-    ra[p][i] = b[node] - ax;
+    ra[p][i] = bnode - ax;
   }
   __syncthreads();
   // fast diagonalisation: apply S^T along every direction, scale, apply S
@@ -585,21 +616,15 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   }
 }
 
-// Cut patches, phase 1: residual on the internal nodes and dense local solve,
-// one block per patch.  The patch closure and, on every side that carries a
-// ghost face, the node slab of the neighbouring cell layer are staged in LDS
-// (an extended (4k+1)^d box with the closure at [k, 3k]^d).  The jumps
-// J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost face touching the
-// patch are computed once per face; each internal node then needs only its
-// cell rows (uncut stiffness or cut-cell matrix) and k (k+1)^{d-1} terms per
-// incident ghost face.  The local solve is a GEMV with the symmetric inverse.
+// Sizes of the cut-patch kernels (one block per patch).
 template <int D, int K>
 struct CutShape {
   static constexpr int E1 = 4 * K + 1;                    // extended box, nodes per direction
   static constexpr int NE = Pow<E1, D>::v;
   static constexpr int NF = D * 3 * (1 << (D - 1));       // faces touching a 2^d patch
   static constexpr int NT = Pow<K + 1, D - 1>::v;         // nodes of a cell face
-  static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;
+  static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;  // one thread per internal node at least
+  static_assert(Shape<D, K>::NP <= THREADS, "a cut-patch block needs a thread per internal node");
   static constexpr int NCL = Shape<D, K>::NC;             // closure nodes
   static constexpr int SLAB = K * Pow<2 * K + 1, D - 1>::v;  // nodes of one halo slab
   static constexpr int NSTG = NCL + 2 * D * SLAB;         // closure + 2d slabs
@@ -636,35 +661,34 @@ __device__ __forceinline__ int staged_coords(int e, int* q) {
   return slab;
 }
 
+// LDS of one cut-patch block.
 template <int D, int K, typename T>
-__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
-                                                                        const T* __restrict__ x,
-                                                                        const T* __restrict__ b,
-                                                                        T* __restrict__ dbuf) {
+struct CutSmem {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
-  constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NE = C::NE, NF = C::NF, NT = C::NT;
-  constexpr int NCELL = 1 << D, W1 = 2 * K + 1;
-  __shared__ double tab[S::T_D1 + K * N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
-  __shared__ T xs[NE];
-  __shared__ T Wf[NF][K][NT];
-  __shared__ T rs[S::NP];
-  __shared__ T parts[S::NP][1 << D];
-  __shared__ int8_t npi[S::NP][3];
-  __shared__ uint8_t cfl[NCELL], cgh[NCELL];
-  __shared__ int32_t ccut[NCELL];
-  __shared__ int needlo[3], needhi[3];
+  double tab[S::T_D1 + K * S::N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
+  T xs[C::NE];
+  T Wf[C::NF][K][C::NT];
+  T parts[S::NP][1 << D];
+  int8_t npi[S::NP][3];
+  uint8_t cfl[1 << D], cgh[1 << D];
+  int32_t ccut[1 << D];
+  int needlo[3], needhi[3];
+};
+
+// Patch set-up shared by the cut-patch kernels: level tables, the 2^d cells
+// around the vertex (flags, ghost bits, cut ids), the sides that need a halo
+// slab, and the patch-local coordinates of the internal nodes.  Returns the
+// lattice node of the thread's internal node (tid < nj), else -1.
+template <int D, int K, typename T>
+__device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, CutSmem<D, K, T>& sm, int* V) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1, NCELL = 1 << D;
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int gp = blockIdx.x;
-  const double* mh = tab;
-  const double* d0 = tab + (S::T_D0 - S::T_MHAT);
-  const double* d1 = tab + (S::T_D1 - S::T_MHAT);
-  const double* gc = tab + (S::T_GC - S::T_MHAT);
-  for (int i = tid; i < S::T_D1 + K * N1 + K - S::T_MHAT; i += nth) tab[i] = L.tables[S::T_MHAT + i];
+  for (int i = tid; i < S::T_D1 + K * N1 + K - S::T_MHAT; i += nth) sm.tab[i] = L.tables[S::T_MHAT + i];
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
   const int NV = L.N + 1;
-  int V[3] = {0, 0, 0};
   {
     int vr = G.vertex[gp];
 #pragma unroll
@@ -686,37 +710,86 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
       g = L.ghost[cl];
       cid = L.cut_id[cl];
     }
-    cfl[tid] = f;
-    cgh[tid] = g;
-    ccut[tid] = cid;
+    sm.cfl[tid] = f;
+    sm.cgh[tid] = g;
+    sm.ccut[tid] = cid;
   }
-  if (tid < 3) { needlo[tid] = 0; needhi[tid] = 0; }
+  if (tid < 3) { sm.needlo[tid] = 0; sm.needhi[tid] = 0; }
+  int node = -1;
+  if (tid < nj) {
+    int r = G.nodes[off + tid];
+    node = r;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      sm.npi[tid][a] = static_cast<int8_t>(r % L.nn - K * (V[a] - 1));
+      r /= L.nn;
+    }
+  }
   __syncthreads();
   if (tid < NCELL) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int o = (tid >> a) & 1;
-      if (o == 0 && (cgh[tid] & (1 << (2 * a)))) atomicOr(&needlo[a], 1);
-      if (o == 1 && (cgh[tid] & (1 << (2 * a + 1)))) atomicOr(&needhi[a], 1);
+      if (o == 0 && (sm.cgh[tid] & (1 << (2 * a)))) atomicOr(&sm.needlo[a], 1);
+      if (o == 1 && (sm.cgh[tid] & (1 << (2 * a + 1)))) atomicOr(&sm.needhi[a], 1);
     }
   }
   __syncthreads();
+  return node;
+}
+
+// (A x) at the internal node of thread tid (tid < nj; other threads return 0)
+// for the patch prepared by cut_patch_setup.  The patch closure and, on every
+// side that carries a ghost face, the node slab of the neighbouring cell layer
+// are staged in LDS (an extended (4k+1)^d box with the closure at [k, 3k]^d);
+// the jumps J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost face
+// touching the patch are contracted with the face mass once per face; each
+// (node, cell) pair then needs its cell row (uncut stiffness or cut-cell
+// matrix) and k (k+1)^{d-1} terms per incident ghost face.  Called by all
+// threads of the block (it synchronises); the LDS buffers are reused on the
+// next call.
+template <int D, int K, typename T>
+__device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const T* __restrict__ x, CutSmem<D, K, T>& sm) {
+  using S = Shape<D, K>;
+  using C = CutShape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NF = C::NF, NT = C::NT;
+  constexpr int NCELL = 1 << D;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const double* mh = sm.tab;
+  const double* d0 = sm.tab + (S::T_D0 - S::T_MHAT);
+  const double* d1 = sm.tab + (S::T_D1 - S::T_MHAT);
+  const double* gc = sm.tab + (S::T_GC - S::T_MHAT);
   // stage x: closure [K, 3K]^D, plus the slab [0, K-1] / [3K+1, 4K] along a
-  // direction when a ghost face lies on that side of the patch
-  for (int e = tid; e < C::NSTG; e += nth) {
-    int q[3];
-    const int slab = staged_coords<D, K>(e, q);
-    if (slab >= 0 && !((slab & 1) ? needhi[slab >> 1] : needlo[slab >> 1])) continue;
-    int I[3];
-    bool in = true;
+  // direction when a ghost face lies on that side of the patch (all loads of a
+  // thread are issued before its LDS stores; blockDim == THREADS)
+  {
+    constexpr int NIT = (C::NSTG + C::THREADS - 1) / C::THREADS;
+    T v[NIT];
+    int elx[NIT];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      I[a] = K * (V[a] - 2) + q[a];
-      in = in && I[a] >= 0 && I[a] < L.nn;
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + C::THREADS * u;
+      v[u] = 0;
+      elx[u] = -1;
+      if (e < C::NSTG) {
+        int q[3];
+        const int slab = staged_coords<D, K>(e, q);
+        if (slab < 0 || ((slab & 1) ? sm.needhi[slab >> 1] : sm.needlo[slab >> 1])) {
+          int I[3];
+          bool in = true;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            I[a] = K * (V[a] - 2) + q[a];
+            in = in && I[a] >= 0 && I[a] < L.nn;
+          }
+          elx[u] = q[0] + E1 * q[1] + (D == 3 ? E1 * E1 * q[2] : 0);
+          if (in) v[u] = x[lat(D, L.nn, I)];
+        }
+      }
     }
-    int el = q[0] + E1 * q[1];
-    if (D == 3) el += E1 * E1 * q[2];
-    xs[el] = in ? x[lat(D, L.nn, I)] : (T)0;
+#pragma unroll
+    for (int u = 0; u < NIT; ++u)
+      if (elx[u] >= 0) sm.xs[elx[u]] = v[u];
   }
   __syncthreads();
   // mass-contracted jumps W_m(i_t) of every ghost face touching the patch:
@@ -735,9 +808,9 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
       ++tb;
     }
     bool ghost;
-    if (plane == 0) ghost = cgh[o] & (1 << (2 * dir));               // lower face of layer 0
-    else if (plane == 1) ghost = cgh[o] & (1 << (2 * dir + 1));      // between layers 0 and 1
-    else ghost = cgh[o | (1 << dir)] & (1 << (2 * dir + 1));         // upper face of layer 1
+    if (plane == 0) ghost = sm.cgh[o] & (1 << (2 * dir));               // lower face of layer 0
+    else if (plane == 1) ghost = sm.cgh[o] & (1 << (2 * dir + 1));      // between layers 0 and 1
+    else ghost = sm.cgh[o | (1 << dir)] & (1 << (2 * dir + 1));         // upper face of layer 1
     if (!ghost) continue;
     // strides of the tangential directions and of the normal one
     constexpr int E2 = E1 * E1;
@@ -765,8 +838,8 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
       T acc0 = 0, acc1 = 0;
 #pragma unroll
       for (int bd = 0; bd <= K; ++bd) {
-        acc0 += dl[bd] * xs[el + bd * sn];
-        acc1 += du[bd] * xs[el + (bd + K) * sn];
+        acc0 += dl[bd] * sm.xs[el + bd * sn];
+        acc1 += du[bd] * sm.xs[el + (bd + K) * sn];
       }
       J[bt] = acc0 - acc1;
     }
@@ -779,7 +852,7 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
         T acc = 0;
 #pragma unroll
         for (int bt = 0; bt < N1; ++bt) acc += mm[it * N1 + bt] * J[bt];
-        Wf[f][m][it] = acc;
+        sm.Wf[f][m][it] = acc;
       }
     } else {
       // (Mhat x Mhat) J by two 1-D contractions
@@ -800,17 +873,8 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
           T acc = 0;
 #pragma unroll
           for (int b1 = 0; b1 < N1; ++b1) acc += mm[i1 * N1 + b1] * H[i0 + N1 * b1];
-          Wf[f][m][i0 + N1 * i1] = acc;
+          sm.Wf[f][m][i0 + N1 * i1] = acc;
         }
-    }
-  }
-  // patch-local coordinates (1 .. 2K-1) of the internal nodes
-  for (int i = tid; i < nj; i += nth) {
-    int r = G.nodes[off + i];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      npi[i][a] = static_cast<int8_t>(r % L.nn - K * (V[a] - 1));
-      r /= L.nn;
     }
   }
   __syncthreads();
@@ -822,11 +886,11 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
     bool contains = true;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const int pa = npi[i][a], oa = (o >> a) & 1;
+      const int pa = sm.npi[i][a], oa = (o >> a) & 1;
       il[a] = pa - K * oa;
       contains = contains && il[a] >= 0 && il[a] <= K;
     }
-    const uint8_t f = cfl[o];
+    const uint8_t f = sm.cfl[o];
     if (contains && (f & 1)) {
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
@@ -839,12 +903,12 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
 #pragma unroll
       for (int a = 0; a < NRW; ++a) acc[a] = 0;
       if (f & 2) {
-        const T* row = L.cut_mats_t<T>() + ((int64_t)ccut[o] * NL + iloc) * NL;
+        const T* row = L.cut_mats_t<T>() + ((int64_t)sm.ccut[o] * NL + iloc) * NL;
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
-          acc[b12] += row[bq] * xs[xi];
+          acc[b12] += row[bq] * sm.xs[xi];
         }
       } else {
         const double* row = L.tables + S::T_KCELL + iloc * NL;
@@ -852,12 +916,12 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
-          acc[b12] += (T)row[bq] * xs[xi];
+          acc[b12] += (T)row[bq] * sm.xs[xi];
         }
       }
 #pragma unroll
       for (int a = 0; a < NRW; ++a) part += acc[a];
-      const uint8_t g = cgh[o];
+      const uint8_t g = sm.cgh[o];
       if (g) {
 #pragma unroll
         for (int dir = 0; dir < D; ++dir)
@@ -878,40 +942,140 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
 #pragma unroll
             for (int m = 0; m < K; ++m) {
               const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
-              part += (T)sg * Wf[fi][m][it];
+              part += (T)sg * sm.Wf[fi][m][it];
             }
           }
       }
     }
-    parts[i][o] = part;
+    sm.parts[i][o] = part;
   }
   __syncthreads();
-  for (int i = tid; i < nj; i += nth) {
-    T ax = 0;
+  T ax = 0;
+  if (tid < nj) {
 #pragma unroll
-    for (int o = 0; o < NCELL; ++o) ax += parts[i][o];
-    rs[i] = b[G.nodes[off + i]] - ax;
+    for (int o = 0; o < NCELL; ++o) ax += sm.parts[tid][o];
+  }
+  __syncthreads();  // the buffers may be restaged by the next call
+  return ax;
+}
+
+// Cut patches, phase 1: residual on the internal nodes and dense local solve
+// d_j = A_j^{-1} r_j (GEMV with the symmetric inverse), one block per patch
+// and one column per blockIdx.y (columns are n_nodes apart in x and b and
+// n_nodes of the colour apart in dbuf).
+template <int D, int K, typename T>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
+                                                                        const T* __restrict__ x,
+                                                                        const T* __restrict__ b,
+                                                                        T* __restrict__ dbuf) {
+  using S = Shape<D, K>;
+  __shared__ CutSmem<D, K, T> sm;
+  __shared__ T rs[S::NP];
+  const int tid = threadIdx.x;
+  const int gp = blockIdx.x;
+  x += blockIdx.y * L.n_nodes;
+  b += blockIdx.y * L.n_nodes;
+  dbuf += blockIdx.y * G.n_nodes;
+  int V[3] = {0, 0, 0};
+  const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V);
+  const int off = G.off[gp];
+  const int nj = G.off[gp + 1] - off;
+  const T bval = node >= 0 ? b[node] : (T)0;  // fetched long before it is needed
+  const T ax = cut_patch_ax<D, K, T>(L, nj, V, x, sm);
+  if (tid < nj) rs[tid] = bval - ax;
+  __syncthreads();
+  // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric);
+  // eight independent loads in flight per step (blockDim >= NP >= nj)
+  const T* inv = G.inv_t<T>() + G.inv_off[gp];
+  if (tid < nj) {
+    const int i = tid;
+    T acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0;
+    int j = 0;
+    for (; j + 8 <= nj; j += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = inv[(int64_t)(j + u) * nj + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += v[u] * rs[j + u];
+    }
+    for (; j < nj; ++j) acc[0] += inv[(int64_t)j * nj + i] * rs[j];
+    dbuf[off + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Cut patches, phase 1 for several columns in FP32: the residuals of all
+// columns (one pass of cut_patch_ax per column), then D = A_j^{-1} R on the
+// matrix cores.  v_mfma_f32_16x16x4f32 multiplies a 16x4 tile of the inverse
+// (lane l holds row l%16, column l/16) by a 4x16 slice of R (lane l holds row
+// l/16, column l%16; columns >= kMaxCols are zero) into 16x16 accumulators
+// (lane l holds rows 4(l/16)..4(l/16)+3 of column l%16).  The inverse is
+// stored tile by tile in exactly that lane order (CutGroupDev::inv_tiles), so
+// every tile is one coalesced 256-byte wave load, and is read once for all
+// columns.  Row blocks of 16 are spread over the block's wavefronts.
+template <int D, int K>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KLevel L, CutGroupDev G,
+                                                                             const float* __restrict__ x,
+                                                                             const float* __restrict__ b,
+                                                                             float* __restrict__ dbuf, int ncol) {
+  using S = Shape<D, K>;
+  constexpr int NPK = (S::NP + 3) / 4 * 4;
+  __shared__ CutSmem<D, K, float> sm;
+  __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
+  const int tid = threadIdx.x;
+  const int gp = blockIdx.x;
+  for (int e = tid; e < NPK * kMaxCols; e += blockDim.x) (&rs[0][0])[e] = 0.f;
+  int V[3] = {0, 0, 0};
+  const int node = cut_patch_setup<D, K, float>(L, G, gp, sm, V);
+  const int off = G.off[gp];
+  const int nj = G.off[gp + 1] - off;
+  for (int c = 0; c < ncol; ++c) {
+    const float bval = node >= 0 ? b[c * L.n_nodes + node] : 0.f;
+    const float ax = cut_patch_ax<D, K, float>(L, nj, V, x + c * L.n_nodes, sm);
+    if (tid < nj) rs[tid][c] = bval - ax;
   }
   __syncthreads();
-  const T* inv = G.inv_t<T>() + G.inv_off[gp];
-  for (int i = tid; i < nj; i += nth) {
-    T a0 = 0, a1 = 0;
-    int j = 0;
-    for (; j + 1 < nj; j += 2) {
-      a0 += inv[(int64_t)j * nj + i] * rs[j];
-      a1 += inv[(int64_t)(j + 1) * nj + i] * rs[j + 1];
+  const int lane = tid % 64, wave = tid / 64, nwave = blockDim.x / 64;
+  const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
+  const int kr = lane / 16, jc = lane % 16;
+  const float* tiles = G.inv_tiles + G.tile_off[gp];
+  for (int rb = wave; rb < nrb; rb += nwave) {  // wave-uniform: every lane takes part in the MFMA
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* t = tiles + (int64_t)rb * nkb * 64 + lane;
+    int kb = 0;
+    for (; kb + 4 <= nkb; kb += 4) {
+      float a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = t[(kb + u) * 64];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bb[u] = jc < kMaxCols ? rs[(kb + u) * 4 + kr][jc] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc, 0, 0, 0);
     }
-    if (j < nj) a0 += inv[(int64_t)j * nj + i] * rs[j];
-    dbuf[off + i] = a0 + a1;
+    for (; kb < nkb; ++kb) {
+      const float a = t[kb * 64];
+      const float bb = jc < kMaxCols ? rs[kb * 4 + kr][jc] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+    }
+    if (jc < ncol) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = rb * 16 + 4 * kr + v;
+        if (i < nj) dbuf[jc * G.n_nodes + off + i] = acc[v];
+      }
+    }
   }
 }
 
 // Cut patches, phase 2: x[I_j] += d_j for all patches of the colour.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cut_update(const int32_t* __restrict__ nodes, int64_t n,
-                                                    const T* __restrict__ dbuf, T* __restrict__ x) {
+                                                    const T* __restrict__ dbuf, T* __restrict__ x, int64_t ldx) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e < n) x[nodes[e]] += dbuf[e];
+  if (e < n) x[blockIdx.y * ldx + nodes[e]] += dbuf[blockIdx.y * n + e];
 }
 
 // x_f[I] += sum_J P(I, J) x_c[J] for every active fine node (embedding).
@@ -923,6 +1087,8 @@ __global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const
   __shared__ double p1d[S::NC1 * N1];
   for (int t = threadIdx.x; t < S::NC1 * N1; t += blockDim.x) p1d[t] = Lf.tables[S::T_P1D + t];
   __syncthreads();
+  xc += blockIdx.y * Lc.n_nodes;  // column blockIdx.y
+  xf += blockIdx.y * Lf.n_nodes;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= Lf.n_dofs) return;
   const int32_t node = Lf.dof_node[i];
@@ -985,6 +1151,8 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
   __shared__ double p1d[S::NC1 * N1];
   for (int t = threadIdx.x; t < S::NC1 * N1; t += blockDim.x) p1d[t] = Lf.tables[S::T_P1D + t];
   __syncthreads();
+  rf += blockIdx.y * Lf.n_nodes;  // column blockIdx.y
+  bc += blockIdx.y * Lc.n_nodes;
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= Lc.n_dofs) return;
   const int32_t node = Lc.dof_node[j];
@@ -1034,10 +1202,12 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
 // x_0 = A_0^{-1} b_0 on the coarsest level: one 64-wide wavefront per row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const int32_t* __restrict__ dof_node,
-                                                int n0, const T* __restrict__ b, T* __restrict__ x) {
+                                                int n0, const T* __restrict__ b, T* __restrict__ x, int64_t ld) {
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (row >= n0) return;
+  b += blockIdx.y * ld;  // column blockIdx.y
+  x += blockIdx.y * ld;
   T s = 0;
   for (int j = lane; j < n0; j += 64) s += inv[(int64_t)row * n0 + j] * b[dof_node[j]];
 #pragma unroll
@@ -1046,23 +1216,24 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_zero_active(const int32_t* __restrict__ dof_node, int64_t n, T* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_zero_active(const int32_t* __restrict__ dof_node, int64_t n, T* __restrict__ x,
+                                                     int64_t ld) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[dof_node[i]] = 0;
+  if (i < n) x[blockIdx.y * ld + dof_node[i]] = 0;
 }
 
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ dof_node, int64_t n,
-                                                 const TS* __restrict__ src, TD* __restrict__ lat_dst) {
+                                                 const TS* __restrict__ src, TD* __restrict__ lat_dst, int64_t ld) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) lat_dst[dof_node[i]] = (TD)src[i];
+  if (i < n) lat_dst[blockIdx.y * ld + dof_node[i]] = (TD)src[blockIdx.y * n + i];
 }
 
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ dof_node, int64_t n,
-                                                const TS* __restrict__ lat_src, TD* __restrict__ dst) {
+                                                const TS* __restrict__ lat_src, TD* __restrict__ dst, int64_t ld) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (TD)lat_src[dof_node[i]];
+  if (i < n) dst[blockIdx.y * n + i] = (TD)lat_src[blockIdx.y * ld + dof_node[i]];
 }
 
 }  // namespace dev
@@ -1100,115 +1271,138 @@ int tables_size(int d, int k) {
 }
 
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s) {
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s, int ncol) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     if (L.n_faces > 0) {
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value)), dim3(256), 0, s,
-                         L, x, W);
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value), ncol), dim3(256), 0,
+                         s, L, x, W);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks);
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, x, b, y, W);
+    const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks / ncol + 1);
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, W);
     return hipGetLastError();
   });
 }
 
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
-                                hipStream_t s) {
+                                hipStream_t s, int ncol) {
   if (nv == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
-    const unsigned nb = std::min<unsigned>(blocks(nv, PPB), kMaxResidentBlocks);
-    hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(nb), dim3(256), 0, s, L, verts, nv, x,
-                       b);
+    const unsigned nb = std::min<unsigned>(blocks(nv, PPB), kMaxResidentBlocks / ncol + 1);
+    hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, verts, nv,
+                       x, b);
     return hipGetLastError();
   });
 }
 
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s) {
+                            hipStream_t s, int ncol) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
-    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, dbuf);
+    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G, x, b,
+                       dbuf);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,
+                                 float* dbuf, int ncol, hipStream_t s) {
+  if (G.n_patch == 0) return hipSuccess;
+  if (!G.inv_tiles || !G.tile_off || ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
+  return dispatch(d, k, [&](auto D, auto K) {
+    constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+    hipLaunchKernelGGL((dev::k_cut_solve_mfma<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, dbuf,
+                       ncol);
     return hipGetLastError();
   });
 }
 
 template <typename T>
-hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, hipStream_t s) {
+hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, int64_t ldx, hipStream_t s, int ncol) {
   if (G.n_nodes == 0) return hipSuccess;
-  hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes)), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf, x);
+  hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes), ncol), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf,
+                     x, ldx);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s) {
+hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s,
+                              int ncol) {
   return dispatch(d, k, [&](auto D, auto K) {
-    hipLaunchKernelGGL((dev::k_prolong_add<D.value, K.value, T>), dim3(blocks(Lf.n_dofs)), dim3(256), 0, s, Lc, Lf,
-                       xc, xf);
+    hipLaunchKernelGGL((dev::k_prolong_add<D.value, K.value, T>), dim3(blocks(Lf.n_dofs), ncol), dim3(256), 0, s, Lc,
+                       Lf, xc, xf);
     return hipGetLastError();
   });
 }
 
 template <typename T>
-hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s) {
+hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s,
+                           int ncol) {
   return dispatch(d, k, [&](auto D, auto K) {
-    hipLaunchKernelGGL((dev::k_restrict<D.value, K.value, T>), dim3(blocks(Lc.n_dofs)), dim3(256), 0, s, Lc, Lf,
-                       rf, bc);
+    hipLaunchKernelGGL((dev::k_restrict<D.value, K.value, T>), dim3(blocks(Lc.n_dofs), ncol), dim3(256), 0, s, Lc,
+                       Lf, rf, bc);
     return hipGetLastError();
   });
 }
 
 template <typename T>
-hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((dev::k_coarse<T>), dim3(blocks(n0, 4)), dim3(256), 0, s, inv, dof_node, n0, b, x);
+hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, int64_t ld, hipStream_t s,
+                         int ncol) {
+  hipLaunchKernelGGL((dev::k_coarse<T>), dim3(blocks(n0, 4), ncol), dim3(256), 0, s, inv, dof_node, n0, b, x, ld);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, hipStream_t s) {
+hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, int64_t ld, hipStream_t s, int ncol) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((dev::k_zero_active<T>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, x);
+  hipLaunchKernelGGL((dev::k_zero_active<T>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, x, ld);
   return hipGetLastError();
 }
 
 template <typename TS, typename TD>
-hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, hipStream_t s) {
+hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, int64_t ld, hipStream_t s,
+                          int ncol) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((dev::k_scatter<TS, TD>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, src, lat);
+  hipLaunchKernelGGL((dev::k_scatter<TS, TD>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, src, lat, ld);
   return hipGetLastError();
 }
 
 template <typename TS, typename TD>
-hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, hipStream_t s) {
+hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, int64_t ld, hipStream_t s,
+                         int ncol) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL((dev::k_gather<TS, TD>), dim3(blocks(n)), dim3(256), 0, s, dof_node, n, lat, dst);
+  hipLaunchKernelGGL((dev::k_gather<TS, TD>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, lat, dst, ld);
   return hipGetLastError();
 }
 
-#define CMG_INSTANTIATE(T)                                                                                   \
-  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t);            \
+#define CMG_INSTANTIATE(T)                                                                                      \
+  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t, int);     \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
-                                              hipStream_t);                                                        \
+                                              hipStream_t, int);                                                   \
   template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
-                                          hipStream_t);                                                            \
-  template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, hipStream_t);                         \
-  template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t);    \
-  template hipError_t launch_restrict<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t);       \
-  template hipError_t launch_coarse<T>(const T*, const int32_t*, int, const T*, T*, hipStream_t);                  \
-  template hipError_t launch_zero_active<T>(const int32_t*, int64_t, T*, hipStream_t);
-
+                                          hipStream_t, int);                                                       \
+  template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, int64_t, hipStream_t, int);          \
+  template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t,     \
+                                            int);                                                                  \
+  template hipError_t launch_restrict<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t, int); \
+  template hipError_t launch_coarse<T>(const T*, const int32_t*, int, const T*, T*, int64_t, hipStream_t, int);  \
+  template hipError_t launch_zero_active<T>(const int32_t*, int64_t, T*, int64_t, hipStream_t, int);
 CMG_INSTANTIATE(double)
 CMG_INSTANTIATE(float)
-template hipError_t launch_scatter<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
-template hipError_t launch_gather<double, double>(const int32_t*, int64_t, const double*, double*, hipStream_t);
-template hipError_t launch_scatter<double, float>(const int32_t*, int64_t, const double*, float*, hipStream_t);
-template hipError_t launch_gather<float, double>(const int32_t*, int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_scatter<double, double>(const int32_t*, int64_t, const double*, double*, int64_t,
+                                                   hipStream_t, int);
+template hipError_t launch_gather<double, double>(const int32_t*, int64_t, const double*, double*, int64_t,
+                                                  hipStream_t, int);
+template hipError_t launch_scatter<double, float>(const int32_t*, int64_t, const double*, float*, int64_t,
+                                                  hipStream_t, int);
+template hipError_t launch_gather<float, double>(const int32_t*, int64_t, const float*, double*, int64_t,
+                                                 hipStream_t, int);
 
 }  // namespace cmg
 
@@ -1221,6 +1415,9 @@ namespace dev {
 __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x, const double* __restrict__ y,
                                                      int64_t n, double* __restrict__ part) {
   __shared__ double red[4];
+  x += blockIdx.y * n;  // column blockIdx.y
+  y += blockIdx.y * n;
+  part += blockIdx.y * gridDim.x;
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     s += x[i] * y[i];
@@ -1243,10 +1440,38 @@ __global__ __launch_bounds__(256) void k_xpay(int64_t n, double a, const double*
   if (i < n) y[i] = x[i] + a * y[i];
 }
 
+// Column-wise forms: column c = blockIdx.y of n entries, coefficient a.v[c].
+__global__ __launch_bounds__(256) void k_axpy_cols(int64_t n, ColCoef a, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t o = blockIdx.y * n;
+  if (i < n) y[o + i] += a.v[blockIdx.y] * x[o + i];
+}
+
+__global__ __launch_bounds__(256) void k_xpay_cols(int64_t n, ColCoef a, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t o = blockIdx.y * n;
+  if (i < n) y[o + i] = x[o + i] + a.v[blockIdx.y] * y[o + i];
+}
+
 }  // namespace dev
 
-hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(dev::k_dot_partial, dim3(nblk), dim3(256), 0, s, x, y, n, part);
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s,
+                              int ncol) {
+  hipLaunchKernelGGL(dev::k_dot_partial, dim3(nblk, ncol), dim3(256), 0, s, x, y, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_axpy_cols, dim3((n + 255) / 256, ncol), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpay_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_xpay_cols, dim3((n + 255) / 256, ncol), dim3(256), 0, s, n, a, x, y);
   return hipGetLastError();
 }
 

@@ -765,33 +765,51 @@ void load_vector(const Hierarchy& H, const std::function<double(const double*)>&
   const int nq = cfg.quad_n;
   std::vector<double> tx(nq), tw(nq);
   gauss_legendre(nq, tx.data(), tw.data());
-  std::vector<double> loc(nl);
-  auto phi = [&](const double* xi, int a, int deriv_dir) {
-    double v = 1.0;
-    for (int j = 0, r = a; j < d; ++j) {
-      v *= H.basis.eval(r % n1, xi[j], j == deriv_dir ? 1 : 0);
-      r /= n1;
-    }
-    return v;
-  };
-  for (int64_t c = 0; c < L.n_cells; ++c) {
-    const uint8_t fl = L.cell_flags[c];
-    if (!(fl & kActive)) continue;
-    int ci[kMaxDim];
-    geo.cell_of(c, ci);
-    double lo[kMaxDim], hi[kMaxDim];
-    for (int j = 0; j < d; ++j) { lo[j] = cfg.lo + ci[j] * h; hi[j] = lo[j] + h; }
-    std::fill(loc.begin(), loc.end(), 0.0);
-    if (!(fl & kCut)) {
-      const int npts = ipow(ng, d);
-      for (int p = 0; p < npts; ++p) {
-        double xi[kMaxDim], x[kMaxDim], w = std::pow(h, d);
-        for (int j = 0, r = p; j < d; ++j) { xi[j] = gx[r % ng]; w *= gw[r % ng]; x[j] = lo[j] + h * xi[j]; r /= ng; }
-        const double fv = f(x) * w;
-        for (int a = 0; a < nl; ++a) loc[a] += fv * phi(xi, a, -1);
+  std::vector<int64_t> cells;
+  for (int64_t c = 0; c < L.n_cells; ++c)
+    if (L.cell_flags[c] & kActive) cells.push_back(c);
+  // cell vectors in parallel, then summed into b in cell order (deterministic)
+  std::vector<double> locs(cells.size() * static_cast<size_t>(nl), 0.0);
+#pragma omp parallel
+  {
+    // 1-D basis values (and derivatives) at the point, per direction
+    double e[kMaxDim][kMaxDeg + 1], de[kMaxDim][kMaxDeg + 1];
+    auto tabulate = [&](const double* xi, bool deriv) {
+      for (int j = 0; j < d; ++j)
+        for (int i = 0; i < n1; ++i) {
+          e[j][i] = H.basis.eval(i, xi[j], 0);
+          if (deriv) de[j][i] = H.basis.eval(i, xi[j], 1);
+        }
+    };
+    auto phi = [&](int a, int deriv_dir) {
+      double v = 1.0;
+      for (int j = 0, r = a; j < d; ++j) {
+        v *= j == deriv_dir ? de[j][r % n1] : e[j][r % n1];
+        r /= n1;
       }
-    } else {
-      std::vector<Column> cols;
+      return v;
+    };
+    std::vector<Column> cols;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t ic = 0; ic < static_cast<int64_t>(cells.size()); ++ic) {
+      const int64_t c = cells[ic];
+      double* loc = locs.data() + ic * nl;
+      int ci[kMaxDim];
+      geo.cell_of(c, ci);
+      double lo[kMaxDim], hi[kMaxDim];
+      for (int j = 0; j < d; ++j) { lo[j] = cfg.lo + ci[j] * h; hi[j] = lo[j] + h; }
+      if (!(L.cell_flags[c] & kCut)) {
+        const int npts = ipow(ng, d);
+        for (int p = 0; p < npts; ++p) {
+          double xi[kMaxDim], x[kMaxDim], w = std::pow(h, d);
+          for (int j = 0, r = p; j < d; ++j) { xi[j] = gx[r % ng]; w *= gw[r % ng]; x[j] = lo[j] + h * xi[j]; r /= ng; }
+          const double fv = f(x) * w;
+          tabulate(xi, false);
+          for (int a = 0; a < nl; ++a) loc[a] += fv * phi(a, -1);
+        }
+        continue;
+      }
+      cols.clear();
       cut_columns_union(d, cfg.shapes, lo, hi, nq, nq, cfg.quad_beta, cfg.union_depth, cols);
       for (const Column& col : cols) {
         double x[kMaxDim], xi[kMaxDim];
@@ -801,25 +819,31 @@ void load_vector(const Hierarchy& H, const std::function<double(const double*)>&
             x[col.e] = col.t0 + (col.t1 - col.t0) * tx[t];
             for (int j = 0; j < d; ++j) xi[j] = (x[j] - lo[j]) / h;
             const double fv = f(x) * col.w * (col.t1 - col.t0) * tw[t];
-            for (int a = 0; a < nl; ++a) loc[a] += fv * phi(xi, a, -1);
+            tabulate(xi, false);
+            for (int a = 0; a < nl; ++a) loc[a] += fv * phi(a, -1);
           }
         }
         if (col.surf && u) {
           x[col.e] = col.ts;
           for (int j = 0; j < d; ++j) xi[j] = (x[j] - lo[j]) / h;
           const double gv = u(x) * col.sw;
+          tabulate(xi, true);
           for (int a = 0; a < nl; ++a) {
             double dn = 0.0;
-            for (int j = 0; j < d; ++j) dn += col.nrm[j] * phi(xi, a, j) / h;
-            loc[a] += gv * (cfg.gamma_D / h * phi(xi, a, -1) - dn);
+            for (int j = 0; j < d; ++j) dn += col.nrm[j] * phi(a, j) / h;
+            loc[a] += gv * (cfg.gamma_D / h * phi(a, -1) - dn);
           }
         }
       }
     }
+  }
+  for (size_t ic = 0; ic < cells.size(); ++ic) {
+    int ci[kMaxDim];
+    geo.cell_of(cells[ic], ci);
     for (int a = 0; a < nl; ++a) {
       int I[kMaxDim];
       for (int j = 0, r = a; j < d; ++j) { I[j] = k * ci[j] + r % n1; r /= n1; }
-      b[L.node_dof[geo.node(I)]] += loc[a];
+      b[L.node_dof[geo.node(I)]] += locs[ic * nl + a];
     }
   }
 }

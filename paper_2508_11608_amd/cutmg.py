@@ -57,7 +57,8 @@ class Result(ctypes.Structure):
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured", "cmg_rhs_fourier",
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
-            "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy"]
+            "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
+            "cmg_vcycle_multi", "cmg_solve_multi"]
 
 _lib = None
 
@@ -84,6 +85,8 @@ def load_library():
         "cmg_coarse_solve": [P, V, V, V],
         "cmg_vcycle": [P, V, V, V],
         "cmg_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
+        "cmg_vcycle_multi": [P, I, V, V, V],
+        "cmg_solve_multi": [P, I, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_rhs_manufactured": [P, ctypes.POINTER(ctypes.c_double)],
         "cmg_rhs_fourier": [P, I, V, V, V, ctypes.POINTER(ctypes.c_double)],
         "cmg_export": [P, I, I, V, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
@@ -232,6 +235,32 @@ class Problem:
             _check(st)
         return x, {"iterations": info.iterations, "rel_residual": info.rel_residual, "n_frac": info.n_frac,
                    "status": st}
+
+    def vcycle_multi(self, r, z=None):
+        """z[c] = B r[c] for the rows c of r (shape (nrhs, n), nrhs <= 8)."""
+        import torch
+
+        nrhs, n = r.shape
+        if n != self.ndofs(None):
+            raise ValueError("columns must have the finest level's length")
+        z = torch.empty_like(r) if z is None else z
+        _check(_lib.cmg_vcycle_multi(self._h, nrhs, _dev(r, nrhs * n), _dev(z, nrhs * n), _stream()))
+        return z
+
+    def solve_multi(self, b, x=None, rtol=1e-8, maxit=200, raise_on_fail=True):
+        """PCG for every row of b (shape (nrhs, n)); returns x and one info dict per row."""
+        import torch
+
+        nrhs, n = b.shape
+        if n != self.ndofs(None):
+            raise ValueError("columns must have the finest level's length")
+        x = torch.empty_like(b) if x is None else x
+        info = (SolveInfo * nrhs)()
+        st = _lib.cmg_solve_multi(self._h, nrhs, _dev(b, nrhs * n), _dev(x, nrhs * n), rtol, maxit, info, _stream())
+        if raise_on_fail:
+            _check(st)
+        return x, [{"iterations": i.iterations, "rel_residual": i.rel_residual, "n_frac": i.n_frac, "status": st}
+                   for i in info]
 
     def rhs_manufactured(self) -> np.ndarray:
         b = np.empty(self.ndofs(None), dtype=np.float64)

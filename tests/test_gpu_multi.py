@@ -1,0 +1,140 @@
+"""Several right-hand sides at once (cmg_vcycle_multi / cmg_solve_multi) through
+the C ABI: FP64 columns equal single-column runs bit for bit; FP32 columns (cut
+local solves on the matrix cores) match the float32 oracle V-cycle per column;
+the multi-column PCG keeps every column's iteration count.
+
+Every case prints its name first so that a failing GPU run can be located."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+try:  # import at collection time: the first import on a fresh machine is slow
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+CASES = [W.disc_q2(), W.offcentre_ball(3, 2), W.ball_union(2, 3)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda w: w.name)
+def case(request):
+    import torch
+    from oracle import problem as OP
+    from oracle.multigrid import Hierarchy
+    from paper_2508_11608_amd import Problem
+
+    w = request.param
+    print(f"\n[case] {w.name} dim={w.dim} k={w.k} levels={w.n_levels} (multi-column)", flush=True)
+    P = Problem(w)
+    levels, mats, prols, H = OP.build(w)
+    H32 = Hierarchy(levels, mats, prols, n_c=w.n_c, dtype=np.float32)
+    yield w, P, levels, mats, H, H32
+    P.close()
+    torch.cuda.synchronize()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _cols(n, nrhs, seed):
+    return np.stack([W.random_vector(n, seed=seed + c) for c in range(nrhs)])
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_fp64_columns_equal_single_vcycles(case, nrhs):
+    import torch
+
+    w, P, levels, *_ = case
+    P.set_precision(False)
+    r = torch.from_numpy(_cols(levels[-1].n_dofs, nrhs, 100)).cuda()
+    z = P.vcycle_multi(r)
+    for c in range(nrhs):
+        zc = P.vcycle(r[c].contiguous())
+        assert torch.equal(z[c], zc), c
+
+
+@pytest.mark.parametrize("nrhs", [2, 8])
+def test_fp32_columns_match_oracle(case, nrhs):
+    """Matrix-core local solves: each column against the float32 oracle, with the
+    FP32 tolerance of the single-column tests (10x the oracle's own
+    float32-vs-float64 deviation + 1e-6), and no less accurate than the
+    single-column FP32 V-cycle by more than a factor 2."""
+    import torch
+
+    w, P, levels, mats, H, H32 = case
+    n = levels[-1].n_dofs
+    rs = _cols(n, nrhs, 200)
+    P.set_precision(True)
+    try:
+        z = P.vcycle_multi(torch.from_numpy(rs).cuda()).cpu().numpy()
+        single = [P.vcycle(torch.from_numpy(rs[c]).cuda()).cpu().numpy() for c in range(nrhs)]
+    finally:
+        P.set_precision(False)
+    for c in range(nrhs):
+        z64 = H.vcycle(rs[c])
+        z32 = H32.vcycle(rs[c]).astype(np.float64)
+        tol = 10.0 * _rel(z32, z64) + 1e-6
+        print(f"  column {c}: multi vs oracle32 {_rel(z[c], z32):.2e}, single vs oracle32 {_rel(single[c], z32):.2e},"
+              f" multi vs fp64 {_rel(z[c], z64):.2e}, single vs fp64 {_rel(single[c], z64):.2e}")
+        assert _rel(z[c], z32) < tol
+        assert _rel(z[c], z64) <= 2.0 * _rel(single[c], z64) + 1e-7
+
+
+def test_fp64_multi_solve_equals_single_solves(case):
+    import torch
+
+    w, P, levels, *_ = case
+    P.set_precision(False)
+    n = levels[-1].n_dofs
+    kap = [W.fourier_modes(w.dim, seed=1000 + c) for c in range(3)]
+    B = np.stack([P.rhs_manufactured()] + [P.rhs_fourier(*m) for m in kap[:2]] + [np.zeros(n)])
+    X, infos = P.solve_multi(torch.from_numpy(B).cuda(), rtol=1e-8, maxit=300)
+    assert infos[3]["iterations"] == 0  # zero right-hand side: x = 0 without iterating
+    assert not X[3].any()
+    for c in range(3):
+        xc, info = P.solve(torch.from_numpy(B[c]).cuda(), rtol=1e-8, maxit=300)
+        assert infos[c]["iterations"] == info["iterations"], c
+        assert torch.equal(X[c], xc), c
+
+
+def test_fp32_multi_solve(case):
+    """Eight Fourier right-hand sides, FP32 multigrid with matrix-core local
+    solves inside FP64 CG: every column converges to 1e-8 within one
+    iteration of its single-column FP32 solve, close to the FP64 solution."""
+    import torch
+
+    w, P, levels, *_ = case
+    B = np.stack([P.rhs_fourier(*W.fourier_modes(w.dim, seed=1000 + c)) for c in range(8)])
+    Bg = torch.from_numpy(B).cuda()
+    P.set_precision(False)
+    X64, _ = P.solve_multi(Bg, rtol=1e-10, maxit=300)
+    P.set_precision(True)
+    try:
+        X, infos = P.solve_multi(Bg, rtol=1e-8, maxit=300)
+        for c in range(8):
+            _, info = P.solve(Bg[c].contiguous(), rtol=1e-8, maxit=300)
+            err = _rel(X[c].cpu().numpy(), X64[c].cpu().numpy())
+            print(f"  column {c}: {infos[c]['iterations']} its (single {info['iterations']}), "
+                  f"rel residual {infos[c]['rel_residual']:.2e}, error vs FP64 solution {err:.2e}")
+            assert abs(infos[c]["iterations"] - info["iterations"]) <= 1
+            assert infos[c]["rel_residual"] <= 1e-8
+            assert err < 1e-6
+    finally:
+        P.set_precision(False)
+
+
+def test_bad_column_counts_are_rejected(case):
+    import torch
+
+    from paper_2508_11608_amd.cutmg import CutmgError
+
+    w, P, levels, *_ = case
+    n = levels[-1].n_dofs
+    with pytest.raises(CutmgError):
+        P.vcycle_multi(torch.zeros((9, n), dtype=torch.float64, device="cuda"))
+    with pytest.raises(CutmgError):
+        P.solve_multi(torch.zeros((9, n), dtype=torch.float64, device="cuda"))

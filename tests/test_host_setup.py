@@ -143,3 +143,19 @@ def test_fourier_rhs(pair):
     b = P.rhs_fourier(kappa, amp, theta)
     ref = OP.rhs_fourier(w, levels[-1], kappa, amp, theta)
     assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_device_entry_points_reject_a_host_only_problem():
+    """Argument and state checks run before any device work, so they can be
+    exercised without a GPU: a host-only problem and bad column counts are
+    refused with CMG_EINVAL."""
+    from paper_2508_11608_amd import Problem
+    from paper_2508_11608_amd import cutmg
+
+    P = Problem(W.disc_q2(), device=False)
+    lib = cutmg.load_library()
+    info = (cutmg.SolveInfo * 9)()
+    for nrhs in (0, 1, 9):
+        assert lib.cmg_vcycle_multi(P._h, nrhs, None, None, None) == -1
+        assert lib.cmg_solve_multi(P._h, nrhs, None, None, 1e-8, 10, info, None) == -1
+    assert lib.cmg_vcycle(P._h, None, None, None) == -1
