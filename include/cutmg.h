@@ -93,9 +93,11 @@ cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_pro
  * (no-op for a device problem).  Synchronous. */
 cmg_status cmg_upload(cmg_problem* p);
 
-/* Device memory in bytes that the problem occupies once uploaded (fp32 = 1:
- * including the FP32 copies of the mixed-precision V-cycle). */
-cmg_status cmg_device_bytes(const cmg_problem* p, int fp32, size_t* bytes);
+/* Device memory in bytes that the problem occupies once uploaded.  flags bit 0:
+ * include the FP32 copies of the mixed-precision V-cycle; bit 1: include the
+ * buffers of the multi-column calls (8 columns of work vectors on every level,
+ * the multi-column Krylov vectors and, with bit 0, the tiled FP32 inverses). */
+cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes);
 
 /* Precision of the multigrid part: fp32 = 0 runs every V-cycle kernel in FP64;
  * fp32 = 1 runs smoother, transfers, level residuals and the coarse solve in FP32
@@ -148,8 +150,10 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
  * through the same kernels as cmg_vcycle (one grid row per column) and the
  * results equal nrhs single V-cycles bit for bit.  In FP32 (cmg_set_precision)
  * the cut-patch local solves read each inverse once for all columns and apply
- * it on the matrix cores (16x16x4 FP32 MFMA, FP32 accumulation), so the
- * result differs from single V-cycles by rounding only.
+ * it on the matrix cores (16x16x4 FP32 MFMA, FP32 accumulation), also for
+ * nrhs = 1, so the result differs from cmg_vcycle by rounding only.  In both
+ * precisions a column's result is independent of the other columns and of
+ * nrhs, bit for bit.
  *
  * cmg_solve_multi: nrhs independent PCG recurrences (own alpha, beta and
  * stopping test per column) that share one multi-column V-cycle and one
@@ -211,13 +215,18 @@ void cmg_destroy(cmg_problem* p);
 
 /* ---- serving: continuous batching of solves on one GPU -------------------
  * A server owns max_slots worker threads, each with its own HIP stream.
- * Requests are taken in arrival order; a hierarchy with the same geometry and
- * parameters stays resident between requests (least-recently-used idle
- * hierarchies are evicted when a new one needs room), and a new hierarchy is
- * admitted to the device when its exact footprint (cmg_device_bytes) fits into
- * hbm_budget_bytes.  Solves of different slots overlap on the device; every
- * result is independent of what else runs.  Intended for callers that submit
- * many solves of differing geometries, degrees and depths. */
+ * Requests are taken in arrival order.  A free slot takes the oldest queued
+ * request together with up to 7 further queued requests of the same geometry,
+ * parameters, rtol and maxit, and solves them as one batch: one multi-column
+ * PCG (cmg_solve_multi), so the V-cycles of the batch share every kernel
+ * launch.  A hierarchy stays resident between batches (least-recently-used idle
+ * hierarchies are evicted when a new one needs room); a new hierarchy is
+ * admitted to the device when its exact footprint (cmg_device_bytes with the
+ * multi-column buffers) fits into hbm_budget_bytes.  Batches of different
+ * slots overlap on the device.  Every result is independent of what else runs
+ * and of the batch it was solved in, bit for bit (the column arithmetic of
+ * cmg_solve_multi does not depend on the other columns).  Intended for callers
+ * that submit many solves of differing geometries, degrees and depths. */
 typedef struct cmg_server cmg_server;
 
 typedef struct {
@@ -237,6 +246,7 @@ typedef struct {
   cmg_solve_info info;
   int cache_hit;           /* 1 when the hierarchy was already resident */
   double t_submit, t_start, t_admitted, t_solve_start, t_done;  /* seconds since server creation */
+  int batch;               /* number of requests solved together with this one (itself included) */
 } cmg_result;
 
 cmg_status cmg_server_create(size_t hbm_budget_bytes, int max_slots, cmg_server** out);

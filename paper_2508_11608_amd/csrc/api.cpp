@@ -399,19 +399,22 @@ enum KernelKind {
 };
 
 // ---- device-side building blocks on the internal lattice vectors ------------
-// ncol = 1: the single-column work vectors; ncol > 1: the first ncol columns of
-// the multi-column work vectors (kMaxCols columns, n_nodes apart).
+// multi = false: the single-column work vectors (ncol = 1); multi = true: the
+// first ncol columns of the multi-column work vectors (kMaxCols columns,
+// n_nodes apart), and in FP32 the matrix-core cut-patch solves, whatever ncol
+// is, so that a column's result does not depend on how many columns run with it.
 
 template <typename T>
-Vecs<T>& work(DevLevel& D, int ncol) {
-  return ncol > 1 ? mvecs<T>(D) : vecs<T>(D);
+Vecs<T>& work(DevLevel& D, bool multi) {
+  return multi ? mvecs<T>(D) : vecs<T>(D);
 }
 
 template <typename T>
-cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s, int ncol = 1) {
+cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStream_t s, int ncol = 1,
+                       bool multi = false) {
   const int d = P->H.cfg.dim, k = P->H.cfg.k;
   DevLevel& D = P->lv[l];
-  Vecs<T>& v = work<T>(D, ncol);
+  Vecs<T>& v = work<T>(D, multi);
   if (interior) {
     if (D.n_int[colour] == 0) return CMG_OK;
     KTimer t(P, kInterior, l, s);
@@ -423,13 +426,13 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
   {
     KTimer t(P, kCutSolve, l, s);
     if constexpr (std::is_same<T, float>::value) {
-      if (ncol > 1 && G.inv_tiles) {
-        HIP_TRY(cmg::launch_cut_solve_mfma(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, ncol, s));
+      if (multi && G.inv_tiles) {
+        HIP_TRY(cmg::launch_cut_solve_mfma(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, ncol, s));
       } else {
-        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, s, ncol));
       }
     } else {
-      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, s, ncol));
     }
   }
   KTimer t(P, kCutUpdate, l, s);
@@ -438,23 +441,23 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
 }
 
 template <typename T>
-cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s, int ncol = 1) {
+cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s, int ncol = 1, bool multi = false) {
   const int C = 1 << P->H.cfg.dim;
   std::vector<std::pair<bool, int>> seq;
   for (int c = 0; c < C; ++c) seq.push_back({true, c});
   for (int r = 0; r < P->H.cfg.n_c; ++r)
     for (int c = 0; c < C; ++c) seq.push_back({false, c});
   if (post) std::reverse(seq.begin(), seq.end());
-  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s, ncol));
+  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s, ncol, multi));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status coarse(cmg_problem* P, hipStream_t s, int ncol = 1) {
+cmg_status coarse(cmg_problem* P, hipStream_t s, int ncol = 1, bool multi = false) {
   DevLevel& D = P->lv[0];
   KTimer t(P, kCoarse, 0, s);
   HIP_TRY(cmg::launch_coarse<T>(coarse_inv<T>(P), D.kl64.dof_node, static_cast<int>(P->H.n_coarse),
-                                work<T>(D, ncol).b, work<T>(D, ncol).x, D.kl64.n_nodes, s, ncol));
+                                work<T>(D, multi).b, work<T>(D, multi).x, D.kl64.n_nodes, s, ncol));
   return CMG_OK;
 }
 
@@ -467,44 +470,45 @@ cmg_status zero_active(cmg_problem* P, int l, T* x, hipStream_t s, int ncol = 1)
 }
 
 template <typename T>
-cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s, int ncol = 1) {
+cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s, int ncol = 1,
+                     bool multi = false) {
   KTimer t(P, kApply, l, s);
-  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], ncol).W, s,
+  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], multi).W, s,
                                ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status prolong_add(cmg_problem* P, int l, hipStream_t s, int ncol = 1) {
+cmg_status prolong_add(cmg_problem* P, int l, hipStream_t s, int ncol = 1, bool multi = false) {
   KTimer t(P, kProlong, l, s);
   HIP_TRY(cmg::launch_prolong_add<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]),
-                                     work<T>(P->lv[l - 1], ncol).x, work<T>(P->lv[l], ncol).x, s, ncol));
+                                     work<T>(P->lv[l - 1], multi).x, work<T>(P->lv[l], multi).x, s, ncol));
   return CMG_OK;
 }
 
 template <typename T>
-cmg_status restrict_(cmg_problem* P, int l, const T* rf, hipStream_t s, int ncol = 1) {
+cmg_status restrict_(cmg_problem* P, int l, const T* rf, hipStream_t s, int ncol = 1, bool multi = false) {
   KTimer t(P, kRestrict, l, s);
   HIP_TRY(cmg::launch_restrict<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l - 1]), kl<T>(P->lv[l]), rf,
-                                  work<T>(P->lv[l - 1], ncol).b, s, ncol));
+                                  work<T>(P->lv[l - 1], multi).b, s, ncol));
   return CMG_OK;
 }
 
 // V-cycle on the lattice vectors of precision T: x_L = B b_L, zero initial guess.
 template <typename T>
-cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s, int ncol = 1) {
+cmg_status vcycle_lattice(cmg_problem* P, hipStream_t s, int ncol = 1, bool multi = false) {
   const int L = P->H.cfg.n_levels - 1;
   for (int l = L; l >= 1; --l) {
-    Vecs<T>& v = work<T>(P->lv[l], ncol);
+    Vecs<T>& v = work<T>(P->lv[l], multi);
     TRY(zero_active<T>(P, l, v.x, s, ncol));
-    TRY(smooth<T>(P, l, false, s, ncol));
-    TRY(apply_lat<T>(P, l, v.x, v.b, v.r, s, ncol));
-    TRY(restrict_<T>(P, l, v.r, s, ncol));
+    TRY(smooth<T>(P, l, false, s, ncol, multi));
+    TRY(apply_lat<T>(P, l, v.x, v.b, v.r, s, ncol, multi));
+    TRY(restrict_<T>(P, l, v.r, s, ncol, multi));
   }
-  TRY(coarse<T>(P, s, ncol));
+  TRY(coarse<T>(P, s, ncol, multi));
   for (int l = 1; l <= L; ++l) {
-    TRY(prolong_add<T>(P, l, s, ncol));
-    TRY(smooth<T>(P, l, true, s, ncol));
+    TRY(prolong_add<T>(P, l, s, ncol, multi));
+    TRY(smooth<T>(P, l, true, s, ncol, multi));
   }
   return CMG_OK;
 }
@@ -625,9 +629,9 @@ cmg_status vcycle_current(cmg_problem* p, const double* r, double* z, hipStream_
 template <typename T>
 cmg_status op_vcycle_multi(cmg_problem* p, int ncol, const double* r, double* z, hipStream_t s) {
   const int L = p->H.cfg.n_levels - 1;
-  Vecs<T>& v = work<T>(p->lv[L], ncol);
+  Vecs<T>& v = mvecs<T>(p->lv[L]);
   TRY(scatter<T>(p, L, r, v.b, s, ncol));
-  TRY(vcycle_lattice<T>(p, s, ncol));
+  TRY(vcycle_lattice<T>(p, s, ncol, true));
   return gather<T>(p, L, v.x, z, s, ncol);
 }
 
@@ -638,9 +642,9 @@ cmg_status vcycle_multi_current(cmg_problem* p, int ncol, const double* r, doubl
 // ncol columns: y = A x in FP64 on the finest level.
 cmg_status op_apply_multi(cmg_problem* p, int ncol, const double* x, double* y, hipStream_t s) {
   const int L = p->H.cfg.n_levels - 1;
-  Vecs<double>& v = work<double>(p->lv[L], ncol);
+  Vecs<double>& v = mvecs<double>(p->lv[L]);
   TRY(scatter<double>(p, L, x, v.x, s, ncol));
-  TRY(apply_lat<double>(p, L, v.x, nullptr, v.r, s, ncol));
+  TRY(apply_lat<double>(p, L, v.x, nullptr, v.r, s, ncol, true));
   return gather<double>(p, L, v.r, y, s, ncol);
 }
 
@@ -753,12 +757,15 @@ cmg_status cmg_upload(cmg_problem* p) {
   return st;
 }
 
-cmg_status cmg_device_bytes(const cmg_problem* p, int fp32, size_t* bytes) {
+cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
   if (!p || !bytes) return fail(CMG_EINVAL, "null argument");
+  if (flags < 0 || flags > 3) return fail(CMG_EINVAL, "flags: bit 0 FP32 copies, bit 1 multi-column buffers");
+  const bool fp32 = flags & 1, multi = flags & 2;
   const cmg::Config& cfg = p->H.cfg;
   const size_t nt = static_cast<size_t>(cmg::tables_size(cfg.dim, cfg.k));
   const size_t nw_face = static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
-  size_t b64 = 0, b32 = 0;
+  const size_t C = cmg::kMaxCols;
+  size_t b64 = 0, b32 = 0, m64 = 0, m32 = 0;
   for (const cmg::HostLevel& h : p->H.levels) {
     size_t maxn = 0;
     b64 += h.cell_flags.size() + h.ghost_mask.size() + 4 * (h.cut_id.size() + h.dof_node.size()) +
@@ -772,13 +779,24 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int fp32, size_t* bytes) {
              8 * g.inv.size();
       b32 += 4 * g.inv.size();
       maxn = std::max(maxn, g.nodes.size());
+      if (g.vertex.empty()) continue;
+      m32 += 8 * (g.vertex.size() + 1);  // tile offsets
+      for (size_t q = 0; q + 1 < g.off.size(); ++q) {
+        const size_t nj = static_cast<size_t>(g.off[q + 1] - g.off[q]);
+        m32 += 4 * ((nj + 15) / 16) * ((nj + 3) / 4) * 64;
+      }
     }
     b64 += 8 * maxn;
     b32 += 4 * maxn;
+    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn;
+    m64 += 8 * C * per_col;
+    m32 += 4 * C * per_col;
   }
-  b64 += 8 * p->H.coarse_inv.size() + 8 * 4 * static_cast<size_t>(p->H.levels.back().n_dofs) + 8 * 1024;
+  const size_t nL = static_cast<size_t>(p->H.levels.back().n_dofs);
+  b64 += 8 * p->H.coarse_inv.size() + 8 * 4 * nL + 8 * 1024;
   b32 += 4 * p->H.coarse_inv.size();
-  *bytes = b64 + (fp32 ? b32 : 0);
+  m64 += 8 * 4 * C * nL + 8 * C * 1024;
+  *bytes = b64 + (fp32 ? b32 : 0) + (multi ? m64 + (fp32 ? m32 : 0) : 0);
   return CMG_OK;
 }
 

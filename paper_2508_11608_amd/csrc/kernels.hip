@@ -1005,40 +1005,270 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   }
 }
 
+// Residual rows of one cut patch for NCOL columns at once, one thread per
+// internal node.  The patch closure of every column is staged node-major in LDS
+// (the columns of a node adjacent); thread i forms row i of A x for all columns:
+// every cell row (cut-cell matrix or uncut stiffness) is read once and applied
+// to all columns, and the ghost-face terms come from the face buffer W of the
+// level (mass-contracted jumps of every ghost face, written by k_face_w for
+// the current x just before).  Every column follows the same arithmetic in the
+// same order, so its result does not depend on the other columns.  Writes
+// rs[i][c] = b_c - (A x_c) at node i for i < nj, c < ncol (other entries are
+// left as they are).  All threads of the block call it (it synchronises).
+template <int D, int K, typename T, int NCOL>
+struct NodeSmem {
+  using S = Shape<D, K>;
+  double tab[S::T_GC + K - S::T_D0];  // d0 | d1 | gc
+  T xs[S::NC][NCOL];
+  uint8_t cfl[1 << D], cgh[1 << D];
+  int32_t ccut[1 << D], cgid[1 << D];
+};
+
+template <int D, int K, typename T, int NCOL>
+__device__ void cut_residual_nodes(const KLevel& L, const CutGroupDev& G, int gp, const T* __restrict__ x,
+                                   const T* __restrict__ b, const T* __restrict__ W, int ncol,
+                                   NodeSmem<D, K, T, NCOL>& sm, T (*rs)[NCOL], int& off, int& nj) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, NC1 = S::NC1, NCELL = 1 << D;
+  constexpr int NT = Pow<N1, D - 1>::v;
+  constexpr int NTAB = S::T_GC + K - S::T_D0;
+  constexpr int TH = CutShape<D, K>::THREADS;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NTAB; i += TH) sm.tab[i] = L.tables[S::T_D0 + i];
+  const double* d0 = sm.tab;
+  const double* d1 = sm.tab + K * N1;
+  const double* gc = sm.tab + 2 * K * N1;
+  off = G.off[gp];
+  nj = G.off[gp + 1] - off;
+  const int NV = L.N + 1;
+  int V[3] = {0, 0, 0};
+  {
+    int vr = G.vertex[gp];
+#pragma unroll
+    for (int a = 0; a < D; ++a) { V[a] = vr % NV; vr /= NV; }
+  }
+  const int64_t nn = L.nn, nn2 = nn * nn;
+  const int64_t cbase = K * (V[0] - 1) + nn * (K * (V[1] - 1)) + (D == 3 ? nn2 * (K * (V[2] - 1)) : 0);
+  if (tid < NCELL) {
+    int c[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      c[a] = V[a] - 1 + ((tid >> a) & 1);
+      in = in && c[a] >= 0 && c[a] < L.N;
+    }
+    uint8_t f = 0, g = 0;
+    int32_t cid = -1, gid = -1;
+    if (in) {
+      const int64_t cl = cell_lin(D, L.N, c);
+      f = L.flags[cl];
+      g = L.ghost[cl];
+      cid = L.cut_id[cl];
+      gid = L.cell_gid[cl];
+    }
+    sm.cfl[tid] = f;
+    sm.cgh[tid] = g;
+    sm.ccut[tid] = cid;
+    sm.cgid[tid] = gid;
+  }
+  // node and b of the thread's row, fetched before the staging completes
+  int node = 0;
+  T bv[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) bv[c] = 0;
+  if (tid < nj) {
+    node = G.nodes[off + tid];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+      if (c < ncol) bv[c] = b[c * L.n_nodes + node];
+  }
+  // stage the closure of every column (nodes outside the lattice are zero);
+  // all loads of a thread are issued before its LDS stores
+  {
+    constexpr int NST = NC * NCOL;
+    constexpr int NIT = (NST + TH - 1) / TH;
+    T v[NIT];
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + TH * u;
+      v[u] = 0;
+      const int q = e / NCOL, c = e % NCOL;
+      if (e < NST && c < ncol) {
+        const int q0 = q % NC1, q1 = (q / NC1) % NC1, q2 = q / (NC1 * NC1);
+        const int I0 = K * (V[0] - 1) + q0, I1 = K * (V[1] - 1) + q1, I2 = D == 3 ? K * (V[2] - 1) + q2 : 0;
+        const bool in = I0 >= 0 && I0 < nn && I1 >= 0 && I1 < nn && (D == 2 || (I2 >= 0 && I2 < nn));
+        if (in) v[u] = x[c * L.n_nodes + cbase + q0 + nn * q1 + (D == 3 ? nn2 * q2 : 0)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int e = tid + TH * u;
+      if (e < NST) sm.xs[e / NCOL][e % NCOL] = v[u];
+    }
+  }
+  __syncthreads();
+  if (tid < nj) {
+    int pi[3];
+    {
+      int r = node;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        pi[a] = r % L.nn - K * (V[a] - 1);
+        r /= L.nn;
+      }
+    }
+    T acc[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) acc[c] = 0;
+    const int64_t wcol = L.n_faces * K * NT;
+    for (int o = 0; o < NCELL; ++o) {
+      int il[3];
+      bool contains = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        il[a] = pi[a] - K * ((o >> a) & 1);
+        contains = contains && il[a] >= 0 && il[a] <= K;
+      }
+      const uint8_t f = sm.cfl[o];
+      if (!contains || !(f & 1)) continue;
+      int iloc = il[0] + N1 * il[1];
+      if (D == 3) iloc += N1 * N1 * il[2];
+      int qb = K * (o & 1) + NC1 * K * ((o >> 1) & 1);  // closure index of the cell's first node
+      if (D == 3) qb += NC1 * NC1 * K * ((o >> 2) & 1);
+      // one partial sum per x-row of the cell and column
+      constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+      constexpr int NSPLIT = NCOL == 1 ? NRW : 1;
+      T part[NSPLIT][NCOL];
+#pragma unroll
+      for (int r = 0; r < NSPLIT; ++r)
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) part[r][c] = 0;
+      if (f & 2) {
+        const T* row = L.cut_mats_t<T>() + ((int64_t)sm.ccut[o] * NL + iloc) * NL;
+#pragma unroll
+        for (int bq = 0; bq < NL; ++bq) {
+          const int b0 = bq % N1, b12 = bq / N1;
+          const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
+          const T m = row[bq];
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) part[NCOL == 1 ? b12 : 0][c] += m * sm.xs[q][c];
+        }
+      } else {
+        const double* row = L.tables + S::T_KCELL + iloc * NL;
+#pragma unroll
+        for (int bq = 0; bq < NL; ++bq) {
+          const int b0 = bq % N1, b12 = bq / N1;
+          const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
+          const T m = (T)row[bq];
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) part[NCOL == 1 ? b12 : 0][c] += m * sm.xs[q][c];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NSPLIT; ++r)
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) acc[c] += part[r][c];
+      const uint8_t g = sm.cgh[o];
+      if (g) {
+        const int gid = sm.cgid[o];
+#pragma unroll
+        for (int dir = 0; dir < D; ++dir)
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            if (!(g & (1 << (2 * dir + side)))) continue;
+            const int fid = L.cell_faces[(int64_t)gid * 2 * D + 2 * dir + side];
+            int it = 0, st = 1;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              if (a == dir) continue;
+              it += il[a] * st;
+              st *= N1;
+            }
+            const T* w = W + (int64_t)fid * K * NT + it;
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+              const T sg = (T)(gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]));
+#pragma unroll
+              for (int c = 0; c < NCOL; ++c)
+                if (c < ncol) acc[c] += sg * w[c * wcol + m * NT];
+            }
+          }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+      if (c < ncol) rs[tid][c] = bv[c] - acc[c];
+  }
+  __syncthreads();
+}
+
+// Cut patches, phase 1 with the node-thread residual: one block per patch and
+// one column per blockIdx.y; d_j = A_j^{-1} r_j by a GEMV with the symmetric
+// inverse.  W must hold the ghost-face jumps of x (k_face_w).
+template <int D, int K, typename T>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_nodes(KLevel L, CutGroupDev G,
+                                                                              const T* __restrict__ x,
+                                                                              const T* __restrict__ b,
+                                                                              const T* __restrict__ W,
+                                                                              T* __restrict__ dbuf) {
+  using S = Shape<D, K>;
+  constexpr int NT = Pow<S::N1, D - 1>::v;
+  __shared__ NodeSmem<D, K, T, 1> sm;
+  __shared__ T rs[S::NP][1];
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  b += blockIdx.y * L.n_nodes;
+  W += blockIdx.y * L.n_faces * K * NT;
+  dbuf += blockIdx.y * G.n_nodes;
+  int off, nj;
+  cut_residual_nodes<D, K, T, 1>(L, G, blockIdx.x, x, b, W, 1, sm, rs, off, nj);
+  const int tid = threadIdx.x;
+  const T* inv = G.inv_t<T>() + G.inv_off[blockIdx.x];
+  if (tid < nj) {
+    const int i = tid;
+    T acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0;
+    int j = 0;
+    for (; j + 8 <= nj; j += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = inv[(int64_t)(j + u) * nj + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += v[u] * rs[j + u][0];
+    }
+    for (; j < nj; ++j) acc[0] += inv[(int64_t)j * nj + i] * rs[j][0];
+    dbuf[off + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+}
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Cut patches, phase 1 for several columns in FP32: the residuals of all
-// columns (one pass of cut_patch_ax per column), then D = A_j^{-1} R on the
-// matrix cores.  v_mfma_f32_16x16x4f32 multiplies a 16x4 tile of the inverse
-// (lane l holds row l%16, column l/16) by a 4x16 slice of R (lane l holds row
-// l/16, column l%16; columns >= kMaxCols are zero) into 16x16 accumulators
-// (lane l holds rows 4(l/16)..4(l/16)+3 of column l%16).  The inverse is
-// stored tile by tile in exactly that lane order (CutGroupDev::inv_tiles), so
-// every tile is one coalesced 256-byte wave load, and is read once for all
-// columns.  Row blocks of 16 are spread over the block's wavefronts.
+// Cut patches, phase 1 for up to kMaxCols columns in FP32, local solves on the
+// matrix cores.  Residuals of all columns by cut_residual_nodes, then
+// D = A_j^{-1} R with v_mfma_f32_16x16x4f32, which multiplies a 16x4 tile of
+// the inverse (lane l holds row l%16, column l/16) by a 4x16 slice of R (lane
+// l holds row l/16, column l%16; columns >= kMaxCols are zero) into 16x16
+// accumulators (lane l holds rows 4(l/16)..4(l/16)+3 of column l%16).  The
+// inverse is stored tile by tile in exactly that lane order
+// (CutGroupDev::inv_tiles), so a tile is one coalesced 256-byte wave load, and
+// it is read once for all columns.  Row blocks of 16 are spread over the
+// block's wavefronts.
 template <int D, int K>
 __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KLevel L, CutGroupDev G,
                                                                              const float* __restrict__ x,
                                                                              const float* __restrict__ b,
+                                                                             const float* __restrict__ W,
                                                                              float* __restrict__ dbuf, int ncol) {
   using S = Shape<D, K>;
   constexpr int NPK = (S::NP + 3) / 4 * 4;
-  __shared__ CutSmem<D, K, float> sm;
+  __shared__ NodeSmem<D, K, float, kMaxCols> sm;
   __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = blockIdx.x;
-  for (int e = tid; e < NPK * kMaxCols; e += blockDim.x) (&rs[0][0])[e] = 0.f;
-  int V[3] = {0, 0, 0};
-  const int node = cut_patch_setup<D, K, float>(L, G, gp, sm, V);
-  const int off = G.off[gp];
-  const int nj = G.off[gp + 1] - off;
-  for (int c = 0; c < ncol; ++c) {
-    const float bval = node >= 0 ? b[c * L.n_nodes + node] : 0.f;
-    const float ax = cut_patch_ax<D, K, float>(L, nj, V, x + c * L.n_nodes, sm);
-    if (tid < nj) rs[tid][c] = bval - ax;
-  }
-  __syncthreads();
-  const int lane = tid % 64, wave = tid / 64, nwave = blockDim.x / 64;
+  for (int e = tid; e < NPK * kMaxCols; e += nth) (&rs[0][0])[e] = 0.f;
+  int off, nj;
+  cut_residual_nodes<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
+  const int lane = tid % 64, wave = tid / 64, nwave = nth / 64;
   const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
   const int kr = lane / 16, jc = lane % 16;
   const float* tiles = G.inv_tiles + G.tile_off[gp];
@@ -1300,25 +1530,43 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
 }
 
 template <typename T>
-hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s, int ncol) {
+hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* W,
+                            T* dbuf, hipStream_t s, int ncol) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+#ifdef CMG_CUT_NODE_THREADS
+    if (L.n_faces > 0) {  // ghost-face jumps of the current x
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value), ncol), dim3(256), 0,
+                         s, L, x, W);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((dev::k_cut_solve_nodes<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G,
+                       x, b, W, dbuf);
+#else
+    (void)W;
     hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G, x, b,
                        dbuf);
+#endif
     return hipGetLastError();
   });
 }
 
 hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,
-                                 float* dbuf, int ncol, hipStream_t s) {
+                                 float* W, float* dbuf, int ncol, hipStream_t s) {
   if (G.n_patch == 0) return hipSuccess;
   if (!G.inv_tiles || !G.tile_off || ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
   return dispatch(d, k, [&](auto D, auto K) {
+    if (L.n_faces > 0) {  // ghost-face jumps of the current x, all columns
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, float>), dim3(blocks(L.n_faces * K.value), ncol),
+                         dim3(256), 0, s, L, x, W);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
-    hipLaunchKernelGGL((dev::k_cut_solve_mfma<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, dbuf,
-                       ncol);
+    hipLaunchKernelGGL((dev::k_cut_solve_mfma<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, W,
+                       dbuf, ncol);
     return hipGetLastError();
   });
 }
@@ -1385,7 +1633,7 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
   template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t, int);     \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
                                               hipStream_t, int);                                                   \
-  template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
+  template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*, T*, \
                                           hipStream_t, int);                                                       \
   template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, int64_t, hipStream_t, int);          \
   template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t,     \

@@ -2,15 +2,18 @@
 //
 // Requests (a level-set domain, discretisation parameters, a right-hand side and
 // a tolerance) are queued in arrival order.  Every slot is a worker thread with
-// its own HIP stream (default priority).  A slot takes the next request, looks
-// for a resident hierarchy with the same geometry and parameters, otherwise
-// sets one up on the host (one set-up at a time; it is OpenMP-parallel
-// itself) and admits it to the device once its exact footprint fits into the
-// HBM budget, evicting least-recently used idle hierarchies.  It then solves
-// with V-cycle-preconditioned CG on its own stream, so requests that arrive
-// while others run are admitted as slots and memory free up and their kernels
-// overlap on the device.  Each solve is deterministic and touches only its own
-// hierarchy and vectors, so a result does not depend on what else runs.
+// its own HIP stream (default priority).  A free slot takes the oldest request
+// and up to kMaxCols - 1 further queued requests with the same geometry,
+// parameters, tolerance and iteration limit (a batch), looks for a resident
+// hierarchy of that geometry, otherwise sets one up on the host (one set-up at
+// a time; it is OpenMP-parallel itself) and admits it to the device once its
+// exact footprint fits into the HBM budget, evicting least-recently used idle
+// hierarchies.  The batch is solved by one multi-column PCG on the slot's
+// stream: every V-cycle launch carries all requests of the batch, requests
+// that arrive while others run join the next batch, and batches of different
+// slots overlap on the device.  The column arithmetic of the multi-column
+// solve does not depend on the other columns, so a result is the same alone
+// and in any batch or mix.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -29,6 +32,8 @@
 #include "../../include/cutmg.h"
 
 namespace {
+
+constexpr size_t kBatch = 8;  // requests per multi-column solve (cmg_solve_multi takes up to 8 columns)
 
 struct OwnedRequest {
   uint64_t ticket = 0;
@@ -50,6 +55,13 @@ struct OwnedRequest {
     put(&box_lo, sizeof box_lo);
     put(&box_hi, sizeof box_hi);
     put(&params, sizeof params);
+    return k;
+  }
+  // requests that can share one multi-column solve
+  std::string batch_key() const {
+    std::string k = key();
+    k.append(reinterpret_cast<const char*>(&rtol), sizeof rtol);
+    k.append(reinterpret_cast<const char*>(&maxit), sizeof maxit);
     return k;
   }
 };
@@ -147,7 +159,7 @@ cmg_status acquire(cmg_server* S, const OwnedRequest& rq, Entry** out, cmg_resul
   }
   if (st != CMG_OK) return st;
   size_t bytes = 0;
-  cmg_device_bytes(p, rq.params.precond_fp32, &bytes);
+  cmg_device_bytes(p, rq.params.precond_fp32 | 2, &bytes);  // with the multi-column buffers
   {
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
@@ -203,40 +215,64 @@ void worker(cmg_server* S) {
   hipStream_t stream = nullptr;
   (void)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
   for (;;) {
-    OwnedRequest rq;
+    std::vector<OwnedRequest> batch;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv.wait(lk, [S] { return S->stop || !S->queue.empty(); });
       if (S->stop && S->queue.empty()) break;
-      rq = std::move(S->queue.front());
+      batch.push_back(std::move(S->queue.front()));
       S->queue.pop_front();
+      const std::string bk = batch[0].batch_key();
+      for (auto it = S->queue.begin(); it != S->queue.end() && batch.size() < kBatch;) {
+        if (it->batch_key() == bk) {
+          batch.push_back(std::move(*it));
+          it = S->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
     }
-    cmg_result res{};
-    res.t_submit = rq.t_submit;
-    res.t_start = S->now();
+    const int nb = static_cast<int>(batch.size());
+    const OwnedRequest& rq = batch[0];
+    std::vector<cmg_result> res(nb);
+    const double t_start = S->now();
+    for (int c = 0; c < nb; ++c) {
+      res[c] = cmg_result{};
+      res[c].t_submit = batch[c].t_submit;
+      res[c].t_start = t_start;
+      res[c].batch = nb;
+    }
     Entry* e = nullptr;
-    cmg_status st = acquire(S, rq, &e, res);
-    std::vector<double> x;
+    cmg_status st = acquire(S, rq, &e, res[0]);
+    for (int c = 1; c < nb; ++c) {
+      res[c].cache_hit = res[0].cache_hit;
+      res[c].t_admitted = res[0].t_admitted;
+    }
+    std::vector<double> X;
+    int64_t n = 0;
+    std::vector<cmg_solve_info> info(nb, cmg_solve_info{0, 0.0, 0.0});
     if (st == CMG_OK) {
-      int64_t n = 0;
       cmg_ndofs(e->p, rq.params.n_levels - 1, &n);
-      res.n_dofs = n;
-      std::vector<double> b(n);
-      st = rq.kappa.empty() ? cmg_rhs_manufactured(e->p, b.data())
-                            : cmg_rhs_fourier(e->p, static_cast<int>(rq.amp.size()), rq.kappa.data(), rq.amp.data(),
-                                              rq.phase.data(), b.data());
+      std::vector<double> B(static_cast<size_t>(n) * nb);
+      for (int c = 0; c < nb && st == CMG_OK; ++c) {
+        const OwnedRequest& q = batch[c];
+        double* bc = B.data() + static_cast<size_t>(c) * n;
+        st = q.kappa.empty() ? cmg_rhs_manufactured(e->p, bc)
+                             : cmg_rhs_fourier(e->p, static_cast<int>(q.amp.size()), q.kappa.data(), q.amp.data(),
+                                               q.phase.data(), bc);
+      }
+      const size_t bytes = static_cast<size_t>(n) * nb * sizeof(double);
       double *db = nullptr, *dx = nullptr;
-      if (st == CMG_OK && (hipMalloc(&db, n * sizeof(double)) != hipSuccess ||
-                           hipMalloc(&dx, n * sizeof(double)) != hipSuccess))
+      if (st == CMG_OK && (hipMalloc(&db, bytes) != hipSuccess || hipMalloc(&dx, bytes) != hipSuccess))
         st = CMG_ENOMEM;
-      if (st == CMG_OK &&
-          hipMemcpyAsync(db, b.data(), n * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess)
+      if (st == CMG_OK && hipMemcpyAsync(db, B.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         st = CMG_EHIP;
-      res.t_solve_start = S->now();
-      if (st == CMG_OK) st = cmg_solve(e->p, db, dx, rq.rtol, rq.maxit, &res.info, stream);
+      const double t_solve = S->now();
+      for (int c = 0; c < nb; ++c) res[c].t_solve_start = t_solve;
+      if (st == CMG_OK) st = cmg_solve_multi(e->p, nb, db, dx, rq.rtol, rq.maxit, info.data(), stream);
       if (st == CMG_OK || st == CMG_ENOTCONV) {
-        x.resize(n);
-        if (hipMemcpyAsync(x.data(), dx, n * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        X.resize(static_cast<size_t>(n) * nb);
+        if (hipMemcpyAsync(X.data(), dx, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
           st = CMG_EHIP;
       }
@@ -244,8 +280,15 @@ void worker(cmg_server* S) {
       if (dx) (void)hipFree(dx);
       release(S, e);
     }
-    res.status = st;
-    finish(S, rq, res, std::move(x));
+    for (int c = 0; c < nb; ++c) {
+      res[c].n_dofs = n;
+      res[c].info = info[c];
+      // a batch that missed rtol reports it per request
+      res[c].status = st == CMG_ENOTCONV ? (info[c].rel_residual <= batch[c].rtol ? CMG_OK : CMG_ENOTCONV) : st;
+      std::vector<double> x;
+      if (!X.empty()) x.assign(X.begin() + static_cast<size_t>(c) * n, X.begin() + static_cast<size_t>(c + 1) * n);
+      finish(S, batch[c], res[c], std::move(x));
+    }
   }
   (void)hipStreamDestroy(stream);
 }

@@ -51,7 +51,7 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("n_dofs", ctypes.c_int64), ("info", SolveInfo), ("cache_hit", ctypes.c_int),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_admitted", ctypes.c_double),
-                ("t_solve_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_solve_start", ctypes.c_double), ("t_done", ctypes.c_double), ("batch", ctypes.c_int)]
 
 
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
@@ -369,7 +369,7 @@ class Server:
         out = {"status": res.status, "n_dofs": res.n_dofs, "iterations": res.info.iterations,
                "rel_residual": res.info.rel_residual, "cache_hit": bool(res.cache_hit),
                "t_submit": res.t_submit, "t_start": res.t_start, "t_admitted": res.t_admitted,
-               "t_solve_start": res.t_solve_start, "t_done": res.t_done}
+               "t_solve_start": res.t_solve_start, "t_done": res.t_done, "batch": res.batch}
         return out, x
 
     def close(self):

@@ -16,11 +16,15 @@ pytestmark = pytest.mark.gpu
 
 
 def _mix():
+    """Eight geometries / degrees / precisions, plus six more requests of one
+    geometry with their own right-hand sides, so that batches form."""
     ws = [W.offcentre_disc(2, 4), W.offcentre_ball(2, 3), W.ellipse(3, 3), W.offcentre_disc(1, 4),
-          W.offcentre_ball(1, 3)]
+          W.offcentre_ball(1, 3), W.disc_union(2, 3)]
     out = []
-    for i, w in enumerate(ws + ws[:3]):
+    for i, w in enumerate(ws + ws[:2]):
         out.append((w, W.fourier_modes(w.dim, 1000 + i), bool(i % 2)))
+    for i in range(6):
+        out.append((ws[0], W.fourier_modes(2, 2000 + i), True))
     return out
 
 
@@ -43,6 +47,9 @@ def _run(server, reqs):
 
 
 def test_results_alone_equal_results_in_the_mix():
+    """Every request of a mix (three slots, batches of one geometry) gives the
+    same iterations and the same solution, bit for bit, as the same request
+    alone on a fresh server."""
     from paper_2508_11608_amd import Server
 
     reqs = _mix()
@@ -50,10 +57,13 @@ def test_results_alone_equal_results_in_the_mix():
     mix = Server(8 << 30, 3)
     in_mix = _run(mix, reqs)
     mix.close()
+    print("  batch sizes in the mix:", [r["batch"] for r, _ in in_mix], flush=True)
+    assert max(r["batch"] for r, _ in in_mix) > 1
     for (w, f, fp32), (res, x) in zip(reqs, in_mix):
         alone_srv = Server(8 << 30, 1)
         (res1, x1), = _run(alone_srv, [(w, f, fp32)])
         alone_srv.close()
+        assert res1["batch"] == 1
         assert res["status"] == 0 and res1["status"] == 0
         assert res["rel_residual"] <= 1e-8
         assert res["iterations"] == res1["iterations"]
@@ -61,18 +71,24 @@ def test_results_alone_equal_results_in_the_mix():
 
 
 def test_server_result_matches_direct_solve():
+    """A served FP64 request equals cmg_solve bit for bit; a served FP32 one
+    equals the one-column cmg_solve_multi (matrix-core local solves)."""
     from paper_2508_11608_amd import Problem, Server
 
     w = W.offcentre_ball(2, 3)
     f = W.fourier_modes(3, 7)
     srv = Server(4 << 30, 2)
-    (res, x), = _run(srv, [(w, f, False)])
+    (res, x), (res32, x32) = _run(srv, [(w, f, False), (w, f, True)])
     srv.close()
     P = Problem(w)
     b = torch.from_numpy(P.rhs_fourier(*f)).cuda()
     xd, info = P.solve(b, rtol=1e-8)
     assert res["iterations"] == info["iterations"]
     assert np.array_equal(x, xd.cpu().numpy())
+    P.set_precision(True)
+    xm, infos = P.solve_multi(b[None, :].contiguous(), rtol=1e-8)
+    assert res32["iterations"] == infos[0]["iterations"]
+    assert np.array_equal(x32, xm[0].cpu().numpy())
 
 
 def test_admission_under_a_small_budget():
@@ -87,7 +103,7 @@ def test_admission_under_a_small_budget():
     for w in ws:
         P = Problem(w, device=False)
         b = ctypes.c_size_t()
-        cutmg._lib.cmg_device_bytes(P._h, 1, ctypes.byref(b))
+        cutmg._lib.cmg_device_bytes(P._h, 3, ctypes.byref(b))  # FP32 copies + multi-column buffers
         need = max(need, b.value)
     srv = Server(int(need * 1.5), 2)
     reqs = [(w, W.fourier_modes(2, 50 + i), True) for i, w in enumerate(ws * 2)]
