@@ -429,10 +429,10 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
       if (multi && G.inv_tiles) {
         HIP_TRY(cmg::launch_cut_solve_mfma(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, ncol, s));
       } else {
-        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, s, ncol));
+        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
       }
     } else {
-      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, s, ncol));
+      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
     }
   }
   KTimer t(P, kCutUpdate, l, s);

@@ -68,10 +68,9 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
                                 hipStream_t s, int ncol = 1);
-// W: the ghost-face work buffer of the level (ncol columns), may be rewritten.
 template <typename T>
-hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* W,
-                            T* dbuf, hipStream_t s, int ncol = 1);
+hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
+                            hipStream_t s, int ncol = 1);
 // FP32, ncol <= kMaxCols columns, local solves on the matrix cores (needs
 // inv_tiles); W is the ghost-face work buffer (ncol columns), rewritten here.
 hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,

@@ -1005,36 +1005,45 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   }
 }
 
-// Residual rows of one cut patch for NCOL columns at once, one thread per
-// internal node.  The patch closure of every column is staged node-major in LDS
-// (the columns of a node adjacent); thread i forms row i of A x for all columns:
-// every cell row (cut-cell matrix or uncut stiffness) is read once and applied
-// to all columns, and the ghost-face terms come from the face buffer W of the
-// level (mass-contracted jumps of every ghost face, written by k_face_w for
-// the current x just before).  Every column follows the same arithmetic in the
-// same order, so its result does not depend on the other columns.  Writes
-// rs[i][c] = b_c - (A x_c) at node i for i < nj, c < ncol (other entries are
-// left as they are).  All threads of the block call it (it synchronises).
+// Residual rows of one cut patch for NCOL columns at once.  The patch closure
+// of every column is staged node-major in LDS (the columns of a node
+// adjacent).  The work is split into (node, cell) pairs: along each direction
+// an internal node at patch coordinate p in 1..2k-1 lies in cell layer 0
+// (p <= k) and/or 1 (p >= k), which gives 2k (p, layer) choices per direction
+// and (2k)^d pairs per patch, enumerated arithmetically (pairs of absent nodes
+// or inactive cells contribute zero).  A pair applies its cell row (cut-cell
+// matrix or uncut stiffness, read once for all columns) and the ghost-face
+// terms of that cell (from the level's face buffer W, written by k_face_w for
+// the current x just before) to all columns, into parts[pair][column]; each
+// node then sums its 1..2^d pairs in a fixed order.  Every column follows the
+// same arithmetic in the same order, so its result does not depend on the
+// other columns.  Writes rs[i][c] = b_c - (A x_c) at node i for i < nj,
+// c < ncol.  All threads of the block call it (it synchronises).
 template <int D, int K, typename T, int NCOL>
-struct NodeSmem {
+struct PairSmem {
   using S = Shape<D, K>;
+  static constexpr int NPAIR = Pow<2 * K, D>::v;
   double tab[S::T_GC + K - S::T_D0];  // d0 | d1 | gc
   T xs[S::NC][NCOL];
+  T parts[NPAIR][NCOL];
+  int16_t slot[S::NP];  // row of the patch's node at each internal position, -1 if absent
   uint8_t cfl[1 << D], cgh[1 << D];
   int32_t ccut[1 << D], cgid[1 << D];
 };
 
 template <int D, int K, typename T, int NCOL>
-__device__ void cut_residual_nodes(const KLevel& L, const CutGroupDev& G, int gp, const T* __restrict__ x,
-                                   const T* __restrict__ b, const T* __restrict__ W, int ncol,
-                                   NodeSmem<D, K, T, NCOL>& sm, T (*rs)[NCOL], int& off, int& nj) {
+__device__ void cut_residual_cols(const KLevel& L, const CutGroupDev& G, int gp, const T* __restrict__ x,
+                                  const T* __restrict__ b, const T* __restrict__ W, int ncol,
+                                  PairSmem<D, K, T, NCOL>& sm, T (*rs)[NCOL], int& off, int& nj) {
   using S = Shape<D, K>;
-  constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, NC1 = S::NC1, NCELL = 1 << D;
+  constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, NC1 = S::NC1, NP1 = S::NP1, NCELL = 1 << D;
   constexpr int NT = Pow<N1, D - 1>::v;
   constexpr int NTAB = S::T_GC + K - S::T_D0;
+  constexpr int NPAIR = PairSmem<D, K, T, NCOL>::NPAIR;
   constexpr int TH = CutShape<D, K>::THREADS;
   const int tid = threadIdx.x;
   for (int i = tid; i < NTAB; i += TH) sm.tab[i] = L.tables[S::T_D0 + i];
+  for (int i = tid; i < S::NP; i += TH) sm.slot[i] = -1;
   const double* d0 = sm.tab;
   const double* d1 = sm.tab + K * N1;
   const double* gc = sm.tab + 2 * K * N1;
@@ -1071,16 +1080,22 @@ __device__ void cut_residual_nodes(const KLevel& L, const CutGroupDev& G, int gp
     sm.ccut[tid] = cid;
     sm.cgid[tid] = gid;
   }
-  // node and b of the thread's row, fetched before the staging completes
-  int node = 0;
+  // node, patch position and b of the thread's row, fetched before the staging
+  int pi[3] = {0, 0, 0};
   T bv[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) bv[c] = 0;
   if (tid < nj) {
-    node = G.nodes[off + tid];
+    const int node = G.nodes[off + tid];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c)
       if (c < ncol) bv[c] = b[c * L.n_nodes + node];
+    int r = node;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      pi[a] = r % L.nn - K * (V[a] - 1);
+      r /= L.nn;
+    }
   }
   // stage the closure of every column (nodes outside the lattice are zero);
   // all loads of a thread are issued before its LDS stores
@@ -1106,68 +1121,62 @@ __device__ void cut_residual_nodes(const KLevel& L, const CutGroupDev& G, int gp
       if (e < NST) sm.xs[e / NCOL][e % NCOL] = v[u];
     }
   }
-  __syncthreads();
   if (tid < nj) {
-    int pi[3];
+    int pos = 0;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) pos = pos * NP1 + (pi[a] - 1);
+    sm.slot[pos] = static_cast<int16_t>(tid);
+  }
+  __syncthreads();
+  const int64_t wcol = L.n_faces * K * NT;
+  for (int t = tid; t < NPAIR; t += TH) {
+    int p[3], o = 0, pos = 0;
     {
-      int r = node;
+      int r = t;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        pi[a] = r % L.nn - K * (V[a] - 1);
-        r /= L.nn;
+        const int j = r % (2 * K);
+        r /= 2 * K;
+        const int layer = j >= K ? 1 : 0;
+        p[a] = j < K ? j + 1 : j;
+        o |= layer << a;
       }
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) pos = pos * NP1 + (p[a] - 1);
     }
     T acc[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) acc[c] = 0;
-    const int64_t wcol = L.n_faces * K * NT;
-    for (int o = 0; o < NCELL; ++o) {
+    const uint8_t f = sm.cfl[o];
+    if (sm.slot[pos] >= 0 && (f & 1)) {
       int il[3];
-      bool contains = true;
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        il[a] = pi[a] - K * ((o >> a) & 1);
-        contains = contains && il[a] >= 0 && il[a] <= K;
-      }
-      const uint8_t f = sm.cfl[o];
-      if (!contains || !(f & 1)) continue;
+      for (int a = 0; a < D; ++a) il[a] = p[a] - K * ((o >> a) & 1);
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
       int qb = K * (o & 1) + NC1 * K * ((o >> 1) & 1);  // closure index of the cell's first node
       if (D == 3) qb += NC1 * NC1 * K * ((o >> 2) & 1);
-      // one partial sum per x-row of the cell and column
-      constexpr int NRW = N1 * (D == 3 ? N1 : 1);
-      constexpr int NSPLIT = NCOL == 1 ? NRW : 1;
-      T part[NSPLIT][NCOL];
-#pragma unroll
-      for (int r = 0; r < NSPLIT; ++r)
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) part[r][c] = 0;
       if (f & 2) {
         const T* row = L.cut_mats_t<T>() + ((int64_t)sm.ccut[o] * NL + iloc) * NL;
-#pragma unroll
+#pragma unroll 8
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
           const T m = row[bq];
 #pragma unroll
-          for (int c = 0; c < NCOL; ++c) part[NCOL == 1 ? b12 : 0][c] += m * sm.xs[q][c];
+          for (int c = 0; c < NCOL; ++c) acc[c] += m * sm.xs[q][c];
         }
       } else {
         const double* row = L.tables + S::T_KCELL + iloc * NL;
-#pragma unroll
+#pragma unroll 8
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
           const T m = (T)row[bq];
 #pragma unroll
-          for (int c = 0; c < NCOL; ++c) part[NCOL == 1 ? b12 : 0][c] += m * sm.xs[q][c];
+          for (int c = 0; c < NCOL; ++c) acc[c] += m * sm.xs[q][c];
         }
       }
-#pragma unroll
-      for (int r = 0; r < NSPLIT; ++r)
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) acc[c] += part[r][c];
       const uint8_t g = sm.cgh[o];
       if (g) {
         const int gid = sm.cgid[o];
@@ -1196,55 +1205,45 @@ __device__ void cut_residual_nodes(const KLevel& L, const CutGroupDev& G, int gp
       }
     }
 #pragma unroll
+    for (int c = 0; c < NCOL; ++c) sm.parts[t][c] = acc[c];
+  }
+  __syncthreads();
+  if (tid < nj) {
+    // the node's pairs: per direction index j = p - 1 (layer 0, p <= k) and
+    // j = p (layer 1, p >= k), in increasing pair index
+    int jlo[3], jn[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      jlo[a] = pi[a] <= K ? pi[a] - 1 : pi[a];
+      jn[a] = pi[a] == K ? 2 : 1;
+    }
+    T acc[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) acc[c] = 0;
+    const int ncomb = jn[0] * jn[1] * (D == 3 ? jn[2] : 1);
+    for (int comb = 0; comb < ncomb; ++comb) {
+      int t = 0, r = comb, st = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int sel = r % jn[a];
+        r /= jn[a];
+        t += (jlo[a] + sel) * st;
+        st *= 2 * K;
+      }
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc[c] += sm.parts[t][c];
+    }
+#pragma unroll
     for (int c = 0; c < NCOL; ++c)
       if (c < ncol) rs[tid][c] = bv[c] - acc[c];
   }
   __syncthreads();
 }
 
-// Cut patches, phase 1 with the node-thread residual: one block per patch and
-// one column per blockIdx.y; d_j = A_j^{-1} r_j by a GEMV with the symmetric
-// inverse.  W must hold the ghost-face jumps of x (k_face_w).
-template <int D, int K, typename T>
-__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_nodes(KLevel L, CutGroupDev G,
-                                                                              const T* __restrict__ x,
-                                                                              const T* __restrict__ b,
-                                                                              const T* __restrict__ W,
-                                                                              T* __restrict__ dbuf) {
-  using S = Shape<D, K>;
-  constexpr int NT = Pow<S::N1, D - 1>::v;
-  __shared__ NodeSmem<D, K, T, 1> sm;
-  __shared__ T rs[S::NP][1];
-  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
-  b += blockIdx.y * L.n_nodes;
-  W += blockIdx.y * L.n_faces * K * NT;
-  dbuf += blockIdx.y * G.n_nodes;
-  int off, nj;
-  cut_residual_nodes<D, K, T, 1>(L, G, blockIdx.x, x, b, W, 1, sm, rs, off, nj);
-  const int tid = threadIdx.x;
-  const T* inv = G.inv_t<T>() + G.inv_off[blockIdx.x];
-  if (tid < nj) {
-    const int i = tid;
-    T acc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0;
-    int j = 0;
-    for (; j + 8 <= nj; j += 8) {
-      T v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = inv[(int64_t)(j + u) * nj + i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += v[u] * rs[j + u][0];
-    }
-    for (; j < nj; ++j) acc[0] += inv[(int64_t)j * nj + i] * rs[j][0];
-    dbuf[off + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-  }
-}
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Cut patches, phase 1 for up to kMaxCols columns in FP32, local solves on the
-// matrix cores.  Residuals of all columns by cut_residual_nodes, then
+// matrix cores.  Residuals of all columns by cut_residual_cols, then
 // D = A_j^{-1} R with v_mfma_f32_16x16x4f32, which multiplies a 16x4 tile of
 // the inverse (lane l holds row l%16, column l/16) by a 4x16 slice of R (lane
 // l holds row l/16, column l%16; columns >= kMaxCols are zero) into 16x16
@@ -1261,13 +1260,13 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
                                                                              float* __restrict__ dbuf, int ncol) {
   using S = Shape<D, K>;
   constexpr int NPK = (S::NP + 3) / 4 * 4;
-  __shared__ NodeSmem<D, K, float, kMaxCols> sm;
+  __shared__ PairSmem<D, K, float, kMaxCols> sm;
   __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
   const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = blockIdx.x;
   for (int e = tid; e < NPK * kMaxCols; e += nth) (&rs[0][0])[e] = 0.f;
   int off, nj;
-  cut_residual_nodes<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
+  cut_residual_cols<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
   const int lane = tid % 64, wave = tid / 64, nwave = nth / 64;
   const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
   const int kr = lane / 16, jc = lane % 16;
@@ -1530,25 +1529,13 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
 }
 
 template <typename T>
-hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* W,
-                            T* dbuf, hipStream_t s, int ncol) {
+hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
+                            hipStream_t s, int ncol) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
-#ifdef CMG_CUT_NODE_THREADS
-    if (L.n_faces > 0) {  // ghost-face jumps of the current x
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value), ncol), dim3(256), 0,
-                         s, L, x, W);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((dev::k_cut_solve_nodes<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G,
-                       x, b, W, dbuf);
-#else
-    (void)W;
     hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G, x, b,
                        dbuf);
-#endif
     return hipGetLastError();
   });
 }
@@ -1633,7 +1620,7 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
   template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t, int);     \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
                                               hipStream_t, int);                                                   \
-  template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*, T*, \
+  template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
                                           hipStream_t, int);                                                       \
   template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, int64_t, hipStream_t, int);          \
   template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t,     \
