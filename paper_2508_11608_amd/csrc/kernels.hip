@@ -667,10 +667,11 @@ struct CutSmem {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   double tab[S::T_D1 + K * S::N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
+  static constexpr int NPAIR = Pow<2 * K, D>::v;  // (node, cell) pairs of a patch, see cut_patch_ax
   T xs[C::NE];
   T Wf[C::NF][K][C::NT];
-  T parts[S::NP][1 << D];
-  int8_t npi[S::NP][3];
+  T parts[NPAIR];
+  int16_t slot[S::NP];  // row of the patch's node at each internal position, -1 if absent
   uint8_t cfl[1 << D], cgh[1 << D];
   int32_t ccut[1 << D];
   int needlo[3], needhi[3];
@@ -678,14 +679,17 @@ struct CutSmem {
 
 // Patch set-up shared by the cut-patch kernels: level tables, the 2^d cells
 // around the vertex (flags, ghost bits, cut ids), the sides that need a halo
-// slab, and the patch-local coordinates of the internal nodes.  Returns the
-// lattice node of the thread's internal node (tid < nj), else -1.
+// slab, and the row of every internal position.  Returns the lattice node of
+// the thread's internal node (tid < nj), else -1, and its patch coordinates
+// (1 .. 2k-1 per direction) in pi.
 template <int D, int K, typename T>
-__device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, CutSmem<D, K, T>& sm, int* V) {
+__device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, CutSmem<D, K, T>& sm, int* V,
+                               int* pi) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NCELL = 1 << D;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int i = tid; i < S::T_D1 + K * N1 + K - S::T_MHAT; i += nth) sm.tab[i] = L.tables[S::T_MHAT + i];
+  for (int i = tid; i < S::NP; i += nth) sm.slot[i] = -1;
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
   const int NV = L.N + 1;
@@ -721,11 +725,17 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
     node = r;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      sm.npi[tid][a] = static_cast<int8_t>(r % L.nn - K * (V[a] - 1));
+      pi[a] = r % L.nn - K * (V[a] - 1);
       r /= L.nn;
     }
   }
-  __syncthreads();
+  __syncthreads();  // slot initialised
+  if (tid < nj) {
+    int pos = 0;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (pi[a] - 1);
+    sm.slot[pos] = static_cast<int16_t>(tid);
+  }
   if (tid < NCELL) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -743,17 +753,21 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
 // side that carries a ghost face, the node slab of the neighbouring cell layer
 // are staged in LDS (an extended (4k+1)^d box with the closure at [k, 3k]^d);
 // the jumps J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost face
-// touching the patch are contracted with the face mass once per face; each
-// (node, cell) pair then needs its cell row (uncut stiffness or cut-cell
-// matrix) and k (k+1)^{d-1} terms per incident ghost face.  Called by all
-// threads of the block (it synchronises); the LDS buffers are reused on the
-// next call.
+// touching the patch are contracted with the face mass once per face.  The
+// rows are then split into (node, cell) pairs: along each direction a node at
+// patch coordinate p in 1..2k-1 lies in cell layer 0 (p <= k) and/or 1
+// (p >= k), which gives 2k (p, layer) choices per direction and (2k)^d pairs,
+// enumerated arithmetically (absent nodes and inactive cells give zero).  A
+// pair needs its cell row (uncut stiffness or cut-cell matrix) and k (k+1)^{d-1}
+// terms per incident ghost face; each node sums its pairs in a fixed order.
+// Called by all threads of the block (it synchronises); the LDS buffers are
+// reused on the next call.
 template <int D, int K, typename T>
-__device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const T* __restrict__ x, CutSmem<D, K, T>& sm) {
+__device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, const T* __restrict__ x,
+                          CutSmem<D, K, T>& sm) {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NF = C::NF, NT = C::NT;
-  constexpr int NCELL = 1 << D;
   const int tid = threadIdx.x, nth = blockDim.x;
   const double* mh = sm.tab;
   const double* d0 = sm.tab + (S::T_D0 - S::T_MHAT);
@@ -878,20 +892,28 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const T* __rest
     }
   }
   __syncthreads();
-  // contribution of patch cell o to the row of internal node i
-  for (int task = tid; task < nj * NCELL; task += nth) {
-    const int i = task / NCELL, o = task % NCELL;
-    T part = 0;
-    int il[3];
-    bool contains = true;
+  // (node, cell) pairs
+  constexpr int NPAIR = CutSmem<D, K, T>::NPAIR;
+  for (int t = tid; t < NPAIR; t += nth) {
+    int p[3], o = 0, pos = 0;
+    {
+      int r = t;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int pa = sm.npi[i][a], oa = (o >> a) & 1;
-      il[a] = pa - K * oa;
-      contains = contains && il[a] >= 0 && il[a] <= K;
+      for (int a = 0; a < D; ++a) {
+        const int j = r % (2 * K);
+        r /= 2 * K;
+        p[a] = j < K ? j + 1 : j;
+        o |= (j >= K ? 1 : 0) << a;
+      }
+#pragma unroll
+      for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (p[a] - 1);
     }
+    T part = 0;
     const uint8_t f = sm.cfl[o];
-    if (contains && (f & 1)) {
+    if (sm.slot[pos] >= 0 && (f & 1)) {
+      int il[3];
+#pragma unroll
+      for (int a = 0; a < D; ++a) il[a] = p[a] - K * ((o >> a) & 1);
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
       constexpr int E2 = E1 * E1;
@@ -929,16 +951,16 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const T* __rest
           for (int side = 0; side < 2; ++side) {
             if (!(g & (1 << (2 * dir + side)))) continue;
             const int plane = ((o >> dir) & 1) + side;
-            int t = 0, tb = 0, it = 0, st = 1;
+            int tt = 0, tb = 0, it = 0, st = 1;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
               if (a == dir) continue;
-              t |= ((o >> a) & 1) << tb;
+              tt |= ((o >> a) & 1) << tb;
               ++tb;
               it += il[a] * st;
               st *= N1;
             }
-            const int fi = (dir * 3 + plane) * (1 << (D - 1)) + t;
+            const int fi = (dir * 3 + plane) * (1 << (D - 1)) + tt;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
               const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
@@ -947,13 +969,31 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const T* __rest
           }
       }
     }
-    sm.parts[i][o] = part;
+    sm.parts[t] = part;
   }
   __syncthreads();
   T ax = 0;
   if (tid < nj) {
+    // the node's pairs: per direction index j = p - 1 (layer 0, p <= k) and
+    // j = p (layer 1, p >= k), in increasing pair index
+    int jlo[3], jn[3];
 #pragma unroll
-    for (int o = 0; o < NCELL; ++o) ax += sm.parts[tid][o];
+    for (int a = 0; a < D; ++a) {
+      jlo[a] = pi[a] <= K ? pi[a] - 1 : pi[a];
+      jn[a] = pi[a] == K ? 2 : 1;
+    }
+    const int ncomb = jn[0] * jn[1] * (D == 3 ? jn[2] : 1);
+    for (int comb = 0; comb < ncomb; ++comb) {
+      int t = 0, r = comb, st = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int sel = r % jn[a];
+        r /= jn[a];
+        t += (jlo[a] + sel) * st;
+        st *= 2 * K;
+      }
+      ax += sm.parts[t];
+    }
   }
   __syncthreads();  // the buffers may be restaged by the next call
   return ax;
@@ -976,12 +1016,12 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   x += blockIdx.y * L.n_nodes;
   b += blockIdx.y * L.n_nodes;
   dbuf += blockIdx.y * G.n_nodes;
-  int V[3] = {0, 0, 0};
-  const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V);
+  int V[3] = {0, 0, 0}, pi[3] = {0, 0, 0};
+  const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V, pi);
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
   const T bval = node >= 0 ? b[node] : (T)0;  // fetched long before it is needed
-  const T ax = cut_patch_ax<D, K, T>(L, nj, V, x, sm);
+  const T ax = cut_patch_ax<D, K, T>(L, nj, V, pi, x, sm);
   if (tid < nj) rs[tid] = bval - ax;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric);
