@@ -619,47 +619,11 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
 // Sizes of the cut-patch kernels (one block per patch).
 template <int D, int K>
 struct CutShape {
-  static constexpr int E1 = 4 * K + 1;                    // extended box, nodes per direction
-  static constexpr int NE = Pow<E1, D>::v;
   static constexpr int NF = D * 3 * (1 << (D - 1));       // faces touching a 2^d patch
   static constexpr int NT = Pow<K + 1, D - 1>::v;         // nodes of a cell face
   static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;  // one thread per internal node at least
   static_assert(Shape<D, K>::NP <= THREADS, "a cut-patch block needs a thread per internal node");
-  static constexpr int NCL = Shape<D, K>::NC;             // closure nodes
-  static constexpr int SLAB = K * Pow<2 * K + 1, D - 1>::v;  // nodes of one halo slab
-  static constexpr int NSTG = NCL + 2 * D * SLAB;         // closure + 2d slabs
 };
-
-// Extended-box coordinates (0..4k, closure at [k, 3k]) of the e-th staged
-// node: first the closure, then the slab below / above the closure in each
-// direction (k layers x (2k+1)^(d-1) nodes).  Returns the slab id (-1: closure).
-template <int D, int K>
-__device__ __forceinline__ int staged_coords(int e, int* q) {
-  using C = CutShape<D, K>;
-  constexpr int W1 = 2 * K + 1;
-  if (e < C::NCL) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      q[a] = K + e % W1;
-      e /= W1;
-    }
-    return -1;
-  }
-  e -= C::NCL;
-  const int slab = e / C::SLAB;
-  int r = e % C::SLAB;
-  const int out = slab >> 1, side = slab & 1;
-  const int s = r % K;
-  r /= K;
-  q[out] = side ? 3 * K + 1 + s : s;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    if (a == out) continue;
-    q[a] = K + r % W1;
-    r /= W1;
-  }
-  return slab;
-}
 
 // LDS of one cut-patch block.
 template <int D, int K, typename T>
@@ -668,18 +632,16 @@ struct CutSmem {
   using C = CutShape<D, K>;
   double tab[S::T_D1 + K * S::N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
   static constexpr int NPAIR = Pow<2 * K, D>::v;  // (node, cell) pairs of a patch, see cut_patch_ax
-  T xs[C::NE];
+  T xs[S::NC];                                   // x on the patch closure
   T Wf[C::NF][K][C::NT];
   T parts[NPAIR];
   int16_t slot[S::NP];  // row of the patch's node at each internal position, -1 if absent
   uint8_t cfl[1 << D], cgh[1 << D];
   int32_t ccut[1 << D];
-  int needlo[3], needhi[3];
 };
 
-// Patch set-up shared by the cut-patch kernels: level tables, the 2^d cells
-// around the vertex (flags, ghost bits, cut ids), the sides that need a halo
-// slab, and the row of every internal position.  Returns the lattice node of
+// Patch set-up of the cut-patch kernel: level tables, the 2^d cells around the
+// vertex (flags, ghost bits, cut ids) and the row of every internal position.  Returns the lattice node of
 // the thread's internal node (tid < nj), else -1, and its patch coordinates
 // (1 .. 2k-1 per direction) in pi.
 template <int D, int K, typename T>
@@ -718,7 +680,6 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
     sm.cgh[tid] = g;
     sm.ccut[tid] = cid;
   }
-  if (tid < 3) { sm.needlo[tid] = 0; sm.needhi[tid] = 0; }
   int node = -1;
   if (tid < nj) {
     int r = G.nodes[off + tid];
@@ -736,27 +697,19 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
     for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (pi[a] - 1);
     sm.slot[pos] = static_cast<int16_t>(tid);
   }
-  if (tid < NCELL) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int o = (tid >> a) & 1;
-      if (o == 0 && (sm.cgh[tid] & (1 << (2 * a)))) atomicOr(&sm.needlo[a], 1);
-      if (o == 1 && (sm.cgh[tid] & (1 << (2 * a + 1)))) atomicOr(&sm.needhi[a], 1);
-    }
-  }
   __syncthreads();
   return node;
 }
 
 // (A x) at the internal node of thread tid (tid < nj; other threads return 0)
-// for the patch prepared by cut_patch_setup.  The patch closure and, on every
-// side that carries a ghost face, the node slab of the neighbouring cell layer
-// are staged in LDS (an extended (4k+1)^d box with the closure at [k, 3k]^d);
-// the jumps J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost face
-// touching the patch are contracted with the face mass once per face.  The
-// rows are then split into (node, cell) pairs: along each direction a node at
-// patch coordinate p in 1..2k-1 lies in cell layer 0 (p <= k) and/or 1
-// (p >= k), which gives 2k (p, layer) choices per direction and (2k)^d pairs,
+// for the patch prepared by cut_patch_setup.  x on the patch closure is staged
+// in LDS.  The jumps J_m = d^m-trace(lower) - d^m-trace(upper) of every ghost
+// face touching the patch are formed from x in memory (the nodes of both
+// cells of the face, which can reach one cell layer beyond the closure) while
+// the closure loads are in flight, and contracted with the face mass once per
+// face.  The rows are then split into (node, cell) pairs: along each direction
+// a node at patch coordinate p in 1..2k-1 lies in cell layer 0 (p <= k) and/or
+// 1 (p >= k), which gives 2k (p, layer) choices per direction and (2k)^d pairs,
 // enumerated arithmetically (absent nodes and inactive cells give zero).  A
 // pair needs its cell row (uncut stiffness or cut-cell matrix) and k (k+1)^{d-1}
 // terms per incident ghost face; each node sums its pairs in a fixed order.
@@ -767,45 +720,32 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
                           CutSmem<D, K, T>& sm) {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
-  constexpr int N1 = S::N1, NL = S::NL, E1 = C::E1, NF = C::NF, NT = C::NT;
+  constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, W1 = S::NC1, NF = C::NF, NT = C::NT;
   const int tid = threadIdx.x, nth = blockDim.x;
   const double* mh = sm.tab;
   const double* d0 = sm.tab + (S::T_D0 - S::T_MHAT);
   const double* d1 = sm.tab + (S::T_D1 - S::T_MHAT);
   const double* gc = sm.tab + (S::T_GC - S::T_MHAT);
-  // stage x: closure [K, 3K]^D, plus the slab [0, K-1] / [3K+1, 4K] along a
-  // direction when a ghost face lies on that side of the patch (all loads of a
-  // thread are issued before its LDS stores; blockDim == THREADS)
-  {
-    constexpr int NIT = (C::NSTG + C::THREADS - 1) / C::THREADS;
-    T v[NIT];
-    int elx[NIT];
+  const int64_t nn = L.nn;
+  // closure loads first (stored to LDS after the face jumps; blockDim == THREADS)
+  constexpr int NIT = (NC + C::THREADS - 1) / C::THREADS;
+  T v[NIT];
 #pragma unroll
-    for (int u = 0; u < NIT; ++u) {
-      const int e = tid + C::THREADS * u;
-      v[u] = 0;
-      elx[u] = -1;
-      if (e < C::NSTG) {
-        int q[3];
-        const int slab = staged_coords<D, K>(e, q);
-        if (slab < 0 || ((slab & 1) ? sm.needhi[slab >> 1] : sm.needlo[slab >> 1])) {
-          int I[3];
-          bool in = true;
+  for (int u = 0; u < NIT; ++u) {
+    const int e = tid + C::THREADS * u;
+    v[u] = 0;
+    if (e < NC) {
+      int I[3], r = e;
+      bool in = true;
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            I[a] = K * (V[a] - 2) + q[a];
-            in = in && I[a] >= 0 && I[a] < L.nn;
-          }
-          elx[u] = q[0] + E1 * q[1] + (D == 3 ? E1 * E1 * q[2] : 0);
-          if (in) v[u] = x[lat(D, L.nn, I)];
-        }
+      for (int a = 0; a < D; ++a) {
+        I[a] = K * (V[a] - 1) + r % W1;
+        r /= W1;
+        in = in && I[a] >= 0 && I[a] < L.nn;
       }
+      if (in) v[u] = x[lat(D, L.nn, I)];
     }
-#pragma unroll
-    for (int u = 0; u < NIT; ++u)
-      if (elx[u] >= 0) sm.xs[elx[u]] = v[u];
   }
-  __syncthreads();
   // mass-contracted jumps W_m(i_t) of every ghost face touching the patch:
   // face (dir, plane 0..2, tangential cell t), plane p between cell layers p-1, p
   for (int task = tid; task < NF * K; task += nth) {
@@ -826,19 +766,24 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
     else if (plane == 1) ghost = sm.cgh[o] & (1 << (2 * dir + 1));      // between layers 0 and 1
     else ghost = sm.cgh[o | (1 << dir)] & (1 << (2 * dir + 1));         // upper face of layer 1
     if (!ghost) continue;
-    // strides of the tangential directions and of the normal one
-    constexpr int E2 = E1 * E1;
-    const int sn = dir == 0 ? 1 : (dir == 1 ? E1 : E2);
-    int st0 = 0, st1 = 0, base = 0, tb2 = 0;
+    // first node of the lower cell of the face, lattice strides of the
+    // tangential directions and of the normal one (a ghost face has both of
+    // its cells in the background box, so every node read is in the lattice)
+    int I[3], tb2 = 0;
+    int64_t st0 = 0, st1 = 0, sn = 1, sa = 1;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const int sa = a == 0 ? 1 : (a == 1 ? E1 : E2);
-      if (a == dir) continue;
-      base += (K + K * ((t >> tb2) & 1)) * sa;
-      if (tb2 == 0) st0 = sa; else st1 = sa;
-      ++tb2;
+      if (a == dir) {
+        I[a] = K * (V[a] - 2 + plane);
+        sn = sa;
+      } else {
+        I[a] = K * (V[a] - 1 + ((t >> tb2) & 1));
+        if (tb2 == 0) st0 = sa; else st1 = sa;
+        ++tb2;
+      }
+      sa *= nn;
     }
-    base += K * plane * sn;
+    const int64_t base = lat(D, L.nn, I);
     T dl[N1], du[N1];
 #pragma unroll
     for (int bd = 0; bd <= K; ++bd) {
@@ -848,12 +793,12 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
     T J[NT];
 #pragma unroll
     for (int bt = 0; bt < NT; ++bt) {
-      const int el = base + (bt % N1) * st0 + (D == 3 ? (bt / N1) * st1 : 0);
+      const int64_t el = base + (bt % N1) * st0 + (D == 3 ? (bt / N1) * st1 : 0);
       T acc0 = 0, acc1 = 0;
 #pragma unroll
       for (int bd = 0; bd <= K; ++bd) {
-        acc0 += dl[bd] * sm.xs[el + bd * sn];
-        acc1 += du[bd] * sm.xs[el + (bd + K) * sn];
+        acc0 += dl[bd] * x[el + bd * sn];
+        acc1 += du[bd] * x[el + (bd + K) * sn];
       }
       J[bt] = acc0 - acc1;
     }
@@ -891,6 +836,11 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
         }
     }
   }
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int e = tid + C::THREADS * u;
+    if (e < NC) sm.xs[e] = v[u];
+  }
   __syncthreads();
   // (node, cell) pairs
   constexpr int NPAIR = CutSmem<D, K, T>::NPAIR;
@@ -916,9 +866,8 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
       for (int a = 0; a < D; ++a) il[a] = p[a] - K * ((o >> a) & 1);
       int iloc = il[0] + N1 * il[1];
       if (D == 3) iloc += N1 * N1 * il[2];
-      constexpr int E2 = E1 * E1;
-      int xb = K * (1 + (o & 1)) + E1 * K * (1 + ((o >> 1) & 1));  // staged index of the cell's first node
-      if (D == 3) xb += E2 * K * (1 + ((o >> 2) & 1));
+      int xb = K * (o & 1) + W1 * K * ((o >> 1) & 1);  // closure index of the cell's first node
+      if (D == 3) xb += W1 * W1 * K * ((o >> 2) & 1);
       // dot product of the cell row with x, one partial sum per x-row of the cell
       constexpr int NRW = N1 * (D == 3 ? N1 : 1);
       T acc[NRW];
@@ -929,7 +878,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
-          const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
+          const int xi = xb + b0 + W1 * (b12 % N1) + (D == 3 ? W1 * W1 * (b12 / N1) : 0);
           acc[b12] += row[bq] * sm.xs[xi];
         }
       } else {
@@ -937,7 +886,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
-          const int xi = xb + b0 + E1 * (b12 % N1) + (D == 3 ? E2 * (b12 / N1) : 0);
+          const int xi = xb + b0 + W1 * (b12 % N1) + (D == 3 ? W1 * W1 * (b12 / N1) : 0);
           acc[b12] += (T)row[bq] * sm.xs[xi];
         }
       }
