@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="serving run: N seeded requests with Poisson arrivals instead of the solve benchmark")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--paper-tables", default="", metavar="LEVELS",
+                    help="iteration counts of GMRES and of the stand-alone V-cycle on the paper's circle protocol "
+                         "for the comma-separated finest levels L (k = 1..3, n_c = 1..4), beside the paper's numbers")
     ap.add_argument("--rate", type=float, default=0.8, help="arrival rate as a fraction of the saturation rate")
     return ap.parse_args()
 
@@ -135,6 +138,52 @@ def serve(args):
         "saturation_mean_batch": float(np.mean(sat_batch)), "saturation_max_batch": int(max(sat_batch)),
         "poisson_mean_batch": float(np.mean([r["batch"] for *_, r in out])),
     }
+
+
+def paper_tables(args):
+    """GMRES (restart 30) and the stand-alone V-cycle to 1e-9 on the paper's
+    circle protocol, FP64, manufactured right-hand side, k = 1..3, n_c = 1..4,
+    finest levels L from --paper-tables; the paper's printed counts from
+    tests/golden/paper_iteration_tables.txt beside them."""
+    import torch
+
+    import workloads as W
+    from paper_2508_11608_amd import Problem
+
+    paper = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_iteration_tables.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        solver, k, nc, L, it = line.split()
+        paper[(solver, int(k), int(nc), int(L))] = None if it == "-" else int(it)
+    rows = []
+    t0 = time.perf_counter()
+    for L in [int(v) for v in args.paper_tables.split(",")]:
+        for k in (1, 2, 3):
+            for nc in (1, 2, 3, 4):
+                w = W.paper_circle(k, L, nc)
+                P = Problem(w)
+                b = torch.from_numpy(P.rhs_manufactured()).cuda()
+                x = torch.empty_like(b)
+                res = {}
+                for solver in ("gmres", "vcycle"):
+                    ts = time.perf_counter()
+                    if solver == "gmres":
+                        _, info = P.gmres(b, x, rtol=1e-9, maxit=500, restart=30, raise_on_fail=False)
+                    else:
+                        _, info = P.vcycle_solve(b, x, rtol=1e-9, maxit=500, raise_on_fail=False)
+                    torch.cuda.synchronize()
+                    res[solver] = (info["iterations"] if info["status"] == 0 else None, time.perf_counter() - ts)
+                row = {"L": L, "k": k, "n_c": nc, "dofs": P.ndofs(),
+                       "gmres": res["gmres"][0], "gmres_paper": paper.get(("gmres", k, nc, L)),
+                       "vcycle": res["vcycle"][0], "vcycle_paper": paper.get(("vcycle", k, nc, L)),
+                       "gmres_s": res["gmres"][1], "vcycle_s": res["vcycle"][1]}
+                rows.append(row)
+                print(f"[paper-tables] L={L} Q{k} n_c={nc}: {row['dofs']} DoFs, GMRES {row['gmres']} "
+                      f"(paper {row['gmres_paper']}), V-cycle {row['vcycle']} (paper {row['vcycle_paper']}), "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+                P.close()
+    return {"paper_tables": rows}
 
 
 def kernel_source_hash() -> str:
@@ -361,6 +410,10 @@ def main():
     if args.serve:
         torch.cuda.set_device(0)
         print(json.dumps(serve(args)), flush=True)
+        return
+    if args.paper_tables:
+        torch.cuda.set_device(0)
+        print(json.dumps(paper_tables(args)), flush=True)
         return
 
     import workloads as W

@@ -143,6 +143,22 @@ cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream);
 cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
                      void* stream);
 
+/* The paper's other outer solvers (Section 2.2 and Section 4, its Tables 1-3),
+ * from x = 0, with the V-cycle of the current precision as preconditioner and
+ * FP64 operator products:
+ * cmg_gmres: right-preconditioned restarted GMRES(restart), 1 <= restart < 64;
+ *   Arnoldi on A B with classical Gram-Schmidt applied twice; x = B V y.  Stops
+ *   when the GMRES residual norm (||b - A x|| in exact arithmetic) is <= rtol
+ *   ||b||; info->iterations counts Arnoldi steps (V-cycles).
+ * cmg_vcycle_solve: multigrid as a stand-alone solver, x_{k+1} = x_k + B (b - A x_k),
+ *   until ||b - A x_k|| <= rtol ||b||; CMG_ENOTCONV once the residual exceeds
+ *   1e3 ||b|| (divergence) or after maxit cycles.
+ * Both synchronise the stream a few times per iteration; info may be NULL. */
+cmg_status cmg_gmres(cmg_problem* p, const double* b, double* x, double rtol, int maxit, int restart,
+                     cmg_solve_info* info, void* stream);
+cmg_status cmg_vcycle_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
+                            void* stream);
+
 /* Several right-hand sides at once (1 <= nrhs <= 8).  Column c of r, z, b and x
  * starts at c * n_L (n_L = cmg_ndofs of the finest level), canonical order.
  *

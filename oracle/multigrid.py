@@ -250,3 +250,90 @@ def pcg(A, b, precond, rtol=1e-8, maxit=200):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, maxit, hist
+
+
+def gmres(A, b, precond, rtol=1e-9, restart=30, maxit=500):
+    """Right-preconditioned restarted GMRES from x0 = 0 (the paper's outer
+    solver, Section 2.2 and Section 4): Arnoldi with modified Gram-Schmidt on
+    A B, Givens rotations for the least-squares problem, x = x0 + B V_j y.
+    Stops when the GMRES residual norm |g_{j+1}| (equal to ||b - A x||_2 in
+    exact arithmetic for right preconditioning) is <= rtol ||b||_2.
+
+    Returns (x, iterations, residual history); iterations counts Arnoldi steps
+    (one preconditioner application each)."""
+    n = len(b)
+    x = np.zeros(n)
+    nb = np.linalg.norm(b)
+    hist = [1.0]
+    if nb == 0.0:
+        return x, 0, hist
+    it = 0
+    while it < maxit:
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        if beta <= rtol * nb:
+            return x, it, hist
+        V = np.zeros((restart + 1, n))
+        Z = np.zeros((restart, n))
+        H = np.zeros((restart + 1, restart))
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        V[0] = r / beta
+        j_done = 0
+        converged = False
+        for j in range(restart):
+            Z[j] = precond(V[j]).astype(np.float64)
+            w = A @ Z[j]
+            for i in range(j + 1):
+                H[i, j] = w @ V[i]
+                w -= H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):  # earlier rotations on the new column
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            j_done = j + 1
+            hist.append(abs(g[j + 1]) / nb)
+            if abs(g[j + 1]) <= rtol * nb or it >= maxit:
+                converged = abs(g[j + 1]) <= rtol * nb
+                break
+        y = sla.solve_triangular(H[:j_done, :j_done], g[:j_done])
+        x += Z[:j_done].T @ y
+        if converged:
+            return x, it, hist
+    return x, it, hist
+
+
+def vcycle_iteration(A, b, precond, rtol=1e-9, maxit=500):
+    """Multigrid as a stand-alone solver (Section 4, Table 3):
+    x_{k+1} = x_k + B (b - A x_k) from x_0 = 0, until ||b - A x_k||_2 <= rtol ||b||_2.
+
+    Returns (x, iterations, residual history); None as iterations when the
+    residual grows beyond 1e3 ||b|| (divergence)."""
+    x = np.zeros_like(b)
+    nb = np.linalg.norm(b)
+    hist = [1.0]
+    if nb == 0.0:
+        return x, 0, hist
+    r = b.copy()
+    for it in range(1, maxit + 1):
+        x += precond(r).astype(np.float64)
+        r = b - A @ x
+        rel = np.linalg.norm(r) / nb
+        hist.append(rel)
+        if rel <= rtol:
+            return x, it, hist
+        if rel > 1e3:
+            return x, None, hist
+    return x, maxit, hist

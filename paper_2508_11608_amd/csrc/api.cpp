@@ -76,6 +76,9 @@ struct cmg_problem {
   // multi-column Krylov vectors (kMaxCols columns of the finest level, compact)
   double *mkr = nullptr, *mkz = nullptr, *mkp = nullptr, *mkq = nullptr, *mpart = nullptr;
   double* mpart_host = nullptr;
+  // GMRES basis (restart + 1 rows) and preconditioned basis (restart rows), compact finest level
+  double *gV = nullptr, *gZ = nullptr, *gw = nullptr, *gpart = nullptr, *gpart_host = nullptr;
+  int g_restart = 0;
   // Krylov vectors (compact, finest level)
   double *kr = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr, *part = nullptr;
   double* part_host = nullptr;
@@ -560,6 +563,40 @@ cmg_status dot_cols(cmg_problem* P, const double* x, const double* y, int64_t n,
   return CMG_OK;
 }
 
+// V_j . w for the first m rows of the GMRES basis.
+cmg_status rows_dot(cmg_problem* P, const double* V, const double* w, int64_t n, int m, hipStream_t s,
+                    double* out) {
+  {
+    KTimer t(P, kVector, P->H.cfg.n_levels - 1, s);
+    HIP_TRY(cmg::launch_rows_dot_partial(V, w, n, m, P->gpart, P->nblk, s));
+  }
+  HIP_TRY(hipMemcpyAsync(P->gpart_host, P->gpart, static_cast<size_t>(m) * P->nblk * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int j = 0; j < m; ++j) {
+    double acc = 0.0;
+    for (int i = 0; i < P->nblk; ++i) acc += P->gpart_host[j * P->nblk + i];
+    out[j] = acc;
+  }
+  return CMG_OK;
+}
+
+cmg_status ensure_gmres(cmg_problem* P, int restart) {
+  if (P->g_restart >= restart) return CMG_OK;
+  auto& own = P->owned;
+  const size_t n = static_cast<size_t>(P->H.levels.back().n_dofs);
+  TRY(alloc_zero(own, (restart + 1) * n, &P->gV));
+  TRY(alloc_zero(own, restart * n, &P->gZ));
+  if (!P->gw) TRY(alloc_zero(own, n, &P->gw));
+  TRY(alloc_zero(own, static_cast<size_t>(restart + 1) * P->nblk, &P->gpart));
+  if (P->gpart_host) (void)hipHostFree(P->gpart_host);
+  P->gpart_host = nullptr;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->gpart_host), (restart + 1) * P->nblk * sizeof(double),
+                        hipHostMallocDefault));
+  P->g_restart = restart;
+  return CMG_OK;
+}
+
 // ---- ABI operations in precision T ------------------------------------------
 
 template <typename T>
@@ -744,6 +781,7 @@ void cmg_destroy(cmg_problem* p) {
   for (void* v : p->owned) (void)hipFree(v);
   if (p->part_host) (void)hipHostFree(p->part_host);
   if (p->mpart_host) (void)hipHostFree(p->mpart_host);
+  if (p->gpart_host) (void)hipHostFree(p->gpart_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   delete p;
 }
@@ -915,6 +953,166 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
     rz = rz_new;
   }
   return fail(CMG_ENOTCONV, "CG did not converge within maxit");
+}
+
+cmg_status cmg_gmres(cmg_problem* p, const double* b, double* x, double rtol, int maxit, int restart,
+                     cmg_solve_info* info, void* stream) {
+  TRY(check_device(p));
+  if (!b || !x || !(rtol > 0.0) || maxit < 1 || restart < 1 || restart >= cmg::kMaxRows)
+    return fail(CMG_EINVAL, "bad GMRES arguments (1 <= restart < 64)");
+  TRY(ensure_gmres(p, restart));
+  auto s = static_cast<hipStream_t>(stream);
+  const int L = p->H.cfg.n_levels - 1;
+  const int64_t n = p->H.levels[L].n_dofs;
+  if (info) *info = cmg_solve_info{0, 0.0, 0.0};
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_fill(n, 0.0, x, s));  // x = 0
+  }
+  double bb;
+  TRY(dot(p, b, b, n, s, &bb));
+  const double nb = std::sqrt(bb);
+  if (!std::isfinite(nb)) return fail(CMG_EINVAL, "right-hand side is not finite");
+  if (nb == 0.0) return CMG_OK;
+  double* V = p->gV;
+  double* Z = p->gZ;
+  double* w = p->gw;
+  std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 1),
+      h2(restart + 1);
+  auto Hm = [&](int i, int j) -> double& { return H[i * restart + j]; };
+  int it = 0;
+  while (it < maxit) {
+    // r = b - A x into V_0
+    {
+      TRY(op_apply<double>(p, L, x, w, s));
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_copy(n, b, V, s));
+      HIP_TRY(cmg::launch_axpy(n, -1.0, w, V, s));
+    }
+    double rr;
+    TRY(dot(p, V, V, n, s, &rr));
+    const double beta = std::sqrt(rr);
+    if (beta <= rtol * nb) return CMG_OK;
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_scale(n, 1.0 / beta, V, V, s));
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jdone = 0;
+    bool converged = false;
+    for (int j = 0; j < restart; ++j) {
+      double* Vj = V + static_cast<int64_t>(j) * n;
+      double* Zj = Z + static_cast<int64_t>(j) * n;
+      TRY(vcycle_current(p, Vj, Zj, s));      // z_j = B v_j
+      TRY(op_apply<double>(p, L, Zj, w, s));  // w = A z_j
+      // classical Gram-Schmidt, twice
+      cmg::RowCoef c{};
+      TRY(rows_dot(p, V, w, n, j + 1, s, h.data()));
+      for (int i = 0; i <= j; ++i) c.v[i] = -h[i];
+      {
+        KTimer t(p, kVector, L, s);
+        HIP_TRY(cmg::launch_rows_combine(n, j + 1, c, V, w, s));
+      }
+      TRY(rows_dot(p, V, w, n, j + 1, s, h2.data()));
+      for (int i = 0; i <= j; ++i) {
+        c.v[i] = -h2[i];
+        h[i] += h2[i];
+      }
+      {
+        KTimer t(p, kVector, L, s);
+        HIP_TRY(cmg::launch_rows_combine(n, j + 1, c, V, w, s));
+      }
+      double ww;
+      TRY(dot(p, w, w, n, s, &ww));
+      const double hn = std::sqrt(ww);
+      if (!std::isfinite(hn)) return fail(CMG_EBREAKDOWN, "GMRES breakdown: non-finite Arnoldi vector");
+      if (hn > 0.0) {
+        KTimer t(p, kVector, L, s);
+        HIP_TRY(cmg::launch_scale(n, 1.0 / hn, w, V + static_cast<int64_t>(j + 1) * n, s));
+      }
+      for (int i = 0; i <= j; ++i) Hm(i, j) = h[i];
+      Hm(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
+        const double t1 = cs[i] * Hm(i, j) + sn[i] * Hm(i + 1, j);
+        Hm(i + 1, j) = -sn[i] * Hm(i, j) + cs[i] * Hm(i + 1, j);
+        Hm(i, j) = t1;
+      }
+      const double den = std::hypot(Hm(j, j), Hm(j + 1, j));
+      if (!(den > 0.0)) return fail(CMG_EBREAKDOWN, "GMRES breakdown: singular Hessenberg column");
+      cs[j] = Hm(j, j) / den;
+      sn[j] = Hm(j + 1, j) / den;
+      Hm(j, j) = den;
+      Hm(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jdone = j + 1;
+      const double rel = std::fabs(g[j + 1]) / nb;
+      if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->n_frac = rel > 0.0 ? it * std::log10(rtol) / std::log10(rel) : it;
+      }
+      if (rel <= rtol || it >= maxit) {
+        converged = rel <= rtol;
+        break;
+      }
+    }
+    // x += Z y with H y = g (upper triangular)
+    cmg::RowCoef y{};
+    for (int i = jdone - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k2 = i + 1; k2 < jdone; ++k2) acc -= Hm(i, k2) * y.v[k2];
+      y.v[i] = acc / Hm(i, i);
+    }
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_rows_combine(n, jdone, y, Z, x, s));
+    }
+    if (converged) return CMG_OK;
+  }
+  return fail(CMG_ENOTCONV, "GMRES did not converge within maxit");
+}
+
+cmg_status cmg_vcycle_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
+                            void* stream) {
+  TRY(check_device(p));
+  if (!b || !x || !(rtol > 0.0) || maxit < 1) return fail(CMG_EINVAL, "bad V-cycle solver arguments");
+  auto s = static_cast<hipStream_t>(stream);
+  const int L = p->H.cfg.n_levels - 1;
+  const int64_t n = p->H.levels[L].n_dofs;
+  if (info) *info = cmg_solve_info{0, 0.0, 0.0};
+  {
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_fill(n, 0.0, x, s));    // x = 0
+    HIP_TRY(cmg::launch_copy(n, b, p->kr, s));  // r = b
+  }
+  double bb;
+  TRY(dot(p, b, b, n, s, &bb));
+  const double nb = std::sqrt(bb);
+  if (!std::isfinite(nb)) return fail(CMG_EINVAL, "right-hand side is not finite");
+  if (nb == 0.0) return CMG_OK;
+  for (int it = 1; it <= maxit; ++it) {
+    TRY(vcycle_current(p, p->kr, p->kz, s));  // z = B r
+    TRY(op_apply<double>(p, L, p->kz, p->kq, s));
+    {
+      KTimer t(p, kVector, L, s);
+      HIP_TRY(cmg::launch_axpy(n, 1.0, p->kz, x, s));      // x += z
+      HIP_TRY(cmg::launch_axpy(n, -1.0, p->kq, p->kr, s));  // r -= A z (= b - A x)
+    }
+    double rr;
+    TRY(dot(p, p->kr, p->kr, n, s, &rr));
+    const double rel = std::sqrt(rr) / nb;
+    if (info) {
+      info->iterations = it;
+      info->rel_residual = rel;
+      info->n_frac = rel > 0.0 ? it * std::log10(rtol) / std::log10(rel) : it;
+    }
+    if (rel <= rtol) return CMG_OK;
+    if (!(rel <= 1e3)) return fail(CMG_ENOTCONV, "V-cycle iteration diverges");
+  }
+  return fail(CMG_ENOTCONV, "V-cycle iteration did not converge within maxit");
 }
 
 cmg_status cmg_vcycle_multi(cmg_problem* p, int nrhs, const double* r, double* z, void* stream) {

@@ -52,6 +52,12 @@ struct ColCoef {
   double v[kMaxCols];
 };
 
+constexpr int kMaxRows = 64;  // rows of one row combination (Krylov basis vectors)
+
+struct RowCoef {
+  double v[kMaxRows];
+};
+
 int tables_size(int d, int k);
 
 // Every multigrid launcher works on ncol columns at once (blockIdx.y = column):
@@ -102,6 +108,12 @@ namespace cmg {
 hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s,
                               int ncol = 1);
 hipError_t launch_axpy_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s);
+// part[j * nblk + i]: partial sums of V_j . w for the m rows of V (n entries each)
+hipError_t launch_rows_dot_partial(const double* V, const double* w, int64_t n, int m, double* part, int nblk,
+                                   hipStream_t s);
+// y += sum_{j < m} c.v[j] V_j
+hipError_t launch_rows_combine(int64_t n, int m, const RowCoef& c, const double* V, double* y, hipStream_t s);
+hipError_t launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s);  // y = a x
 hipError_t launch_xpay_cols(int64_t n, const ColCoef& a, const double* x, double* y, int ncol, hipStream_t s);
 hipError_t launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y += a x
 hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStream_t s);   // y = x + a y

@@ -1664,6 +1664,38 @@ __global__ __launch_bounds__(256) void k_xpay(int64_t n, double a, const double*
   if (i < n) y[i] = x[i] + a * y[i];
 }
 
+// part[j * gridDim.x + blockIdx.x]: partial sums of V_j . w for the rows j =
+// blockIdx.y of V (rows of n entries), against one vector w.
+__global__ __launch_bounds__(256) void k_rows_dot_partial(const double* __restrict__ V, const double* __restrict__ w,
+                                                          int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  V += blockIdx.y * n;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += V[i] * w[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// y += sum_{j < m} c.v[j] V_j (rows of n entries), in increasing j.
+__global__ __launch_bounds__(256) void k_rows_combine(int64_t n, int m, RowCoef c, const double* __restrict__ V,
+                                                      double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = y[i];
+  for (int j = 0; j < m; ++j) acc += c.v[j] * V[j * n + i];
+  y[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_scale(int64_t n, double a, const double* __restrict__ x,
+                                               double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
 // Column-wise forms: column c = blockIdx.y of n entries, coefficient a.v[c].
 __global__ __launch_bounds__(256) void k_axpy_cols(int64_t n, ColCoef a, const double* __restrict__ x,
                                                    double* __restrict__ y) {
@@ -1684,6 +1716,25 @@ __global__ __launch_bounds__(256) void k_xpay_cols(int64_t n, ColCoef a, const d
 hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* part, int nblk, hipStream_t s,
                               int ncol) {
   hipLaunchKernelGGL(dev::k_dot_partial, dim3(nblk, ncol), dim3(256), 0, s, x, y, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_dot_partial(const double* V, const double* w, int64_t n, int m, double* part, int nblk,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(dev::k_rows_dot_partial, dim3(nblk, m), dim3(256), 0, s, V, w, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_combine(int64_t n, int m, const RowCoef& c, const double* V, double* y, hipStream_t s) {
+  if (n == 0 || m == 0) return hipSuccess;
+  if (m > kMaxRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dev::k_rows_combine, dim3((n + 255) / 256), dim3(256), 0, s, n, m, c, V, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::k_scale, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, y);
   return hipGetLastError();
 }
 

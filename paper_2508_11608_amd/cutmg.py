@@ -58,7 +58,7 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured", "cmg_rhs_fourier",
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
-            "cmg_vcycle_multi", "cmg_solve_multi"]
+            "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve"]
 
 _lib = None
 
@@ -86,6 +86,8 @@ def load_library():
         "cmg_vcycle": [P, V, V, V],
         "cmg_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_vcycle_multi": [P, I, V, V, V],
+        "cmg_gmres": [P, V, V, D, I, I, ctypes.POINTER(SolveInfo), V],
+        "cmg_vcycle_solve": [P, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_solve_multi": [P, I, V, V, D, I, ctypes.POINTER(SolveInfo), V],
         "cmg_rhs_manufactured": [P, ctypes.POINTER(ctypes.c_double)],
         "cmg_rhs_fourier": [P, I, V, V, V, ctypes.POINTER(ctypes.c_double)],
@@ -231,6 +233,28 @@ class Problem:
         n = self.ndofs(None)
         info = SolveInfo()
         st = _lib.cmg_solve(self._h, _dev(b, n), _dev(x, n), rtol, maxit, ctypes.byref(info), _stream())
+        if raise_on_fail:
+            _check(st)
+        return x, {"iterations": info.iterations, "rel_residual": info.rel_residual, "n_frac": info.n_frac,
+                   "status": st}
+
+    def gmres(self, b, x=None, rtol=1e-9, maxit=500, restart=30, raise_on_fail=True):
+        """Right-preconditioned restarted GMRES with the V-cycle (cmg_gmres)."""
+        x = self._empty(None) if x is None else x
+        n = self.ndofs(None)
+        info = SolveInfo()
+        st = _lib.cmg_gmres(self._h, _dev(b, n), _dev(x, n), rtol, maxit, restart, ctypes.byref(info), _stream())
+        if raise_on_fail:
+            _check(st)
+        return x, {"iterations": info.iterations, "rel_residual": info.rel_residual, "n_frac": info.n_frac,
+                   "status": st}
+
+    def vcycle_solve(self, b, x=None, rtol=1e-9, maxit=500, raise_on_fail=True):
+        """The V-cycle as a stand-alone iterative solver (cmg_vcycle_solve)."""
+        x = self._empty(None) if x is None else x
+        n = self.ndofs(None)
+        info = SolveInfo()
+        st = _lib.cmg_vcycle_solve(self._h, _dev(b, n), _dev(x, n), rtol, maxit, ctypes.byref(info), _stream())
         if raise_on_fail:
             _check(st)
         return x, {"iterations": info.iterations, "rel_residual": info.rel_residual, "n_frac": info.n_frac,

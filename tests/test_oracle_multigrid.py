@@ -8,7 +8,7 @@ import scipy.sparse.linalg as spl
 import workloads as W
 from oracle import problem
 from oracle.assemble import l2_error
-from oracle.multigrid import Hierarchy, pcg
+from oracle.multigrid import Hierarchy, gmres, pcg, vcycle_iteration
 
 
 def _hier(w, L=None, gamma_g=None):
@@ -159,3 +159,68 @@ def test_l2_convergence_rate(k):
         x, _, _ = pcg(mats[-1], b, H.vcycle, rtol=1e-11)
         errs.append(l2_error(levels[-1], problem.shapes_of(w), problem.form_params(w), x, u))
     assert math.log2(errs[0] / errs[1]) >= k + 0.8
+
+
+# ---- outer solvers of the paper's tables: GMRES and the V-cycle iteration ----
+
+def test_gmres_matches_an_independent_implementation():
+    """The oracle's right-preconditioned restarted GMRES against SciPy's GMRES
+    (an independent implementation) on a non-symmetric system: the same number
+    of inner iterations and the same residual to a few digits."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(0)
+    n = 60
+    A = sp.csr_matrix(4.0 * np.eye(n) + 0.3 * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n)
+    x, it, hist = gmres(A, b, lambda v: v, rtol=1e-10, restart=10, maxit=200)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    xs, info = spl.gmres(A, b, rtol=1e-10, restart=10, maxiter=200, callback=cb, callback_type="pr_norm")
+    assert info == 0 and it == count[0]
+    rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert rel <= 1e-10 and abs(rel / (np.linalg.norm(b - A @ xs) / np.linalg.norm(b)) - 1) < 1e-3
+    assert all(h1 >= h2 - 1e-15 for h1, h2 in zip(hist, hist[1:]))  # the GMRES residual never grows
+
+
+def test_gmres_with_exact_preconditioner_takes_one_step(disc3):
+    w, levels, mats, _, _ = disc3
+    A = mats[-1].tocsc()
+    b = problem.rhs(w, levels[-1])
+    lu = spl.splu(A)
+    x, it, _ = gmres(A, b, lu.solve, rtol=1e-12)
+    assert it == 1
+    assert np.abs(x - lu.solve(b)).max() <= 1e-10 * np.abs(x).max()
+
+
+def test_gmres_vcycle_solves_the_cutfem_system(disc3):
+    w, levels, mats, _, H = disc3
+    A = mats[-1]
+    b = problem.rhs(w, levels[-1])
+    x, it, _ = gmres(A, b, H.vcycle, rtol=1e-9)
+    xd = spl.spsolve(A.tocsc(), b)
+    assert 1 <= it <= 30
+    assert np.linalg.norm(b - A @ x) <= 1e-9 * np.linalg.norm(b) * 1.0000001
+    assert np.abs(x - xd).max() <= 1e-6 * np.abs(xd).max()
+
+
+def test_vcycle_iteration_closed_form():
+    """x_k of the stand-alone V-cycle is sum_{i<k} (I - B A)^i B b: the V-cycle
+    is a linear map, so its dense matrix B (columns B e_j) gives the closed form."""
+    w, levels, mats, prols, H = _hier(W.disc_q2(), L=2)
+    A = mats[-1].toarray()
+    n = A.shape[0]
+    B = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    b = problem.rhs(w, levels[-1])
+    M = np.eye(n) - B @ A
+    xk = np.zeros(n)
+    term = B @ b
+    for _ in range(3):
+        xk += term
+        term = M @ term
+    x3, it, _ = vcycle_iteration(mats[-1], b, H.vcycle, rtol=0.0, maxit=3)
+    assert it == 3
+    assert np.abs(x3 - xk).max() <= 1e-12 * np.abs(xk).max()

@@ -95,6 +95,15 @@ def sphere_union_8(k: int = 3, n_levels: int = 5, seed: int = 0) -> Workload:
                     semi=tuple((float(r),) * 3 for r in radii))
 
 
+def paper_circle(k: int, L: int, n_c: int = 2) -> Workload:
+    """The paper's 2-D protocol: circle of radius 1 around the origin in the box
+    [-1.105, 1.105]^2 (the half-width that reproduces the paper's DoF counts),
+    2x2 coarsest cells, finest level L (2^(L+1) cells per direction), n_c sweeps
+    over the cut patches."""
+    return Workload(f"circle-paper-Q{k}-L{L}-nc{n_c}", 2, k, L + 1, coarse_cells=2, lo=-1.105, hi=1.105,
+                    centers=((0.0, 0.0),), semi=((1.0, 1.0),), n_c=n_c)
+
+
 def random_vector(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     """Seeded standard-normal test vector(s), float64, shape (n,) or (nrhs, n)."""
     rng = np.random.default_rng(seed)
