@@ -71,6 +71,8 @@ typedef struct {
   int n_c;               /* sweeps over the cut patches per smoothing step (eq. (smoother-split)) */
   int quad_n;            /* Gauss points per smooth piece of a cut-cell rule (e.g. 14) */
   int precond_fp32;      /* 1: the V-cycle runs in FP32 (see cmg_set_precision) */
+  double gamma_m[3];     /* ghost penalty of derivative order m = 1, 2, 3 (the paper tunes them one by one,
+                            Section 4); an entry <= 0 means gamma_g */
 } cmg_params;
 
 typedef struct {

@@ -11,7 +11,9 @@ with F_G the faces between two active cells of which at least one is cut.
 Readings (the paper prints the ghost scaling as h_F^{2k+1} with the sum from 0):
   * e(m) = 2m - 1 (stiffness scaling, mode 0) or 2m + 1 (as printed, mode 1);
   * the m = 0 jump of a continuous function vanishes and is dropped;
-  * gamma_m = gamma_g for all m; h = h_F = h_l is the cell side length.
+  * gamma_m = gamma_g for all m unless given per order (the paper tunes
+    gamma_1, gamma_2, gamma_3 one by one, Section 4); h = h_F = h_l is the
+    cell side length.
 Load vector (paper eq. (weak-equation) plus the symmetric Nitsche terms for
 non-zero Dirichlet data g):  b_i = (f, phi_i)_Omega + (g, (gamma_D/h) phi_i - d_n phi_i)_Gamma.
 
@@ -40,6 +42,10 @@ class FormParams:
     quad_n: int = 14        # Gauss points per smooth piece of a cut-cell rule
     quad_beta: float = 0.35  # subdivision threshold of the cut-cell rule
     union_depth: int = 4     # bisection depth of cells crossed by several surfaces
+    gamma_m: tuple = ()      # per derivative order m = 1..; overrides gamma_g where given and > 0
+
+    def gamma(self, m: int) -> float:
+        return self.gamma_m[m - 1] if len(self.gamma_m) >= m and self.gamma_m[m - 1] > 0 else self.gamma_g
 
 
 def tensor_gauss_ref(d: int, n: int):
@@ -98,7 +104,7 @@ def ghost_face_matrix(k: int, d: int, h: float, direction: int, fp: FormParams) 
     G = np.zeros((2 * n_loc, 2 * n_loc))
     for m in range(1, k + 1):
         expo = 2 * m - 1 if fp.ghost_exp_mode == 0 else 2 * m + 1
-        coef = fp.gamma_g * h ** expo / math.factorial(m) ** 2
+        coef = fp.gamma(m) * h ** expo / math.factorial(m) ** 2
         J = np.zeros((P, 2 * n_loc))
         for side, xn in ((0, 1.0), (1, 0.0)):
             vals = np.ones((P, n_loc))

@@ -16,7 +16,7 @@ def shapes_of(w) -> list:
 
 
 def form_params(w) -> FormParams:
-    return FormParams(gamma_D=w.gamma_D, gamma_g=w.gamma_g, ghost_exp_mode=w.ghost_exp_mode)
+    return FormParams(gamma_D=w.gamma_D, gamma_g=w.gamma_g, ghost_exp_mode=w.ghost_exp_mode, gamma_m=tuple(w.gamma_m))
 
 
 def manufactured(dim: int):

@@ -732,6 +732,7 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
   if (cfg.shapes.size() > 16) return fail(CMG_EINVAL, "at most 16 shapes");
   cfg.gamma_D = prm->gamma_D;
   cfg.gamma_g = prm->gamma_g;
+  for (int m = 0; m < 3; ++m) cfg.gamma_m[m] = prm->gamma_m[m];
   cfg.ghost_exp_mode = prm->ghost_exp_mode;
   cfg.n_c = prm->n_c;
   cfg.quad_n = prm->quad_n;

@@ -30,6 +30,8 @@ struct Config {
   double lo = -1.0, hi = 1.0;
   std::vector<Shape> shapes;
   double gamma_D = 120.0, gamma_g = 0.1;
+  double gamma_m[3] = {0.0, 0.0, 0.0};  // per derivative order; <= 0: gamma_g
+  double gamma(int m) const { return gamma_m[m - 1] > 0.0 ? gamma_m[m - 1] : gamma_g; }
   int ghost_exp_mode = 0;     // 0: h^(2m-1), 1: h^(2m+1)
   int n_c = 2;
   int quad_n = 14;            // Gauss points per smooth piece of a cut-cell rule

@@ -458,7 +458,7 @@ void ghost_face_matrix(const Config& cfg, const Basis1D& B, double h, int dir, s
     const int expo = cfg.ghost_exp_mode == 0 ? 2 * m - 1 : 2 * m + 1;
     double fact = 1.0;
     for (int i = 2; i <= m; ++i) fact *= i;
-    const double c = cfg.gamma_g * std::pow(h, expo - 2 * m + d - 1) / (fact * fact);
+    const double c = cfg.gamma(m) * std::pow(h, expo - 2 * m + d - 1) / (fact * fact);
     for (int sa = 0; sa < 2; ++sa)
       for (int a = 0; a < nl; ++a)
         for (int sb = 0; sb < 2; ++sb)
@@ -536,7 +536,7 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
         const int expo = cfg.ghost_exp_mode == 0 ? 2 * m - 1 : 2 * m + 1;
         double fact = 1.0;
         for (int i = 2; i <= m; ++i) fact *= i;
-        T.gcoef[m - 1] = cfg.gamma_g * std::pow(L.h, expo - 2 * m + d - 1) / (fact * fact);
+        T.gcoef[m - 1] = cfg.gamma(m) * std::pow(L.h, expo - 2 * m + d - 1) / (fact * fact);
       }
       // fast diagonalisation of the Cartesian patch Laplacian: 1-D patch matrices on
       // two cells, internal nodes 1..2k-1

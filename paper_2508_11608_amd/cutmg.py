@@ -35,7 +35,8 @@ class LevelSet(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("n_levels", ctypes.c_int), ("coarse_cells", ctypes.c_int),
                 ("gamma_D", ctypes.c_double), ("gamma_g", ctypes.c_double), ("ghost_exp_mode", ctypes.c_int),
-                ("n_c", ctypes.c_int), ("quad_n", ctypes.c_int), ("precond_fp32", ctypes.c_int)]
+                ("n_c", ctypes.c_int), ("quad_n", ctypes.c_int), ("precond_fp32", ctypes.c_int),
+                ("gamma_m", ctypes.c_double * 3)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -147,8 +148,7 @@ class Problem:
         self._centers = (ctypes.c_double * (len(workload.centers) * d))(*[v for c in workload.centers for v in c])
         self._semi = (ctypes.c_double * (len(workload.semi) * d))(*[v for s in workload.semi for v in s])
         ls = LevelSet(d, len(workload.centers), self._centers, self._semi, workload.lo, workload.hi)
-        prm = Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
-                     workload.ghost_exp_mode, workload.n_c, quad_n, int(bool(fp32)))
+        prm = _params(workload, quad_n, fp32)
         h = ctypes.c_void_p()
         fn = lib.cmg_setup if device else lib.cmg_setup_host
         _check(fn(ctypes.byref(ls), ctypes.byref(prm), ctypes.byref(h)))
@@ -341,9 +341,14 @@ def _levelset_params(workload, quad_n=14, fp32=False):
     centers = (ctypes.c_double * (len(workload.centers) * d))(*[v for c in workload.centers for v in c])
     semi = (ctypes.c_double * (len(workload.semi) * d))(*[v for s in workload.semi for v in s])
     ls = LevelSet(d, len(workload.centers), centers, semi, workload.lo, workload.hi)
-    prm = Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
-                 workload.ghost_exp_mode, workload.n_c, quad_n, int(bool(fp32)))
+    prm = _params(workload, quad_n, fp32)
     return ls, prm, (centers, semi)
+
+
+def _params(workload, quad_n=14, fp32=False):
+    gm = (ctypes.c_double * 3)(*(list(workload.gamma_m) + [0.0] * 3)[:3])
+    return Params(workload.k, workload.n_levels, workload.coarse_cells, workload.gamma_D, workload.gamma_g,
+                  workload.ghost_exp_mode, workload.n_c, quad_n, int(bool(fp32)), gm)
 
 
 class Server:

@@ -28,10 +28,15 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(EXPORTED)
 
 
+def _per_order_ghost():
+    w = W.offcentre_disc(3, 3)
+    return W.Workload(**{**w.__dict__, "name": "disc-off-Q3-gamma-m", "gamma_m": (0.07, 0.12, 0.05)})
+
+
 def _workloads():
     return [W.disc_q2(), W.offcentre_disc(3, 3), W.offcentre_disc(1, 4), W.ellipse(2, 3),
             W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2),
-            W.disc_union(2, 3), W.ball_union(2, 2), W.sphere_union_8(2, 2)]
+            W.disc_union(2, 3), W.ball_union(2, 2), W.sphere_union_8(2, 2), _per_order_ghost()]
 
 
 @pytest.fixture(scope="module", params=_workloads(), ids=lambda w: w.name)

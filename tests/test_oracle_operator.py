@@ -138,3 +138,19 @@ def test_cartesian_patch_is_kronecker_sum():
     K1, M1 = K1[1:-1, 1:-1], M1[1:-1, 1:-1]
     ref = (np.kron(M1, np.kron(M1, K1)) + np.kron(M1, np.kron(K1, M1)) + np.kron(K1, np.kron(M1, M1)))
     assert np.abs(cartesian_patch_laplacian(k, d, h) - ref).max() < 1e-13
+
+
+def test_ghost_orders_take_their_own_parameter():
+    """Q2, 2-D, per-order parameters (gamma_1, gamma_2): a kink u = |x - x_F| only
+    has a first-derivative jump and sees gamma_1 alone (u^T G u = gamma_1 h 4 h),
+    the C^1 function (x - x_F)^2 on T2 only sees gamma_2 alone
+    (u^T G u = gamma_2 h^3 / 4 * 4 h); gamma_g is then irrelevant."""
+    h = 0.25
+    fp = FormParams(gamma_D=120, gamma_g=0.5, gamma_m=(0.07, 0.13))
+    G = ghost_face_matrix(2, 2, h, 0, fp)
+    xi = gll_nodes(2)
+    kink = np.concatenate([np.array([(1 - xi[i]) * h for j in range(3) for i in range(3)]),
+                           np.array([xi[i] * h for j in range(3) for i in range(3)])])
+    assert abs(kink @ G @ kink - 0.07 * h * 4 * h) < 1e-14
+    c1 = np.concatenate([np.zeros(9), np.array([(xi[i] * h) ** 2 for j in range(3) for i in range(3)])])
+    assert abs(c1 @ G @ c1 - 0.13 * h ** 3 / 4 * 4 * h) < 1e-14

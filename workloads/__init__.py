@@ -26,6 +26,7 @@ class Workload:
     centers: tuple = ()         # one tuple of length dim per shape
     semi: tuple = ()            # semi-axes per shape (all equal for a sphere)
     gamma_g: float = 0.1        # ghost penalty for every derivative order
+    gamma_m: tuple = ()         # per derivative order m = 1.. (overrides gamma_g where given)
     ghost_exp_mode: int = 0     # 0: h^(2m-1) scaling, 1: h^(2m+1)
     n_c: int = 2                # sweeps over the cut patches per smoothing step
     rhs: str = "manufactured"   # "manufactured" (u = prod sin(pi x_j)) or "fourier"
