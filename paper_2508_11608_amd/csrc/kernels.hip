@@ -475,6 +475,8 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   __shared__ T ra[PPB][NP];
   __shared__ T rb[PPB][NP];
   __shared__ int64_t pbase[PPB];  // lattice index of each patch's closure corner (-1: no patch)
+  constexpr int NPAIR = Pow<2 * K, D>::v;  // (node, cell) pairs of a patch, as in the cut-patch step
+  __shared__ T parts[PPB][NPAIR];
   load_tables<D, K>(L.tables, tab, S::T_SIZE);
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   b += blockIdx.y * L.n_nodes;
@@ -542,43 +544,66 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   if (active) {
     node = pbase[p] + ioff;
     bnode = b[node];
-    // residual with the Cartesian stiffness: cells of the patch containing the node
-    int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      if (pi[a] == K) { cc[a][0] = 0; lc[a][0] = K; cc[a][1] = 1; lc[a][1] = 0; nc[a] = 2; }
-      else if (pi[a] < K) { cc[a][0] = 0; lc[a][0] = pi[a]; }
-      else { cc[a][0] = 1; lc[a][0] = pi[a] - K; }
-    }
-    T ax = 0;
-    const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
-    for (int comb = 0; comb < ncomb; ++comb) {
-      int c[3], il[3];
-      int r = comb;
+  }
+  // residual with the Cartesian stiffness, split into (node, cell) pairs: along
+  // each direction a node at patch coordinate p in 1..2k-1 lies in cell layer 0
+  // (p <= k) and/or 1 (p >= k), 2k choices per direction; one pair is one row
+  // of the cell stiffness times the cell's x
+  for (int t = threadIdx.x; t < PPB * NPAIR; t += blockDim.x) {
+    const int pp = t / NPAIR, tt = t % NPAIR;
+    if (gp0 + pp >= nv) continue;
+    int il[3], c[3];
+    {
+      int r = tt;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const int s = r % nc[a];
-        r /= nc[a];
-        c[a] = cc[a][s];
-        il[a] = lc[a][s];
+        const int j = r % (2 * K);
+        r /= 2 * K;
+        c[a] = j >= K ? 1 : 0;
+        il[a] = (j < K ? j + 1 : j) - K * c[a];
       }
-      int iloc = il[0] + N1 * il[1];
-      if (D == 3) iloc += N1 * N1 * il[2];
-      const double* row = tab + S::T_KCELL + iloc * NL;
-      int qb = K * c[0] + NC1 * K * c[1];
-      if (D == 3) qb += NC1 * NC1 * K * c[2];
-      constexpr int NRW = N1 * (D == 3 ? N1 : 1);
-      T acc[NRW];
+    }
+    int iloc = il[0] + N1 * il[1];
+    if (D == 3) iloc += N1 * N1 * il[2];
+    const double* row = tab + S::T_KCELL + iloc * NL;
+    int qb = K * c[0] + NC1 * K * c[1];
+    if (D == 3) qb += NC1 * NC1 * K * c[2];
+    constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+    T acc[NRW];
 #pragma unroll
-      for (int a = 0; a < NRW; ++a) acc[a] = 0;
+    for (int a = 0; a < NRW; ++a) acc[a] = 0;
 #pragma unroll
-      for (int bq = 0; bq < NL; ++bq) {
-        const int b0 = bq % N1, b12 = bq / N1;
-        const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
-        acc[b12] += (T)row[bq] * xs[p][q];
+    for (int bq = 0; bq < NL; ++bq) {
+      const int b0 = bq % N1, b12 = bq / N1;
+      const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
+      acc[b12] += (T)row[bq] * xs[pp][q];
+    }
+    T part = 0;
+#pragma unroll
+    for (int a = 0; a < NRW; ++a) part += acc[a];
+    parts[pp][tt] = part;
+  }
+  __syncthreads();
+  if (active) {
+    // the node's pairs in increasing pair index
+    int jlo[3], jn[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      jlo[a] = pi[a] <= K ? pi[a] - 1 : pi[a];
+      jn[a] = pi[a] == K ? 2 : 1;
+    }
+    T ax = 0;
+    const int ncomb = jn[0] * jn[1] * (D == 3 ? jn[2] : 1);
+    for (int comb = 0; comb < ncomb; ++comb) {
+      int t = 0, r = comb, st = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int sel = r % jn[a];
+        r /= jn[a];
+        t += (jlo[a] + sel) * st;
+        st *= 2 * K;
       }
-#pragma unroll
-      for (int a = 0; a < NRW; ++a) ax += acc[a];
+      ax += parts[p][t];
     }
     ra[p][i] = bnode - ax;
   }
