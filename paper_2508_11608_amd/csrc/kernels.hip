@@ -998,9 +998,22 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   const T ax = cut_patch_ax<D, K, T>(L, nj, V, pi, x, sm);
   if (tid < nj) rs[tid] = bval - ax;
   __syncthreads();
-  // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric);
-  // eight independent loads in flight per step (blockDim >= NP >= nj)
+  // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
+  // (blockDim >= NP >= nj).  Small patches issue all loads of the row at once,
+  // larger ones eight at a time.
   const T* inv = G.inv_t<T>() + G.inv_off[gp];
+  if constexpr (S::NP <= 32) {
+    if (tid < nj) {
+      T v[S::NP];
+#pragma unroll
+      for (int j = 0; j < S::NP; ++j) v[j] = j < nj ? inv[(int64_t)j * nj + tid] : (T)0;
+      T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j < nj ? j : 0];
+      dbuf[off + tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+    return;
+  }
   if (tid < nj) {
     const int i = tid;
     T acc[8];
