@@ -31,7 +31,7 @@ def _run(cmd):
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compile and link libcutmg.so to `out`; `defines` are extra -D flags for
-    the kernels (tuning constants)."""
+    every source (tuning switches)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     with tempfile.TemporaryDirectory(prefix="cutmg_build_") as tmp:
         objs = []
@@ -41,7 +41,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
             # no FMA contraction on the host: quadrature decisions (box classification,
             # subdivision) then round like the plain IEEE arithmetic of the checking code
             cmd = [hipcc, "-x", "c++", *COMMON, "-ffp-contract=off", "-fopenmp", "-D__HIP_PLATFORM_AMD__",
-                   "-I/opt/rocm/include", "-c",
+                   "-I/opt/rocm/include", *[f"-D{d}" for d in defines], "-c",
                    os.path.join(SRC, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
             objs.append(obj)

@@ -200,6 +200,8 @@ __device__ void load_tables(const double* __restrict__ g, double* s, int n) {
 // tangential face nodes b_t, contracted with the reference face mass:
 // W_m(i_t) = sum_{b_t} prod_j Mhat[i_t,j, b_t,j] J_m(b_t).  A row of a node i of
 // a cell adjacent to the face then only needs gc_m * trace_m(i_dir) * W_m(i_t).
+// One thread per face and column: the 2 (k+1) nodes along the normal at each
+// tangential node are read once for all k orders.
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ x, T* __restrict__ W) {
   using S = Shape<D, K>;
@@ -207,10 +209,8 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   constexpr int NT = Pow<N1, D - 1>::v;
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   W += blockIdx.y * L.n_faces * K * NT;
-  const int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (task >= L.n_faces * K) return;
-  const int64_t f = task / K;
-  const int m = static_cast<int>(task % K);
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= L.n_faces) return;
   const double* mh = L.tables + S::T_MHAT;
   const double* d0 = L.tables + S::T_D0;
   const double* d1 = L.tables + S::T_D1;
@@ -221,57 +221,71 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
 #pragma unroll
     for (int a = 0; a < D; ++a) { c[a] = static_cast<int>(r % L.N); r /= L.N; }
   }
-  T J[NT];
-#pragma unroll
-  for (int bt = 0; bt < NT; ++bt) {
-    int I[3];
-    int rb = bt;
+  // first node of the lower cell and the lattice strides
+  int64_t base = 0, sn = 1, st0 = 0, st1 = 0;
+  {
+    int64_t sa = 1;
+    int tb = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      if (a == dir) continue;
-      I[a] = K * c[a] + rb % N1;
-      rb /= N1;
+      base += K * c[a] * sa;
+      if (a == dir) sn = sa;
+      else if (tb++ == 0) st0 = sa;
+      else st1 = sa;
+      sa *= L.nn;
     }
-    T acc = 0;
+  }
+  T J[K][NT];
+#pragma unroll
+  for (int bt = 0; bt < NT; ++bt) {
+    const int64_t el = base + (bt % N1) * st0 + (D == 3 ? (bt / N1) * st1 : 0);
+    T xl[N1], xu[N1];
 #pragma unroll
     for (int bd = 0; bd <= K; ++bd) {
-      I[dir] = K * c[dir] + bd;
-      const T xl = x[lat(D, L.nn, I)];
-      I[dir] += K;
-      acc += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * x[lat(D, L.nn, I)];
+      xl[bd] = x[el + bd * sn];
+      xu[bd] = x[el + (bd + K) * sn];
     }
-    J[bt] = acc;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      T acc = 0;
+#pragma unroll
+      for (int bd = 0; bd <= K; ++bd) acc += (T)d1[m * N1 + bd] * xl[bd] - (T)d0[m * N1 + bd] * xu[bd];
+      J[m][bt] = acc;
+    }
   }
-  T* out = W + (f * K + m) * NT;
-  if (D == 2) {
 #pragma unroll
-    for (int it = 0; it < N1; ++it) {
-      T acc = 0;
+  for (int m = 0; m < K; ++m) {
+    T* out = W + (f * K + m) * NT;
+    if (D == 2) {
 #pragma unroll
-      for (int bt = 0; bt < N1; ++bt) acc += (T)mh[it * N1 + bt] * J[bt];
-      out[it] = acc;
+      for (int it = 0; it < N1; ++it) {
+        T acc = 0;
+#pragma unroll
+        for (int bt = 0; bt < N1; ++bt) acc += (T)mh[it * N1 + bt] * J[m][bt];
+        out[it] = acc;
+      }
+      continue;
     }
-    return;
+    T H[NT];  // (Mhat x Mhat) J by two 1-D contractions
+#pragma unroll
+    for (int b1 = 0; b1 < N1; ++b1)
+#pragma unroll
+      for (int i0 = 0; i0 < N1; ++i0) {
+        T acc = 0;
+#pragma unroll
+        for (int b0 = 0; b0 < N1; ++b0) acc += (T)mh[i0 * N1 + b0] * J[m][b0 + N1 * b1];
+        H[i0 + N1 * b1] = acc;
+      }
+#pragma unroll
+    for (int i1 = 0; i1 < N1; ++i1)
+#pragma unroll
+      for (int i0 = 0; i0 < N1; ++i0) {
+        T acc = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < N1; ++b1) acc += (T)mh[i1 * N1 + b1] * H[i0 + N1 * b1];
+        out[i0 + N1 * i1] = acc;
+      }
   }
-  T H[NT];  // (Mhat x Mhat) J by two 1-D contractions
-#pragma unroll
-  for (int b1 = 0; b1 < N1; ++b1)
-#pragma unroll
-    for (int i0 = 0; i0 < N1; ++i0) {
-      T acc = 0;
-#pragma unroll
-      for (int b0 = 0; b0 < N1; ++b0) acc += (T)mh[i0 * N1 + b0] * J[b0 + N1 * b1];
-      H[i0 + N1 * b1] = acc;
-    }
-#pragma unroll
-  for (int i1 = 0; i1 < N1; ++i1)
-#pragma unroll
-    for (int i0 = 0; i0 < N1; ++i0) {
-      T acc = 0;
-#pragma unroll
-      for (int b1 = 0; b1 < N1; ++b1) acc += (T)mh[i1 * N1 + b1] * H[i0 + N1 * b1];
-      out[i0 + N1 * i1] = acc;
-    }
 }
 
 template <int D, int K>
@@ -1531,8 +1545,8 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     if (L.n_faces > 0) {
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces * K.value), ncol), dim3(256), 0,
-                         s, L, x, W);
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s, L, x,
+                         W);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -1573,8 +1587,8 @@ hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDe
   if (!G.inv_tiles || !G.tile_off || ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
   return dispatch(d, k, [&](auto D, auto K) {
     if (L.n_faces > 0) {  // ghost-face jumps of the current x, all columns
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, float>), dim3(blocks(L.n_faces * K.value), ncol),
-                         dim3(256), 0, s, L, x, W);
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, float>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s,
+                         L, x, W);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
