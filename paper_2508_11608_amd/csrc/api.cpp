@@ -47,6 +47,7 @@ struct Vecs {
   T* r = nullptr;
   T* dbuf = nullptr;  // cut-patch corrections of one colour
   T* W = nullptr;     // ghost-face jumps of the operator kernel
+  T* C = nullptr;     // cut-cell products of the operator kernel
 };
 
 struct DevLevel {
@@ -210,6 +211,15 @@ cmg_status upload_all(cmg_problem* P) {
     k.cell_faces = cfaces;
     k.n_tiles = static_cast<int>(h.tiles.size());
     k.tiles = tiles;
+    {
+      std::vector<int32_t> cc(static_cast<size_t>(h.n_cut));
+      for (size_t c = 0; c < h.cut_id.size(); ++c)
+        if (h.cut_id[c] >= 0) cc[h.cut_id[c]] = static_cast<int32_t>(c);
+      int32_t* dcc;
+      TRY(upload(own, cc, &dcc));
+      k.n_cut = h.n_cut;
+      k.cut_cells = dcc;
+    }
     d.kl32 = k;
     d.kl32.cut_mats = nullptr;
     TRY(alloc_zero(own, h.n_nodes, &d.v64.x));
@@ -217,6 +227,8 @@ cmg_status upload_all(cmg_problem* P) {
     TRY(alloc_zero(own, h.n_nodes, &d.v64.r));
     d.n_w = h.face_lower.size() * static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
     TRY(alloc_zero(own, d.n_w, &d.v64.W));
+    const size_t n_c_entries = static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+    TRY(alloc_zero(own, n_c_entries, &d.v64.C));
     for (int c = 0; c < 8; ++c) {
       TRY(upload(own, h.int_vertex[c], &d.int_verts[c]));
       d.n_int[c] = static_cast<int>(h.int_vertex[c].size());
@@ -274,6 +286,8 @@ cmg_status ensure_fp32(cmg_problem* P) {
     TRY(alloc_zero(own, h.n_nodes, &d.v32.b));
     TRY(alloc_zero(own, h.n_nodes, &d.v32.r));
     TRY(alloc_zero(own, d.n_w, &d.v32.W));
+    TRY(alloc_zero(own, static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim)),
+                   &d.v32.C));
     TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v32.dbuf));
   }
   TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
@@ -298,6 +312,8 @@ cmg_status ensure_multi(cmg_problem* P) {
     TRY(alloc_zero(own, C * h.n_nodes, &v.b));
     TRY(alloc_zero(own, C * h.n_nodes, &v.r));
     TRY(alloc_zero(own, C * d.n_w, &v.W));
+    TRY(alloc_zero(own, C * static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim)),
+                   &v.C));
     TRY(alloc_zero(own, C * static_cast<size_t>(d.max_cut_nodes), &v.dbuf));
   }
   if (!P->mkr) {
@@ -476,8 +492,8 @@ template <typename T>
 cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStream_t s, int ncol = 1,
                      bool multi = false) {
   KTimer t(P, kApply, l, s);
-  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], multi).W, s,
-                               ncol));
+  HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], multi).W,
+                               work<T>(P->lv[l], multi).C, s, ncol));
   return CMG_OK;
 }
 
@@ -827,7 +843,10 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
     }
     b64 += 8 * maxn;
     b32 += 4 * maxn;
-    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn;
+    const size_t ncc = static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+    b64 += 8 * ncc;  // cut-cell products of the operator
+    b32 += 4 * ncc;
+    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc;
     m64 += 8 * C * per_col;
     m32 += 4 * C * per_col;
   }

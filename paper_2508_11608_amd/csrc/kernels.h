@@ -16,7 +16,9 @@ struct KLevel {
   const uint8_t* flags;      // per cell: bit 0 active, bit 1 cut
   const int32_t* cut_id;     // per cell: index of its cut-cell matrix or -1
   const uint8_t* ghost;      // per cell: bit 2*dir+side marks a ghost face
-  const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path
+  const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path (symmetric)
+  int64_t n_cut;             // cut cells
+  const int32_t* cut_cells;  // background cell of every cut cell
   const int32_t* dof_node;   // lattice node of each DoF, ascending
   const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
   int64_t n_faces;           // ghost faces
@@ -67,9 +69,10 @@ int tables_size(int d, int k);
 // compact (DoF-ordered) vectors ncol blocks of n entries.
 
 // y = A x (b == nullptr) or y = b - A x on every active node; W is the work
-// buffer for the ghost-face jumps.
+// buffer for the ghost-face jumps, C the one for the cut-cell products
+// (n_cut (k+1)^d entries per column).
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s,
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, T* C, hipStream_t s,
                         int ncol = 1);
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,

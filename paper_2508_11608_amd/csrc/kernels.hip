@@ -288,6 +288,45 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   }
 }
 
+// Cut-cell pre-pass of the operator: C_T = E_T x_T for every cut cell T (one
+// block per cut cell and column), so that the operator rows only add one value
+// per cut cell.  E_T is symmetric, so thread i reads column i of the row-major
+// matrix, and consecutive threads read consecutive entries.
+template <int D, int K, typename T>
+__global__ __launch_bounds__(64) void k_cut_cell_ax(KLevel L, const T* __restrict__ x, T* __restrict__ C) {
+  using S = Shape<D, K>;
+  constexpr int N1 = S::N1, NL = S::NL;
+  static_assert(NL <= 64, "one thread per cell node");
+  __shared__ T xs[NL];
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  C += blockIdx.y * L.n_cut * NL;
+  const int64_t t = blockIdx.x;
+  const int i = threadIdx.x;
+  if (i < NL) {
+    int64_t r = L.cut_cells[t];
+    int I[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      I[a] = K * static_cast<int>(r % L.N);
+      r /= L.N;
+    }
+    int q = i;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      I[a] += q % N1;
+      q /= N1;
+    }
+    xs[i] = x[lat(D, L.nn, I)];
+  }
+  __syncthreads();
+  if (i >= NL) return;
+  const T* E = L.cut_mats_t<T>() + t * NL * NL + i;
+  T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < NL; ++j) acc[j % 4] += E[j * NL] * xs[j];
+  C[t * NL + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 template <int D, int K>
 struct ApplyShape {
   static constexpr int B = (D == 3 && K == 3) ? 2 : 4;   // cells per tile and direction
@@ -305,7 +344,8 @@ struct ApplyShape {
 // from HBM) and the ghost terms from the pre-pass buffer W.
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, const T* __restrict__ W) {
+                                               T* __restrict__ y, const T* __restrict__ W,
+                                               const T* __restrict__ C) {
   using S = Shape<D, K>;
   using A = ApplyShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
@@ -319,6 +359,7 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   if (b) b += blockIdx.y * L.n_nodes;
   y += blockIdx.y * L.n_nodes;
   W += blockIdx.y * L.n_faces * K * NT;
+  C += blockIdx.y * L.n_cut * NL;
   const double* d0 = tab + S::T_D0;
   const double* d1 = tab + S::T_D1;
   const double* gc = tab + S::T_GC;
@@ -427,13 +468,7 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
 #pragma unroll
         for (int a = 0; a < NRW; ++a) acc[a] = 0;
         if (f & 2) {
-          const T* row = L.cut_mats_t<T>() + ((int64_t)ccut[ce] * NL + iloc) * NL;
-#pragma unroll
-          for (int bq = 0; bq < NL; ++bq) {
-            const int b0 = bq % N1, b12 = bq / N1;
-            const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
-            acc[b12] += row[bq] * xs[xi];
-          }
+          acc[0] = C[(int64_t)ccut[ce] * NL + iloc];  // E_T x_T at this node, from the pre-pass
         } else {
           const double* row = tab + S::T_KCELL + iloc * NL;
 #pragma unroll
@@ -1541,9 +1576,16 @@ int tables_size(int d, int k) {
 }
 
 template <typename T>
-hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, hipStream_t s, int ncol) {
+hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, T* C, hipStream_t s,
+                        int ncol) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
+    if (L.n_cut > 0) {
+      hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T>), dim3(static_cast<unsigned>(L.n_cut), ncol), dim3(64),
+                         0, s, L, x, C);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (L.n_faces > 0) {
       hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s, L, x,
                          W);
@@ -1551,7 +1593,7 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
       if (e != hipSuccess) return e;
     }
     const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks / ncol + 1);
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, W);
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, W, C);
     return hipGetLastError();
   });
 }
@@ -1658,7 +1700,7 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
 }
 
 #define CMG_INSTANTIATE(T)                                                                                      \
-  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, hipStream_t, int);     \
+  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, T*, hipStream_t, int); \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
                                               hipStream_t, int);                                                   \
   template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
