@@ -288,18 +288,17 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   }
 }
 
-// Cut-cell pre-pass of the operator: C_T = E_T x_T for every cut cell T (one
-// block per cut cell and column), so that the operator rows only add one value
-// per cut cell.  E_T is symmetric, so thread i reads column i of the row-major
+// Cut-cell pre-pass of the operator: C_T = E_T x_T for every cut cell T and
+// every column (one block per cut cell, the columns together), so that the
+// operator rows only add one value per cut cell and E_T is read once for all
+// columns.  E_T is symmetric, so thread i reads column i of the row-major
 // matrix, and consecutive threads read consecutive entries.
-template <int D, int K, typename T>
-__global__ __launch_bounds__(64) void k_cut_cell_ax(KLevel L, const T* __restrict__ x, T* __restrict__ C) {
+template <int D, int K, typename T, int NCOL>
+__global__ __launch_bounds__(64) void k_cut_cell_ax(KLevel L, const T* __restrict__ x, T* __restrict__ C, int ncol) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL;
   static_assert(NL <= 64, "one thread per cell node");
-  __shared__ T xs[NL];
-  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
-  C += blockIdx.y * L.n_cut * NL;
+  __shared__ T xs[NL][NCOL];
   const int64_t t = blockIdx.x;
   const int i = threadIdx.x;
   if (i < NL) {
@@ -316,15 +315,25 @@ __global__ __launch_bounds__(64) void k_cut_cell_ax(KLevel L, const T* __restric
       I[a] += q % N1;
       q /= N1;
     }
-    xs[i] = x[lat(D, L.nn, I)];
+    const int64_t node = lat(D, L.nn, I);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) xs[i][c] = c < ncol ? x[c * L.n_nodes + node] : (T)0;
   }
   __syncthreads();
   if (i >= NL) return;
   const T* E = L.cut_mats_t<T>() + t * NL * NL + i;
-  T acc[4] = {0, 0, 0, 0};
+  T acc[NCOL];
 #pragma unroll
-  for (int j = 0; j < NL; ++j) acc[j % 4] += E[j * NL] * xs[j];
-  C[t * NL + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int c = 0; c < NCOL; ++c) acc[c] = 0;
+#pragma unroll 4
+  for (int j = 0; j < NL; ++j) {
+    const T e = E[j * NL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) acc[c] += e * xs[j][c];
+  }
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c)
+    if (c < ncol) C[c * L.n_cut * NL + t * NL + i] = acc[c];
 }
 
 template <int D, int K>
@@ -1581,8 +1590,11 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     if (L.n_cut > 0) {
-      hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T>), dim3(static_cast<unsigned>(L.n_cut), ncol), dim3(64),
-                         0, s, L, x, C);
+      const dim3 g(static_cast<unsigned>(L.n_cut));
+      if (ncol == 1)
+        hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T, 1>), g, dim3(64), 0, s, L, x, C, 1);
+      else
+        hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T, kMaxCols>), g, dim3(64), 0, s, L, x, C, ncol);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
