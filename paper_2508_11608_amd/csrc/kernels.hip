@@ -1356,23 +1356,21 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
   const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
   const int kr = lane / 16, jc = lane % 16;
   const float* tiles = G.inv_tiles + G.tile_off[gp];
+  // all tiles of a row block are loaded at once (NKB <= 32 registers), then
+  // the MFMA chain runs on them
+  constexpr int NKB = NPK / 4;
   for (int rb = wave; rb < nrb; rb += nwave) {  // wave-uniform: every lane takes part in the MFMA
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     const float* t = tiles + (int64_t)rb * nkb * 64 + lane;
-    int kb = 0;
-    for (; kb + 4 <= nkb; kb += 4) {
-      float a[4], bb[4];
+    float a[NKB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = t[(kb + u) * 64];
+    for (int kb = 0; kb < NKB; ++kb) a[kb] = kb < nkb ? t[kb * 64] : 0.f;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bb[u] = jc < kMaxCols ? rs[(kb + u) * 4 + kr][jc] : 0.f;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bb[u], acc, 0, 0, 0);
-    }
-    for (; kb < nkb; ++kb) {
-      const float a = t[kb * 64];
-      const float bb = jc < kMaxCols ? rs[kb * 4 + kr][jc] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb < nkb) {
+        const float bb = jc < kMaxCols ? rs[kb * 4 + kr][jc] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kb], bb, acc, 0, 0, 0);
+      }
     }
     if (jc < ncol) {
 #pragma unroll
