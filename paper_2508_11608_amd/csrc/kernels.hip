@@ -1073,19 +1073,19 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
     return;
   }
   if (tid < nj) {
+    // batches of 32 (FP32) or 16 (FP64) independent loads
+    constexpr int NB = sizeof(T) == 4 ? 32 : 16;
     const int i = tid;
     T acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0;
-    int j = 0;
-    for (; j + 8 <= nj; j += 8) {
-      T v[8];
+    for (int j = 0; j < nj; j += NB) {
+      T v[NB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = inv[(int64_t)(j + u) * nj + i];
+      for (int u = 0; u < NB; ++u) v[u] = j + u < nj ? inv[(int64_t)(j + u) * nj + i] : (T)0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += v[u] * rs[j + u];
+      for (int u = 0; u < NB; ++u) acc[u % 8] += v[u] * rs[j + u < nj ? j + u : 0];
     }
-    for (; j < nj; ++j) acc[0] += inv[(int64_t)j * nj + i] * rs[j];
     dbuf[off + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
 }
