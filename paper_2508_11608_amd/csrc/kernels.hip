@@ -1485,28 +1485,50 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
     lo[a] = lo[a] < 0 ? 0 : lo[a];
     hi[a] = hi[a] > Lf.nn - 1 ? Lf.nn - 1 : hi[a];
   }
+  // 1-D weights over the (at most 4k-1 wide) ranges, zero beyond them; the
+  // loads of one x-y slab are issued together
+  constexpr int WR = 4 * K - 1;
+  T w[3][WR];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int t = 0; t < WR; ++t) w[a][t] = lo[a] + t <= hi[a] ? (T)restrict_weight<K>(p1d, J[a], lo[a] + t) : (T)0;
+  const int64_t nn = Lf.nn;
   T acc = 0;
-  if (D == 2) {
-    for (int i1 = lo[1]; i1 <= hi[1]; ++i1) {
-      const double w1 = restrict_weight<K>(p1d, J[1], i1);
-      T a0 = 0;
-      for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
-        a0 += (T)restrict_weight<K>(p1d, J[0], i0) * rf[i0 + (int64_t)Lf.nn * i1];
-      acc += (T)w1 * a0;
-    }
-  } else {
-    for (int i2 = lo[2]; i2 <= hi[2]; ++i2) {
-      const double w2 = restrict_weight<K>(p1d, J[2], i2);
-      T a1 = 0;
-      for (int i1 = lo[1]; i1 <= hi[1]; ++i1) {
-        const double w1 = restrict_weight<K>(p1d, J[1], i1);
+  for (int t2 = 0; t2 < (D == 3 ? WR : 1); ++t2) {
+    if (D == 3 && lo[2] + t2 > hi[2]) break;
+    const int64_t base = lo[0] + nn * (lo[1] + (D == 3 ? nn * (lo[2] + t2) : 0));
+    T a1 = 0;
+    if constexpr (WR * WR * sizeof(T) <= 400) {  // the slab fits in about 100 registers
+      T v[WR][WR];
+#pragma unroll
+      for (int t1 = 0; t1 < WR; ++t1)
+#pragma unroll
+        for (int t0 = 0; t0 < WR; ++t0)
+          v[t1][t0] = (lo[1] + t1 <= hi[1] && lo[0] + t0 <= hi[0]) ? rf[base + t0 + nn * t1] : (T)0;
+#pragma unroll
+      for (int t1 = 0; t1 < WR; ++t1) {
+        if (lo[1] + t1 > hi[1]) continue;
         T a0 = 0;
-        for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
-          a0 += (T)restrict_weight<K>(p1d, J[0], i0) * rf[i0 + (int64_t)Lf.nn * (i1 + (int64_t)Lf.nn * i2)];
-        a1 += (T)w1 * a0;
+#pragma unroll
+        for (int t0 = 0; t0 < WR; ++t0)
+          if (lo[0] + t0 <= hi[0]) a0 += w[0][t0] * v[t1][t0];
+        a1 += w[1][t1] * a0;
       }
-      acc += (T)w2 * a1;
+    } else {  // row by row
+      for (int t1 = 0; t1 < WR; ++t1) {
+        if (lo[1] + t1 > hi[1]) break;
+        T v[WR];
+#pragma unroll
+        for (int t0 = 0; t0 < WR; ++t0) v[t0] = lo[0] + t0 <= hi[0] ? rf[base + t0 + nn * t1] : (T)0;
+        T a0 = 0;
+#pragma unroll
+        for (int t0 = 0; t0 < WR; ++t0)
+          if (lo[0] + t0 <= hi[0]) a0 += w[0][t0] * v[t0];
+        a1 += w[1][t1] * a0;
+      }
     }
+    acc += D == 3 ? w[2][t2] * a1 : a1;
   }
   bc[node] = acc;
 }
