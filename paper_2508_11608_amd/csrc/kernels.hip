@@ -1420,20 +1420,26 @@ __global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const
       for (int bb = 0; bb < N1; ++bb) w[a][bb] = p1d[q * N1 + bb];
     }
   }
-  T acc = 0;
-  const int ncomb = nq[0] * nq[1] * (D == 3 ? nq[2] : 1);
-  for (int comb = 0; comb < ncomb; ++comb) {
-    int J[3];
-    double wt = 1.0;
-    int rc = comb;
+  // all (k+1)^d coarse values at once (predicated), then the weighted sum in
+  // the order of the contributing combinations
+  constexpr int NQ = Pow<N1, D>::v;
+  T v[NQ];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int s = rc % nq[a];
-      rc /= nq[a];
-      J[a] = J0[a] + s;
-      wt *= w[a][s];
+  for (int q = 0; q < NQ; ++q) {
+    const int s0 = q % N1, s1 = (q / N1) % N1, s2 = D == 3 ? q / (N1 * N1) : 0;
+    const bool use = s0 < nq[0] && s1 < nq[1] && (D == 2 || s2 < nq[2]);
+    int J[3] = {J0[0] + s0, J0[1] + s1, D == 3 ? J0[2] + s2 : 0};
+    v[q] = use ? xc[lat(D, Lc.nn, J)] : (T)0;
+  }
+  T acc = 0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int s0 = q % N1, s1 = (q / N1) % N1, s2 = D == 3 ? q / (N1 * N1) : 0;
+    if (s0 < nq[0] && s1 < nq[1] && (D == 2 || s2 < nq[2])) {
+      double wt = w[0][s0] * w[1][s1];
+      if (D == 3) wt *= w[2][s2];
+      acc += (T)wt * v[q];
     }
-    acc += (T)wt * xc[lat(D, Lc.nn, J)];
   }
   xf[node] += acc;
 }
