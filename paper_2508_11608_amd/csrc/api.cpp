@@ -61,7 +61,31 @@ struct DevLevel {
   cmg::CutGroupDev cut64[8] = {}, cut32[8] = {};
   int64_t max_cut_nodes = 0;
   size_t n_w = 0;  // entries of the ghost-face jump buffer
+  size_t n_c = 0;  // entries of the special-cell product buffer
 };
+
+// Special cells of a level (cut, or with a ghost face) in cell order: their
+// background cells, per special cell its cut id and 2d ghost face ids, and per
+// cell its special id (-1 active and regular, -2 inactive).
+void special_cells(const cmg::HostLevel& h, int dim, std::vector<int32_t>* spec, std::vector<int32_t>* info,
+                   std::vector<int32_t>* sid) {
+  const int nf = 2 * dim;
+  if (sid) sid->assign(static_cast<size_t>(h.n_cells), -2);
+  for (int64_t c = 0; c < h.n_cells; ++c) {
+    if (!(h.cell_flags[c] & 1)) continue;
+    const bool special = h.cut_id[c] >= 0 || h.cell_gid[c] >= 0;
+    if (!special) {
+      if (sid) (*sid)[c] = -1;
+      continue;
+    }
+    if (sid) (*sid)[c] = static_cast<int32_t>(spec->size());
+    spec->push_back(static_cast<int32_t>(c));
+    if (!info) continue;
+    info->push_back(h.cut_id[c]);
+    for (int j = 0; j < nf; ++j)
+      info->push_back(h.cell_gid[c] >= 0 ? h.cell_faces[static_cast<size_t>(h.cell_gid[c]) * nf + j] : -1);
+  }
+}
 
 }  // namespace
 
@@ -211,14 +235,18 @@ cmg_status upload_all(cmg_problem* P) {
     k.cell_faces = cfaces;
     k.n_tiles = static_cast<int>(h.tiles.size());
     k.tiles = tiles;
+    k.n_cut = h.n_cut;
     {
-      std::vector<int32_t> cc(static_cast<size_t>(h.n_cut));
-      for (size_t c = 0; c < h.cut_id.size(); ++c)
-        if (h.cut_id[c] >= 0) cc[h.cut_id[c]] = static_cast<int32_t>(c);
-      int32_t* dcc;
-      TRY(upload(own, cc, &dcc));
-      k.n_cut = h.n_cut;
-      k.cut_cells = dcc;
+      std::vector<int32_t> spec, info, sid;
+      special_cells(h, cfg.dim, &spec, &info, &sid);
+      int32_t *dspec, *dinfo, *dsid;
+      TRY(upload(own, spec, &dspec));
+      TRY(upload(own, info, &dinfo));
+      TRY(upload(own, sid, &dsid));
+      k.n_spec = static_cast<int64_t>(spec.size());
+      k.spec_cells = dspec;
+      k.spec_info = dinfo;
+      k.cell_sid = dsid;
     }
     d.kl32 = k;
     d.kl32.cut_mats = nullptr;
@@ -227,8 +255,8 @@ cmg_status upload_all(cmg_problem* P) {
     TRY(alloc_zero(own, h.n_nodes, &d.v64.r));
     d.n_w = h.face_lower.size() * static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
     TRY(alloc_zero(own, d.n_w, &d.v64.W));
-    const size_t n_c_entries = static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
-    TRY(alloc_zero(own, n_c_entries, &d.v64.C));
+    d.n_c = static_cast<size_t>(k.n_spec) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+    TRY(alloc_zero(own, d.n_c, &d.v64.C));
     for (int c = 0; c < 8; ++c) {
       TRY(upload(own, h.int_vertex[c], &d.int_verts[c]));
       d.n_int[c] = static_cast<int>(h.int_vertex[c].size());
@@ -286,8 +314,7 @@ cmg_status ensure_fp32(cmg_problem* P) {
     TRY(alloc_zero(own, h.n_nodes, &d.v32.b));
     TRY(alloc_zero(own, h.n_nodes, &d.v32.r));
     TRY(alloc_zero(own, d.n_w, &d.v32.W));
-    TRY(alloc_zero(own, static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim)),
-                   &d.v32.C));
+    TRY(alloc_zero(own, d.n_c, &d.v32.C));
     TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v32.dbuf));
   }
   TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
@@ -312,8 +339,7 @@ cmg_status ensure_multi(cmg_problem* P) {
     TRY(alloc_zero(own, C * h.n_nodes, &v.b));
     TRY(alloc_zero(own, C * h.n_nodes, &v.r));
     TRY(alloc_zero(own, C * d.n_w, &v.W));
-    TRY(alloc_zero(own, C * static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim)),
-                   &v.C));
+    TRY(alloc_zero(own, C * d.n_c, &v.C));
     TRY(alloc_zero(own, C * static_cast<size_t>(d.max_cut_nodes), &v.dbuf));
   }
   if (!P->mkr) {
@@ -843,9 +869,12 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
     }
     b64 += 8 * maxn;
     b32 += 4 * maxn;
-    const size_t ncc = static_cast<size_t>(h.n_cut) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
-    b64 += 8 * ncc;  // cut-cell products of the operator
+    std::vector<int32_t> spec;
+    special_cells(h, cfg.dim, &spec, nullptr, nullptr);
+    const size_t ncc = spec.size() * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+    b64 += 8 * ncc;  // special-cell products of the operator
     b32 += 4 * ncc;
+    b64 += 4 * (spec.size() * (2 + 2 * cfg.dim) + static_cast<size_t>(h.n_cells));  // special-cell lists
     const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc;
     m64 += 8 * C * per_col;
     m32 += 4 * C * per_col;

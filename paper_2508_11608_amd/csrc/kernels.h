@@ -18,7 +18,6 @@ struct KLevel {
   const uint8_t* ghost;      // per cell: bit 2*dir+side marks a ghost face
   const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path (symmetric)
   int64_t n_cut;             // cut cells
-  const int32_t* cut_cells;  // background cell of every cut cell
   const int32_t* dof_node;   // lattice node of each DoF, ascending
   const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
   int64_t n_faces;           // ghost faces
@@ -28,6 +27,10 @@ struct KLevel {
   const int32_t* cell_faces; // 2d face ids per cell with ghost faces (-1: none)
   int n_tiles;               // operator tiles owning active nodes
   const int32_t* tiles;
+  int64_t n_spec;            // special cells: cut, or with a ghost face
+  const int32_t* spec_cells; // background cell of every special cell
+  const int32_t* spec_info;  // per special cell 1 + 2d entries: cut id (-1: uncut), ghost face ids (-1: none)
+  const int32_t* cell_sid;   // per cell: special id, -1 active and regular, -2 inactive
   template <typename T>
   __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
 };
@@ -69,8 +72,8 @@ int tables_size(int d, int k);
 // compact (DoF-ordered) vectors ncol blocks of n entries.
 
 // y = A x (b == nullptr) or y = b - A x on every active node; W is the work
-// buffer for the ghost-face jumps, C the one for the cut-cell products
-// (n_cut (k+1)^d entries per column).
+// buffer for the ghost-face jumps, C the one for the special-cell products
+// (n_spec (k+1)^d entries per column).
 template <typename T>
 hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, T* C, hipStream_t s,
                         int ncol = 1);

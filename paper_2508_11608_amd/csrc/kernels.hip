@@ -288,52 +288,108 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   }
 }
 
-// Cut-cell pre-pass of the operator: C_T = E_T x_T for every cut cell T and
-// every column (one block per cut cell, the columns together), so that the
-// operator rows only add one value per cut cell and E_T is read once for all
-// columns.  E_T is symmetric, so thread i reads column i of the row-major
-// matrix, and consecutive threads read consecutive entries.
+// Special-cell pre-pass of the operator.  A special cell T is cut or has a
+// ghost face; for each of them and every column it forms the contribution of T
+// to the rows of its nodes,
+//   C_T(i) = (E_T x_T)_i + sum_{ghost faces F of T} sum_m gc_m trace_m(i_dir) W_m(F)(i_t),
+// with E_T the cut-cell matrix or the uncut stiffness and W the face pre-pass
+// output, so that the operator kernel adds one value per special cell and
+// node.  CPB cells per 64-thread block, one thread per cell node, the columns
+// together; E_T is symmetric, so a thread reads column i and consecutive
+// threads read consecutive entries.
+template <int D, int K>
+struct CellShape {
+  static constexpr int NL = Shape<D, K>::NL;
+  static constexpr int CPB = 64 / NL;
+  static_assert(CPB >= 1, "one thread per cell node");
+};
+
 template <int D, int K, typename T, int NCOL>
-__global__ __launch_bounds__(64) void k_cut_cell_ax(KLevel L, const T* __restrict__ x, T* __restrict__ C, int ncol) {
+__global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ x, const T* __restrict__ W,
+                                                T* __restrict__ C, int ncol) {
   using S = Shape<D, K>;
-  constexpr int N1 = S::N1, NL = S::NL;
-  static_assert(NL <= 64, "one thread per cell node");
-  __shared__ T xs[NL][NCOL];
-  const int64_t t = blockIdx.x;
-  const int i = threadIdx.x;
-  if (i < NL) {
-    int64_t r = L.cut_cells[t];
-    int I[3];
+  constexpr int N1 = S::N1, NL = S::NL, CPB = CellShape<D, K>::CPB, NF = 2 * D;
+  constexpr int NT = Pow<N1, D - 1>::v;
+  __shared__ T xs[CPB][NL][NCOL];
+  const int lc = threadIdx.x / NL;
+  const int i = threadIdx.x % NL;
+  const int64_t t = (int64_t)blockIdx.x * CPB + lc;
+  const bool on = lc < CPB && t < L.n_spec;
+  int il[3] = {0, 0, 0};
+  int32_t info[1 + NF];
+  if (on) {
+    int64_t r = L.spec_cells[t];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      I[a] = K * static_cast<int>(r % L.N);
-      r /= L.N;
-    }
+    for (int j = 0; j <= NF; ++j) info[j] = L.spec_info[t * (1 + NF) + j];
+    int I[3];
     int q = i;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      I[a] += q % N1;
+      il[a] = q % N1;
       q /= N1;
+      I[a] = K * static_cast<int>(r % L.N) + il[a];
+      r /= L.N;
     }
     const int64_t node = lat(D, L.nn, I);
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) xs[i][c] = c < ncol ? x[c * L.n_nodes + node] : (T)0;
+    for (int c = 0; c < NCOL; ++c) xs[lc][i][c] = c < ncol ? x[c * L.n_nodes + node] : (T)0;
   }
   __syncthreads();
-  if (i >= NL) return;
-  const T* E = L.cut_mats_t<T>() + t * NL * NL + i;
+  if (!on) return;
   T acc[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) acc[c] = 0;
-#pragma unroll 4
-  for (int j = 0; j < NL; ++j) {
-    const T e = E[j * NL];
+  // ghost terms first: their loads do not wait for the staged x
+  const int64_t wcol = L.n_faces * K * NT;
+  const double* d0 = L.tables + S::T_D0;
+  const double* d1 = L.tables + S::T_D1;
+  const double* gc = L.tables + S::T_GC;
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) acc[c] += e * xs[j][c];
+  for (int dir = 0; dir < D; ++dir) {
+    int it = 0, st = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (a == dir) continue;
+      it += il[a] * st;
+      st *= N1;
+    }
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int fid = info[1 + 2 * dir + side];
+      if (fid < 0) continue;
+      const T* w = W + (int64_t)fid * K * NT + it;
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        const T sg = (T)(gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]));
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+          if (c < ncol) acc[c] += sg * w[c * wcol + m * NT];
+      }
+    }
+  }
+  T cell[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) cell[c] = 0;
+  if (info[0] >= 0) {
+    const T* E = L.cut_mats_t<T>() + (int64_t)info[0] * NL * NL + i;
+#pragma unroll 4
+    for (int j = 0; j < NL; ++j) {
+      const T e = E[j * NL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) cell[c] += e * xs[lc][j][c];
+    }
+  } else {
+    const double* row = L.tables + S::T_KCELL + i * NL;
+#pragma unroll 4
+    for (int j = 0; j < NL; ++j) {
+      const T e = (T)row[j];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) cell[c] += e * xs[lc][j][c];
+    }
   }
 #pragma unroll
   for (int c = 0; c < NCOL; ++c)
-    if (c < ncol) C[c * L.n_cut * NL + t * NL + i] = acc[c];
+    if (c < ncol) C[c * L.n_spec * NL + t * NL + i] = cell[c] + acc[c];
 }
 
 template <int D, int K>
@@ -349,29 +405,25 @@ struct ApplyShape {
 
 // y = A x (b == nullptr) or y = b - A x on the active nodes of a tile of B^d
 // cells.  x on the cells -1 .. B-1 around the tile is staged in LDS; every
-// owned node sums its cell rows (uncut stiffness from LDS, cut-cell matrices
-// from HBM) and the ghost terms from the pre-pass buffer W.
+// owned node sums, over the cells that contain it, the uncut stiffness row
+// (from LDS) or the special-cell value of the pre-pass (from C).  The C loads
+// of a node's cells are independent and issued together before the LDS rows.
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, const T* __restrict__ W,
-                                               const T* __restrict__ C) {
+                                               T* __restrict__ y, const T* __restrict__ C) {
   using S = Shape<D, K>;
   using A = ApplyShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
-  constexpr int NT = Pow<N1, D - 1>::v;
-  __shared__ double tab[S::T_FDS];  // kcell | mhat | d0 | d1 | gc
+  constexpr int NCB = 1 << D;
+  constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+  __shared__ double tab[S::T_MHAT];  // uncut stiffness
   __shared__ T xs[A::NR];
-  __shared__ uint8_t cfl[A::NCC];
-  __shared__ int32_t ccut[A::NCC], cgid[A::NCC];
-  for (int i = threadIdx.x; i < S::T_FDS; i += blockDim.x) tab[i] = L.tables[i];
+  __shared__ int32_t csid[A::NCC];
+  for (int i = threadIdx.x; i < S::T_MHAT; i += blockDim.x) tab[i] = L.tables[i];
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   if (b) b += blockIdx.y * L.n_nodes;
   y += blockIdx.y * L.n_nodes;
-  W += blockIdx.y * L.n_faces * K * NT;
-  C += blockIdx.y * L.n_cut * NL;
-  const double* d0 = tab + S::T_D0;
-  const double* d1 = tab + S::T_D1;
-  const double* gc = tab + S::T_GC;
+  C += blockIdx.y * L.n_spec * NL;
   const int NTd = (L.N + B - 1) / B;
   for (int ti = blockIdx.x; ti < L.n_tiles; ti += gridDim.x) {
     __syncthreads();
@@ -391,19 +443,7 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
         r /= C1;
         in = in && c[a] >= 0 && c[a] < L.N;
       }
-      uint8_t f = 0;
-      int32_t cid = -1, gid = -1;
-      if (in) {
-        const int64_t cl = cell_lin(D, L.N, c);
-        f = L.flags[cl];
-        if (f & 1) {
-          cid = L.cut_id[cl];
-          gid = L.cell_gid[cl];
-        }
-      }
-      cfl[e] = f;
-      ccut[e] = cid;
-      cgid[e] = gid;
+      csid[e] = in ? L.cell_sid[cell_lin(D, L.N, c)] : -2;
     }
     for (int e = threadIdx.x; e < A::NR; e += blockDim.x) {
       int I[3];
@@ -418,6 +458,27 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
       xs[e] = in ? x[lat(D, L.nn, I)] : (T)0;
     }
     __syncthreads();
+    // the node's cells along each direction: a node on a cell boundary
+    // (q % K == 0) lies in staged cells q/K (local index K) and q/K + 1 (local
+    // index 0), any other node only in q/K + 1; comb bit a selects the upper one
+    auto cell_of = [&](const int* q, int comb, int* c, int* il) {
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int sel = (comb >> a) & 1;
+        if (q[a] % K == 0) {
+          c[a] = q[a] / K + sel;
+          il[a] = sel ? 0 : K;
+        } else {
+          ok = ok && sel == 0;
+          c[a] = q[a] / K + 1;
+          il[a] = q[a] % K;
+        }
+        ok = ok && c[a] < C1;  // beyond the background box
+      }
+      return ok;
+    };
+#pragma unroll 1
     for (int e = threadIdx.x; e < A::NO; e += blockDim.x) {
       int q[3], I[3];
       bool own = true;
@@ -431,93 +492,58 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
         own = own && I[a] < L.nn && (q[a] < B * K || tc[a] == NTd - 1);
       }
       if (!own) continue;
-      // cells containing the node, in staged cell coordinates 0 .. B (cell -1 -> 0)
-      int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
+      const int64_t node = lat(D, L.nn, I);
+      const T bv = b ? b[node] : (T)0;
+      // pass 1: the special-cell values, all loads in flight together
+      T cv[NCB];
+      bool act = false;  // the node lies in an active cell
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        if (q[a] % K == 0) {
-          cc[a][0] = q[a] / K;      // tile cell q/K - 1
-          lc[a][0] = K;
-          cc[a][1] = q[a] / K + 1;  // tile cell q/K
-          lc[a][1] = 0;
-          nc[a] = 2;
-        } else {
-          cc[a][0] = q[a] / K + 1;
-          lc[a][0] = q[a] % K;
-        }
-      }
-      T ax = 0;
-      bool active = false;
-      const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
-      for (int comb = 0; comb < ncomb; ++comb) {
+      for (int comb = 0; comb < NCB; ++comb) {
+        cv[comb] = 0;
         int c[3], il[3];
-        int rr = comb;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const int sel = rr % nc[a];
-          rr /= nc[a];
-          c[a] = cc[a][sel];
-          il[a] = lc[a][sel];
-        }
-        bool inside = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) inside = inside && c[a] < C1;
-        if (!inside) continue;  // beyond the background box
+        if (!cell_of(q, comb, c, il)) continue;
         int ce = c[0] + C1 * c[1];
         if (D == 3) ce += C1 * C1 * c[2];
-        const uint8_t f = cfl[ce];
-        if (!(f & 1)) continue;
-        active = true;
+        const int sid = csid[ce];
+        if (sid == -2) continue;  // inactive cell
+        act = true;
+        if (sid < 0) continue;
+        int iloc = il[0] + N1 * il[1];
+        if (D == 3) iloc += N1 * N1 * il[2];
+        cv[comb] = C[(int64_t)sid * NL + iloc];
+      }
+      if (!act) continue;
+      // pass 2: uncut stiffness rows of the regular cells from LDS
+      T ax = 0;
+#pragma unroll 1
+      for (int comb = 0; comb < NCB; ++comb) {
+        int c[3], il[3];
+        if (!cell_of(q, comb, c, il)) continue;
+        int ce = c[0] + C1 * c[1];
+        if (D == 3) ce += C1 * C1 * c[2];
+        if (csid[ce] != -1) continue;
         int iloc = il[0] + N1 * il[1];
         if (D == 3) iloc += N1 * N1 * il[2];
         int xb = K * c[0] + R1 * K * c[1];
         if (D == 3) xb += R1 * R1 * K * c[2];
-        constexpr int NRW = N1 * (D == 3 ? N1 : 1);
+        const double* row = tab + iloc * NL;
         T acc[NRW];
 #pragma unroll
         for (int a = 0; a < NRW; ++a) acc[a] = 0;
-        if (f & 2) {
-          acc[0] = C[(int64_t)ccut[ce] * NL + iloc];  // E_T x_T at this node, from the pre-pass
-        } else {
-          const double* row = tab + S::T_KCELL + iloc * NL;
 #pragma unroll
-          for (int bq = 0; bq < NL; ++bq) {
-            const int b0 = bq % N1, b12 = bq / N1;
-            const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
-            acc[b12] += (T)row[bq] * xs[xi];
-          }
+        for (int bq = 0; bq < NL; ++bq) {
+          const int b0 = bq % N1, b12 = bq / N1;
+          const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
+          acc[b12] += (T)row[bq] * xs[xi];
         }
         T sacc = 0;
 #pragma unroll
         for (int a = 0; a < NRW; ++a) sacc += acc[a];
-        const int gid = cgid[ce];
-        if (gid >= 0) {
-#pragma unroll
-          for (int dir = 0; dir < D; ++dir)
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-              const int fid = L.cell_faces[(int64_t)gid * 2 * D + 2 * dir + side];
-              if (fid < 0) continue;
-              int it = 0, st = 1;
-#pragma unroll
-              for (int a = 0; a < D; ++a) {
-                if (a == dir) continue;
-                it += il[a] * st;
-                st *= N1;
-              }
-              const T* w = W + (int64_t)fid * K * NT + it;
-#pragma unroll
-              for (int m = 0; m < K; ++m) {
-                const double sg = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
-                sacc += (T)sg * w[m * NT];
-              }
-            }
-        }
         ax += sacc;
       }
-      if (!active) continue;
-      const int64_t node = lat(D, L.nn, I);
-      y[node] = b ? b[node] - ax : ax;
+#pragma unroll
+      for (int comb = 0; comb < NCB; ++comb) ax += cv[comb];
+      y[node] = b ? bv - ax : ax;
     }
   }
 }
@@ -1494,9 +1520,9 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
   // 1-D weights over the (at most 4k-1 wide) ranges, zero beyond them; the
   // loads of one x-y slab are issued together
   constexpr int WR = 4 * K - 1;
-  T w[3][WR];
+  T w[2][WR];  // directions 0 and 1; direction 2 inside the slab loop (a runtime index)
 #pragma unroll
-  for (int a = 0; a < D; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int t = 0; t < WR; ++t) w[a][t] = lo[a] + t <= hi[a] ? (T)restrict_weight<K>(p1d, J[a], lo[a] + t) : (T)0;
   const int64_t nn = Lf.nn;
@@ -1531,10 +1557,10 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
 #pragma unroll
         for (int t0 = 0; t0 < WR; ++t0)
           if (lo[0] + t0 <= hi[0]) a0 += w[0][t0] * v[t0];
-        a1 += w[1][t1] * a0;
+        a1 += (T)restrict_weight<K>(p1d, J[1], lo[1] + t1) * a0;
       }
     }
-    acc += D == 3 ? w[2][t2] * a1 : a1;
+    acc += D == 3 ? (T)restrict_weight<K>(p1d, J[2], lo[2] + t2) * a1 : a1;
   }
   bc[node] = acc;
 }
@@ -1615,23 +1641,24 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
                         int ncol) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    if (L.n_cut > 0) {
-      const dim3 g(static_cast<unsigned>(L.n_cut));
-      if (ncol == 1)
-        hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T, 1>), g, dim3(64), 0, s, L, x, C, 1);
-      else
-        hipLaunchKernelGGL((dev::k_cut_cell_ax<D.value, K.value, T, kMaxCols>), g, dim3(64), 0, s, L, x, C, ncol);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
     if (L.n_faces > 0) {
       hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s, L, x,
                          W);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
+    if (L.n_spec > 0) {
+      constexpr int CPB = dev::CellShape<D.value, K.value>::CPB;
+      const dim3 g(static_cast<unsigned>((L.n_spec + CPB - 1) / CPB));
+      if (ncol == 1)
+        hipLaunchKernelGGL((dev::k_cell_ax<D.value, K.value, T, 1>), g, dim3(64), 0, s, L, x, W, C, 1);
+      else
+        hipLaunchKernelGGL((dev::k_cell_ax<D.value, K.value, T, kMaxCols>), g, dim3(64), 0, s, L, x, W, C, ncol);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks / ncol + 1);
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, W, C);
+    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, C);
     return hipGetLastError();
   });
 }
