@@ -47,7 +47,8 @@ struct Vecs {
   T* r = nullptr;
   T* dbuf = nullptr;  // cut-patch corrections of one colour
   T* W = nullptr;     // ghost-face jumps of the operator kernel
-  T* C = nullptr;     // cut-cell products of the operator kernel
+  T* C = nullptr;     // special-cell products of the operator kernel
+  T* x1 = nullptr;    // second x buffer of the two-buffer cut colour steps
 };
 
 struct DevLevel {
@@ -62,6 +63,8 @@ struct DevLevel {
   int64_t max_cut_nodes = 0;
   size_t n_w = 0;  // entries of the ghost-face jump buffer
   size_t n_c = 0;  // entries of the special-cell product buffer
+  int32_t* region = nullptr;  // cut region (nodes a cut colour step reads)
+  int64_t n_region = 0;
 };
 
 // Special cells of a level (cut, or with a ghost face) in cell order: their
@@ -278,12 +281,18 @@ cmg_status upload_all(cmg_problem* P) {
         G.inv_off = ioff;
         G.nodes = nodes;
         G.inv = inv;
+        uint8_t* nxt;
+        TRY(upload(own, g.nxt, &nxt));
+        G.nxt = nxt;
       }
       d.cut32[c] = G;
       d.cut32[c].inv = nullptr;
       d.max_cut_nodes = std::max(d.max_cut_nodes, G.n_nodes);
     }
     TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v64.dbuf));
+    TRY(upload(own, h.cut_region, &d.region));
+    d.n_region = static_cast<int64_t>(h.cut_region.size());
+    if (d.n_region > 0) TRY(alloc_zero(own, h.n_nodes, &d.v64.x1));
   }
   TRY(upload(own, P->H.coarse_inv, &P->coarse64));
   const int64_t n = P->H.levels.back().n_dofs;
@@ -316,6 +325,7 @@ cmg_status ensure_fp32(cmg_problem* P) {
     TRY(alloc_zero(own, d.n_w, &d.v32.W));
     TRY(alloc_zero(own, d.n_c, &d.v32.C));
     TRY(alloc_zero(own, static_cast<size_t>(d.max_cut_nodes), &d.v32.dbuf));
+    if (d.n_region > 0) TRY(alloc_zero(own, h.n_nodes, &d.v32.x1));
   }
   TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
   P->fp32_ready = true;
@@ -341,6 +351,7 @@ cmg_status ensure_multi(cmg_problem* P) {
     TRY(alloc_zero(own, C * d.n_w, &v.W));
     TRY(alloc_zero(own, C * d.n_c, &v.C));
     TRY(alloc_zero(own, C * static_cast<size_t>(d.max_cut_nodes), &v.dbuf));
+    if (d.n_region > 0) TRY(alloc_zero(own, C * h.n_nodes, &v.x1));
   }
   if (!P->mkr) {
     const size_t n = static_cast<size_t>(P->H.levels.back().n_dofs);
@@ -485,15 +496,54 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
   return CMG_OK;
 }
 
+// The cut colour steps of one smoothing pass (n_c sweeps over the colours
+// that have cut patches; reversed in the post-smoother).  Every step reads x
+// as it was at the start of the step (same-coloured patches are updated
+// together).  With the single-matrix-row kernel the steps alternate between two
+// x buffers: step i reads X[i % 2] and writes X[(i + 1) % 2], where the patch
+// blocks store x + d on the colour's internal DoFs and copy blocks bring over
+// the previous colour's DoFs that the current colour does not own; X1 is made
+// equal to X0 on the cut region first, and an even number of steps ends in
+// X0 (an odd last step uses the correction buffer).  The matrix-core kernel
+// keeps the correction buffer and a separate update for every step.
+template <typename T>
+cmg_status cut_steps(cmg_problem* P, int l, bool post, hipStream_t s, int ncol, bool multi) {
+  const int d = P->H.cfg.dim, k = P->H.cfg.k;
+  DevLevel& D = P->lv[l];
+  Vecs<T>& v = work<T>(D, multi);
+  const int C = 1 << d;
+  std::vector<int> seq;
+  for (int r = 0; r < P->H.cfg.n_c; ++r)
+    for (int c = 0; c < C; ++c)
+      if (cutg<T>(D, c).n_patch > 0) seq.push_back(c);
+  if (post) std::reverse(seq.begin(), seq.end());
+  bool mfma = false;
+  if constexpr (std::is_same<T, float>::value)
+    for (int c = 0; c < C; ++c) mfma = mfma || (multi && cutg<T>(D, c).inv_tiles);
+  size_t npp = seq.size() - seq.size() % 2;
+  if (mfma || !v.x1 || npp == 0) npp = 0;
+  if (npp > 0) {
+    KTimer t(P, kCutUpdate, l, s);
+    HIP_TRY(cmg::launch_copy_nodes<T>(D.region, D.n_region, v.x, v.x1, D.kl64.n_nodes, s, ncol));
+  }
+  T* X[2] = {v.x, v.x1};
+  for (size_t i = 0; i < npp; ++i) {
+    const cmg::CutGroupDev& G = cutg<T>(D, seq[i]);
+    cmg::CopyJob cj;
+    if (i > 0) cj = cmg::cut_copy_job(d, k, cutg<T>(D, seq[i - 1]), post ? 2 : 1);
+    KTimer t(P, kCutSolve, l, s);
+    HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, X[i % 2], v.b, v.dbuf, s, ncol, X[(i + 1) % 2], cj));
+  }
+  for (size_t i = npp; i < seq.size(); ++i) TRY(colour_step<T>(P, l, false, seq[i], s, ncol, multi));
+  return CMG_OK;
+}
+
 template <typename T>
 cmg_status smooth(cmg_problem* P, int l, bool post, hipStream_t s, int ncol = 1, bool multi = false) {
   const int C = 1 << P->H.cfg.dim;
-  std::vector<std::pair<bool, int>> seq;
-  for (int c = 0; c < C; ++c) seq.push_back({true, c});
-  for (int r = 0; r < P->H.cfg.n_c; ++r)
-    for (int c = 0; c < C; ++c) seq.push_back({false, c});
-  if (post) std::reverse(seq.begin(), seq.end());
-  for (auto [interior, c] : seq) TRY(colour_step<T>(P, l, interior, c, s, ncol, multi));
+  if (post) TRY(cut_steps<T>(P, l, post, s, ncol, multi));
+  for (int i = 0; i < C; ++i) TRY(colour_step<T>(P, l, true, post ? C - 1 - i : i, s, ncol, multi));
+  if (!post) TRY(cut_steps<T>(P, l, post, s, ncol, multi));
   return CMG_OK;
 }
 
@@ -857,7 +907,7 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
     for (int c = 0; c < 8; ++c) {
       const cmg::CutPatchGroup& g = h.cut[c];
       b64 += 4 * (h.int_vertex[c].size() + g.vertex.size() + g.off.size() + g.nodes.size()) + 8 * g.inv_off.size() +
-             8 * g.inv.size();
+             8 * g.inv.size() + g.nxt.size();
       b32 += 4 * g.inv.size();
       maxn = std::max(maxn, g.nodes.size());
       if (g.vertex.empty()) continue;
@@ -875,7 +925,10 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
     b64 += 8 * ncc;  // special-cell products of the operator
     b32 += 4 * ncc;
     b64 += 4 * (spec.size() * (2 + 2 * cfg.dim) + static_cast<size_t>(h.n_cells));  // special-cell lists
-    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc;
+    const size_t nx1 = h.cut_region.empty() ? 0 : static_cast<size_t>(h.n_nodes);  // second x buffer
+    b64 += 4 * h.cut_region.size() + 8 * nx1;
+    b32 += 4 * nx1;
+    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc + nx1;
     m64 += 8 * C * per_col;
     m32 += 4 * C * per_col;
   }

@@ -88,6 +88,8 @@ struct CutPatchGroup {          // cut patches of one colour on one level
   std::vector<int64_t> inv_off; // offset of its dense inverse (size n_patch + 1)
   std::vector<int32_t> nodes;   // lattice node indices of the internal DoFs
   std::vector<double> inv;      // dense symmetric N_j x N_j inverses
+  std::vector<uint8_t> nxt;     // per node: bit 0 (1) it is also an internal DoF of a cut patch of
+                                // the next (previous) colour with cut patches, cyclically
 };
 
 struct HostLevel {
@@ -108,6 +110,7 @@ struct HostLevel {
   int n_cut = 0;
   std::vector<int32_t> int_vertex[8];  // interior patches per colour (vertex linear index)
   CutPatchGroup cut[8];
+  std::vector<int32_t> cut_region;  // active nodes that a cut colour step reads (closures and ghost halos)
   int64_t n_int_patches = 0, n_cut_patches = 0;
   double max_local_cond = 0;
 };

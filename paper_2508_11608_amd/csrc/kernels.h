@@ -46,8 +46,20 @@ struct CutGroupDev {
   const void* inv;           // symmetric dense inverses, scalar type of the path
   const float* inv_tiles;    // FP32 inverses in MFMA tile order (see k_cut_solve_mfma), or null
   const int64_t* tile_off;   // tile offsets, n_patch + 1, or null
+  const uint8_t* nxt;        // per node: bit 0 (1) also internal to the next (previous) cut colour
   template <typename T>
   __host__ __device__ const T* inv_t() const { return static_cast<const T*>(inv); }
+};
+
+// Copy part of a two-buffer cut step: dst[nodes[i]] = src[nodes[i]] for the i < n
+// whose skip[i] has none of the bits of mask, in nblk extra blocks placed before
+// the patch blocks.
+struct CopyJob {
+  const int32_t* nodes = nullptr;
+  const uint8_t* skip = nullptr;
+  int mask = 0;
+  int64_t n = 0;
+  int nblk = 0;
 };
 
 constexpr int kMaxCols = 8;  // columns (right-hand sides) of one multi-column launch
@@ -80,9 +92,21 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
                                 hipStream_t s, int ncol = 1);
+// Cut colour step, phase 1.  xb == nullptr: the corrections d_j go to dbuf
+// (launch_cut_update adds them).  Otherwise two-buffer form: x is read, and
+// xb receives x + d_j on the internal DoFs of the colour plus the copy job
+// (build it with cut_copy_job; x and xb are distinct buffers).
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s, int ncol = 1);
+                            hipStream_t s, int ncol = 1, T* xb = nullptr, const CopyJob& cj = CopyJob());
+// Copy job of a two-buffer step after the step of colour group Gp: the nodes of
+// Gp that are not internal to the current colour (mask 1: next colour in
+// increasing order, 2: in decreasing order).
+CopyJob cut_copy_job(int d, int k, const CutGroupDev& Gp, int mask);
+// dst[nodes[i]] = src[nodes[i]] (ncol columns, ld apart)
+template <typename T>
+hipError_t launch_copy_nodes(const int32_t* nodes, int64_t n, const T* src, T* dst, int64_t ld, hipStream_t s,
+                             int ncol = 1);
 // FP32, ncol <= kMaxCols columns, local solves on the matrix cores (needs
 // inv_tiles); W is the ghost-face work buffer (ncol columns), rewritten here.
 hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,

@@ -731,6 +731,7 @@ struct CutShape {
   static constexpr int NF = D * 3 * (1 << (D - 1));       // faces touching a 2^d patch
   static constexpr int NT = Pow<K + 1, D - 1>::v;         // nodes of a cell face
   static constexpr int THREADS = Shape<D, K>::NP <= 64 ? 64 : 128;  // one thread per internal node at least
+  static constexpr int COPY = 8;                                      // copy-job items per thread of a copy block
   static_assert(Shape<D, K>::NP <= THREADS, "a cut-patch block needs a thread per internal node");
 };
 
@@ -822,11 +823,11 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
 // enumerated arithmetically (absent nodes and inactive cells give zero).  A
 // pair needs its cell row (uncut stiffness or cut-cell matrix) and k (k+1)^{d-1}
 // terms per incident ghost face; each node sums its pairs in a fixed order.
-// Called by all threads of the block (it synchronises); the LDS buffers are
-// reused on the next call.
+// xold receives x at the thread's node.  Called by all threads of the block
+// (it synchronises); the LDS buffers are reused on the next call.
 template <int D, int K, typename T>
 __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, const T* __restrict__ x,
-                          CutSmem<D, K, T>& sm) {
+                          CutSmem<D, K, T>& sm, T* xold) {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, W1 = S::NC1, NF = C::NF, NT = C::NT;
@@ -1032,6 +1033,8 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
   __syncthreads();
   T ax = 0;
   if (tid < nj) {
+    // x at the node itself (closure index = patch coordinates)
+    *xold = sm.xs[pi[0] + W1 * pi[1] + (D == 3 ? W1 * W1 * pi[2] : 0)];
     // the node's pairs: per direction index j = p - 1 (layer 0, p <= k) and
     // j = p (layer 1, p >= k), in increasing pair index
     int jlo[3], jn[3];
@@ -1059,46 +1062,67 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
 
 // Cut patches, phase 1: residual on the internal nodes and dense local solve
 // d_j = A_j^{-1} r_j (GEMV with the symmetric inverse), one block per patch
-// and one column per blockIdx.y (columns are n_nodes apart in x and b and
-// n_nodes of the colour apart in dbuf).
+// and one column per blockIdx.y (columns are n_nodes apart in x, b and xb and
+// n_nodes of the colour apart in dbuf).  With xb == nullptr d_j goes to dbuf;
+// otherwise xb = x + d_j on the patch's internal DoFs (same-coloured patches
+// share none), and the first cj.nblk blocks copy the nodes of the copy job
+// from x to xb instead of solving a patch.
 template <int D, int K, typename T>
 __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
                                                                         const T* __restrict__ x,
                                                                         const T* __restrict__ b,
-                                                                        T* __restrict__ dbuf) {
+                                                                        T* __restrict__ dbuf, T* __restrict__ xb,
+                                                                        CopyJob cj) {
   using S = Shape<D, K>;
+  using C = CutShape<D, K>;
   __shared__ CutSmem<D, K, T> sm;
   __shared__ T rs[S::NP];
   const int tid = threadIdx.x;
-  const int gp = blockIdx.x;
   x += blockIdx.y * L.n_nodes;
   b += blockIdx.y * L.n_nodes;
   dbuf += blockIdx.y * G.n_nodes;
+  if (xb) xb += blockIdx.y * L.n_nodes;
+  if ((int)blockIdx.x < cj.nblk) {
+    // copy block: C::COPY items per thread, index loads first, then the values
+    int32_t nd[C::COPY];
+#pragma unroll
+    for (int u = 0; u < C::COPY; ++u) {
+      const int64_t i = ((int64_t)blockIdx.x * C::COPY + u) * C::THREADS + tid;
+      nd[u] = (i < cj.n && !(cj.skip[i] & cj.mask)) ? cj.nodes[i] : -1;
+    }
+    T v[C::COPY];
+#pragma unroll
+    for (int u = 0; u < C::COPY; ++u) v[u] = nd[u] >= 0 ? x[nd[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < C::COPY; ++u)
+      if (nd[u] >= 0) xb[nd[u]] = v[u];
+    return;
+  }
+  const int gp = blockIdx.x - cj.nblk;
   int V[3] = {0, 0, 0}, pi[3] = {0, 0, 0};
   const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V, pi);
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
   const T bval = node >= 0 ? b[node] : (T)0;  // fetched long before it is needed
-  const T ax = cut_patch_ax<D, K, T>(L, nj, V, pi, x, sm);
+  T xold = 0;
+  const T ax = cut_patch_ax<D, K, T>(L, nj, V, pi, x, sm, &xold);
   if (tid < nj) rs[tid] = bval - ax;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
   // (blockDim >= NP >= nj).  Small patches issue all loads of the row at once,
-  // larger ones eight at a time.
+  // larger ones in batches.
+  if (tid >= nj) return;
   const T* inv = G.inv_t<T>() + G.inv_off[gp];
+  T dv;
   if constexpr (S::NP <= 32) {
-    if (tid < nj) {
-      T v[S::NP];
+    T v[S::NP];
 #pragma unroll
-      for (int j = 0; j < S::NP; ++j) v[j] = j < nj ? inv[(int64_t)j * nj + tid] : (T)0;
-      T acc[4] = {0, 0, 0, 0};
+    for (int j = 0; j < S::NP; ++j) v[j] = j < nj ? inv[(int64_t)j * nj + tid] : (T)0;
+    T acc[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j < nj ? j : 0];
-      dbuf[off + tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    }
-    return;
-  }
-  if (tid < nj) {
+    for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j < nj ? j : 0];
+    dv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  } else {
     // batches of 32 (FP32) or 16 (FP64) independent loads
     constexpr int NB = sizeof(T) == 4 ? 32 : 16;
     const int i = tid;
@@ -1112,8 +1136,12 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
 #pragma unroll
       for (int u = 0; u < NB; ++u) acc[u % 8] += v[u] * rs[j + u < nj ? j + u : 0];
     }
-    dbuf[off + i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    dv = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
+  if (xb)
+    xb[node] = xold + dv;
+  else
+    dbuf[off + tid] = dv;
 }
 
 // Residual rows of one cut patch for NCOL columns at once.  The patch closure
@@ -1408,6 +1436,17 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
   }
 }
 
+// dst = src on a node list (the cut region before a run of two-buffer cut steps).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_nodes(const int32_t* __restrict__ nodes, int64_t n,
+                                                    const T* __restrict__ src, T* __restrict__ dst, int64_t ld) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) {
+    const int64_t o = blockIdx.y * ld + nodes[e];
+    dst[o] = src[o];
+  }
+}
+
 // Cut patches, phase 2: x[I_j] += d_j for all patches of the colour.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cut_update(const int32_t* __restrict__ nodes, int64_t n,
@@ -1678,14 +1717,38 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
 
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s, int ncol) {
+                            hipStream_t s, int ncol, T* xb, const CopyJob& cj) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
-    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(G.n_patch, ncol), dim3(TH), 0, s, L, G, x, b,
-                       dbuf);
+    if (xb == nullptr && cj.nblk != 0) return hipErrorInvalidValue;  // a copy job needs the second buffer
+    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(cj.nblk + G.n_patch, ncol), dim3(TH), 0, s, L,
+                       G, x, b, dbuf, xb, cj);
     return hipGetLastError();
   });
+}
+
+CopyJob cut_copy_job(int d, int k, const CutGroupDev& Gp, int mask) {
+  CopyJob cj;
+  if (Gp.n_nodes == 0) return cj;
+  cj.nodes = Gp.nodes;
+  cj.skip = Gp.nxt;
+  cj.mask = mask;
+  cj.n = Gp.n_nodes;
+  (void)dispatch(d, k, [&](auto D, auto K) {
+    using C = dev::CutShape<D.value, K.value>;
+    cj.nblk = static_cast<int>((Gp.n_nodes + C::THREADS * C::COPY - 1) / (C::THREADS * C::COPY));
+    return hipSuccess;
+  });
+  return cj;
+}
+
+template <typename T>
+hipError_t launch_copy_nodes(const int32_t* nodes, int64_t n, const T* src, T* dst, int64_t ld, hipStream_t s,
+                             int ncol) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((dev::k_copy_nodes<T>), dim3(blocks(n), ncol), dim3(256), 0, s, nodes, n, src, dst, ld);
+  return hipGetLastError();
 }
 
 hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,
@@ -1769,7 +1832,8 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
                                               hipStream_t, int);                                                   \
   template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
-                                          hipStream_t, int);                                                       \
+                                          hipStream_t, int, T*, const CopyJob&);                                   \
+  template hipError_t launch_copy_nodes<T>(const int32_t*, int64_t, const T*, T*, int64_t, hipStream_t, int);      \
   template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, int64_t, hipStream_t, int);          \
   template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t,     \
                                             int);                                                                  \

@@ -475,6 +475,8 @@ void ghost_face_matrix(const Config& cfg, const Basis1D& B, double h, int dir, s
   }
 }
 
+void cut_step_sets(HostLevel& L, int d, int k);
+
 std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
   if (cfg.dim < 2 || cfg.dim > 3 || cfg.k < 1 || cfg.k > kMaxDeg || cfg.n_levels < 1 || cfg.coarse_cells < 1)
     return "EINVAL: unsupported dimension, degree or level count";
@@ -719,11 +721,62 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
         }
         if (!perr.empty()) return perr;
       }
+      cut_step_sets(L, d, k);
     }
   } catch (const std::exception& ex) {
     return std::string("EINVAL: ") + ex.what();
   }
   return "";
+}
+
+// Node sets of the cut colour steps of one level: the cut region (every active
+// node a cut step reads: the closure of each cut patch and the cells across its
+// ghost faces, i.e. cells V-2 and V+1 along one direction) and, per colour, which
+// internal DoFs are also internal DoFs of the next / previous colour that has
+// cut patches.
+void cut_step_sets(HostLevel& L, int d, int k) {
+  LevelGeom geo{d, k, L.N, L.nn};
+  const int NV = L.N + 1;
+  std::vector<uint8_t> member(static_cast<size_t>(L.n_nodes), 0), region(static_cast<size_t>(L.n_nodes), 0);
+  int present[8], np = 0;
+  for (int c = 0; c < 8; ++c) {
+    for (int32_t n : L.cut[c].nodes) member[n] |= static_cast<uint8_t>(1u << c);
+    if (!L.cut[c].vertex.empty()) present[np++] = c;
+  }
+  const int span = 4;  // cells V-2 .. V+1 per direction
+  for (int c = 0; c < 8; ++c)
+    for (int32_t v : L.cut[c].vertex) {
+      int V[kMaxDim];
+      for (int j = 0, r = v; j < d; ++j) { V[j] = r % NV; r /= NV; }
+      for (int o = 0; o < ipow(span, d); ++o) {
+        int ci[kMaxDim], outer = 0;
+        bool in = true;
+        for (int j = 0, r = o; j < d; ++j, r /= span) {
+          const int t = r % span;
+          ci[j] = V[j] - 2 + t;
+          outer += t == 0 || t == span - 1;
+          in &= ci[j] >= 0 && ci[j] < L.N;
+        }
+        if (!in || outer > 1) continue;
+        int I[kMaxDim] = {0, 0, 0};
+        for (int q = 0; q < ipow(k + 1, d); ++q) {
+          for (int j = 0, r = q; j < d; ++j, r /= k + 1) I[j] = k * ci[j] + r % (k + 1);
+          region[geo.node(I)] = 1;
+        }
+      }
+    }
+  L.cut_region.clear();
+  for (int64_t n = 0; n < L.n_nodes; ++n)
+    if (region[n] && L.node_dof[n] >= 0) L.cut_region.push_back(static_cast<int32_t>(n));
+  for (int i = 0; i < np; ++i) {
+    const int c = present[i], fwd = present[(i + 1) % np], bwd = present[(i + np - 1) % np];
+    CutPatchGroup& g = L.cut[c];
+    g.nxt.resize(g.nodes.size());
+    for (size_t t = 0; t < g.nodes.size(); ++t) {
+      const uint8_t m = member[g.nodes[t]];
+      g.nxt[t] = static_cast<uint8_t>(((m >> fwd) & 1) | (((m >> bwd) & 1) << 1));
+    }
+  }
 }
 
 void manufactured_rhs(const Hierarchy& H, std::vector<double>& b) {
