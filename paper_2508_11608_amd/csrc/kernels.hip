@@ -742,7 +742,12 @@ struct CutSmem {
   using C = CutShape<D, K>;
   double tab[S::T_D1 + K * S::N1 + K - S::T_MHAT];  // mhat | d0 | d1 | gc
   static constexpr int NPAIR = Pow<2 * K, D>::v;  // (node, cell) pairs of a patch, see cut_patch_ax
-  T xs[S::NC];                                   // x on the patch closure
+  // FP64 Q2 in 3-D stages the halo of the ghost faces too (measured faster
+  // there; elsewhere the extra staging costs more than the scattered loads)
+  static constexpr bool kHalo = sizeof(T) == 8 && D == 3 && K == 2;
+  static constexpr int NH = K * Pow<S::NC1, D - 1>::v;  // nodes of one halo slab
+  static constexpr int NE = S::NC + (kHalo ? 2 * D * NH : 0);
+  T xs[NE];  // x on the patch closure, then the halo slabs (dir, side), see cut_patch_ax
   T Wf[C::NF][K][C::NT];
   T parts[NPAIR];
   int16_t slot[S::NP];  // row of the patch's node at each internal position, -1 if absent
@@ -836,6 +841,167 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
   const double* d0 = sm.tab + (S::T_D0 - S::T_MHAT);
   const double* d1 = sm.tab + (S::T_D1 - S::T_MHAT);
   const double* gc = sm.tab + (S::T_GC - S::T_MHAT);
+  if constexpr (CutSmem<D, K, T>::kHalo) {
+  // Stage x on the closure and on the halo slabs that ghost faces on the
+  // patch boundary need: slab (a, side) holds the k node layers beyond the
+  // closure along direction a (cell V-2 for side 0, V+1 for side 1) over the
+  // closure's tangential range, node layers fastest.  Coordinates are relative
+  // to the closure origin k (V-1).
+  constexpr int NH = CutSmem<D, K, T>::NH, NE = CutSmem<D, K, T>::NE;
+  uint32_t need = 0;  // bit 2a+side: slab (a, side) is read by a ghost face
+#pragma unroll
+  for (int o = 0; o < (1 << D); ++o) {
+    const uint8_t g = sm.cgh[o];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (((o >> a) & 1) == 0 && (g & (1 << (2 * a)))) need |= 1u << (2 * a);
+      if (((o >> a) & 1) == 1 && (g & (1 << (2 * a + 1)))) need |= 1u << (2 * a + 1);
+    }
+  }
+  constexpr int NIT = (NE + C::THREADS - 1) / C::THREADS;
+  T v[NIT];
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int e = tid + C::THREADS * u;
+    v[u] = 0;
+    int rr[3];
+    bool ld = e < NE;
+    if (e < NC) {
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { rr[a] = r % W1; r /= W1; }
+    } else if (ld) {
+      const int h = e - NC, slab = h / NH, dir = slab >> 1, side = slab & 1;
+      int r = h % NH;
+      const int layer = r % K;
+      r /= K;
+      ld = (need >> slab) & 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (a == dir) {
+          rr[a] = side ? 2 * K + 1 + layer : layer - K;
+        } else {
+          rr[a] = r % W1;
+          r /= W1;
+        }
+      }
+    }
+    if (ld) {
+      int I[3];
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        I[a] = K * (V[a] - 1) + rr[a];
+        in = in && I[a] >= 0 && I[a] < L.nn;
+      }
+      if (in) v[u] = x[lat(D, L.nn, I)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NIT; ++u) {
+    const int e = tid + C::THREADS * u;
+    if (e < NE) sm.xs[e] = v[u];
+  }
+  __syncthreads();
+  // mass-contracted jumps W_m(i_t) of every ghost face touching the patch:
+  // face (dir, plane 0..2, tangential cell t), plane p between cell layers p-1, p
+  for (int task = tid; task < NF * K; task += nth) {
+    const int m = task % K;
+    const int f = task / K;
+    const int dir = f / (3 << (D - 1));
+    const int plane = (f >> (D - 1)) % 3;
+    const int t = f & ((1 << (D - 1)) - 1);
+    int o = 0, tb = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (a == dir) continue;
+      o |= ((t >> tb) & 1) << a;
+      ++tb;
+    }
+    bool ghost;
+    if (plane == 0) ghost = sm.cgh[o] & (1 << (2 * dir));               // lower face of layer 0
+    else if (plane == 1) ghost = sm.cgh[o] & (1 << (2 * dir + 1));      // between layers 0 and 1
+    else ghost = sm.cgh[o | (1 << dir)] & (1 << (2 * dir + 1));         // upper face of layer 1
+    if (!ghost) continue;
+    // closure strides of the normal (sd) and tangential (s0, s1) directions
+    // and the tangential cell offsets (K t0, K t1) of the face
+    int sd = 1, s0 = 0, s1 = 0, k0 = 0, k1 = 0, tb2 = 0, st = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (a == dir) {
+        sd = st;
+      } else if (tb2 == 0) {
+        s0 = st;
+        k0 = K * ((t >> tb2) & 1);
+        ++tb2;
+      } else {
+        s1 = st;
+        k1 = K * ((t >> tb2) & 1);
+        ++tb2;
+      }
+      st *= W1;
+    }
+    const int hbase = NC + 2 * dir * NH;
+    T dl[N1], du[N1];
+#pragma unroll
+    for (int bd = 0; bd <= K; ++bd) {
+      dl[bd] = (T)d1[m * N1 + bd];
+      du[bd] = (T)d0[m * N1 + bd];
+    }
+    // LDS index of the node with normal coordinate rd (first node of the lower
+    // cell at K (plane - 1)) and tangential coordinates (r0, r1)
+    auto idx = [&](int rd, int r0, int r1) {
+      if (rd >= 0 && rd <= 2 * K) return r0 * s0 + r1 * s1 + rd * sd;
+      const int side = rd > 2 * K;
+      return hbase + side * NH + (r0 + W1 * r1) * K + (side ? rd - 2 * K - 1 : rd + K);
+    };
+    T J[NT];
+#pragma unroll
+    for (int bt = 0; bt < NT; ++bt) {
+      const int r0 = k0 + bt % N1, r1 = D == 3 ? k1 + bt / N1 : 0;
+      T acc0 = 0, acc1 = 0;
+#pragma unroll
+      for (int bd = 0; bd <= K; ++bd) {
+        acc0 += dl[bd] * sm.xs[idx(K * (plane - 1) + bd, r0, r1)];
+        acc1 += du[bd] * sm.xs[idx(K * plane + bd, r0, r1)];
+      }
+      J[bt] = acc0 - acc1;
+    }
+    T mm[N1 * N1];
+#pragma unroll
+    for (int i = 0; i < N1 * N1; ++i) mm[i] = (T)mh[i];
+    if (D == 2) {
+#pragma unroll
+      for (int it = 0; it < N1; ++it) {
+        T acc = 0;
+#pragma unroll
+        for (int bt = 0; bt < N1; ++bt) acc += mm[it * N1 + bt] * J[bt];
+        sm.Wf[f][m][it] = acc;
+      }
+    } else {
+      // (Mhat x Mhat) J by two 1-D contractions
+      T H[NT];
+#pragma unroll
+      for (int b1 = 0; b1 < N1; ++b1)
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) {
+          T acc = 0;
+#pragma unroll
+          for (int b0 = 0; b0 < N1; ++b0) acc += mm[i0 * N1 + b0] * J[b0 + N1 * b1];
+          H[i0 + N1 * b1] = acc;
+        }
+#pragma unroll
+      for (int i1 = 0; i1 < N1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < N1; ++i0) {
+          T acc = 0;
+#pragma unroll
+          for (int b1 = 0; b1 < N1; ++b1) acc += mm[i1 * N1 + b1] * H[i0 + N1 * b1];
+          sm.Wf[f][m][i0 + N1 * i1] = acc;
+        }
+    }
+  }
+  } else {
   const int64_t nn = L.nn;
   // closure loads first (stored to LDS after the face jumps; blockDim == THREADS)
   constexpr int NIT = (NC + C::THREADS - 1) / C::THREADS;
@@ -950,6 +1116,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
   for (int u = 0; u < NIT; ++u) {
     const int e = tid + C::THREADS * u;
     if (e < NC) sm.xs[e] = v[u];
+  }
   }
   __syncthreads();
   // (node, cell) pairs

@@ -18,6 +18,7 @@ LIBRARY_PATH = os.path.join(_HERE, "libcutmg.so")
 CMG_STATUS = {0: "CMG_OK", -1: "CMG_EINVAL", -2: "CMG_ENOMEM", -3: "CMG_EGEOM", -4: "CMG_ENOTSPD",
               -5: "CMG_ENOTCONV", -6: "CMG_EBREAKDOWN", -7: "CMG_EHIP", 1: "CMG_PENDING"}
 CMG_PENDING = 1
+CMG_EINVAL = -1
 
 
 class CutmgError(RuntimeError):
@@ -393,8 +394,12 @@ class Server:
                            n_dofs if n_dofs is not None else 0)
         if st == CMG_PENDING:
             return None
+        if st == CMG_EINVAL and x is not None:
+            # no solution of that length: a failed request keeps none
+            st = _lib.cmg_poll(self._h, ticket, ctypes.byref(res), None, 0)
+            x = None
         if st != 0:
-            raise CutmgError(st, "poll failed (wrong solution length?)")
+            raise CutmgError(st, "poll failed")
         out = {"status": res.status, "n_dofs": res.n_dofs, "iterations": res.info.iterations,
                "rel_residual": res.info.rel_residual, "cache_hit": bool(res.cache_hit),
                "t_submit": res.t_submit, "t_start": res.t_start, "t_admitted": res.t_admitted,

@@ -64,7 +64,7 @@ def test_results_alone_equal_results_in_the_mix():
         (res1, x1), = _run(alone_srv, [(w, f, fp32)])
         alone_srv.close()
         assert res1["batch"] == 1
-        assert res["status"] == 0 and res1["status"] == 0
+        assert res["status"] == 0 and res1["status"] == 0, (w.name, fp32, res["status"], res1["status"])
         assert res["rel_residual"] <= 1e-8
         assert res["iterations"] == res1["iterations"]
         assert np.array_equal(x, x1), w.name
