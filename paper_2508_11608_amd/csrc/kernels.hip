@@ -721,7 +721,8 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
     src = dst;
     dst = t;
   }
-  if (active) x[node] += src[p * NP + i];
+  // x at the node is still in the staged closure: no second read of HBM
+  if (active) x[node] = xs[p][pi[0] + NC1 * pi[1] + (D == 3 ? NC1 * NC1 * pi[2] : 0)] + src[p * NP + i];
   }
 }
 
