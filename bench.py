@@ -243,7 +243,7 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1) -> dict:
+def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool = True) -> dict:
     """Algorithmic HBM bytes of every launch of one kernel kind in one V-cycle,
     keyed by (level, colour) (or level for 'apply'); s = 8 B (FP64 multigrid)
     or 4 B (FP32 multigrid), indices 4 B.  With m columns the matrix and index
@@ -254,9 +254,12 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1) -> dict:
         2k nodes), b on the internal nodes, x written on them, vertex index.
     cut_solve, per patch j:    s N_j^2 + N_j (4 + 2 s) + 12 + s (2k)^d
                                + s k^d (k+1)^d x (cut cells of the patch)
-        dense inverse, node list, b and correction, offsets, x over the
+        dense inverse, node list, b and the new x, offsets, x over the
         closure, and the k^d rows of every cut-cell matrix that belong to
-        internal nodes of the patch.
+        internal nodes of the patch; plus the copy blocks of a two-buffer step
+        after colour p: 5 B (node, flag) per DoF of p and 2 s per DoF of p
+        that the current colour does not own (every step of a pass but the
+        first, in both passes; averaged over the colour's launches).
     apply (residual), per DoF: 4 + 3 s, plus s (k+1)^{2d} per cut cell; the
         CG product A p once per iteration on the finest level, always FP64:
         4 + 2*8 per DoF plus 8 (k+1)^{2d} per cut cell.
@@ -275,6 +278,20 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1) -> dict:
         Nc = round(len(N) ** (1.0 / d))
         flags = N.reshape((Nc,) * d)  # index order (z, y, x) / (y, x)
         cut = (flags & 2) != 0
+        copy = {}
+        if kind == "cut_solve" and two_buffer:  # (the matrix-core step has no copy blocks)
+            nodes = {c: P.export(l, 32 + c, np.int32) for c in range(2 ** d)}
+            present = [c for c in range(2 ** d) if len(nodes[c])]
+            for i, c in enumerate(present):
+                total = 0
+                for prev in (present[i - 1], present[(i + 1) % len(present)]):  # forward, backward pass
+                    first = (prev == present[-1] and c == present[0]) or (prev == present[0] and c == present[-1])
+                    times = w.n_c - 1 if (first and len(present) > 1) else w.n_c
+                    if len(present) == 1:
+                        times = w.n_c - 1
+                    moved = np.count_nonzero(~np.isin(nodes[prev], nodes[c]))
+                    total += times * (5 * len(nodes[prev]) + 2 * s * m * moved)
+                copy[c] = total / (2 * w.n_c)
         for col in range(2 ** d):
             if kind == "interior_step":
                 nv = len(P.export(l, 16 + col, np.int32))
@@ -295,13 +312,13 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1) -> dict:
                 idx = tuple(ci[ok][:, i] for i in reversed(range(d)))
                 ncut[ok] += cut[idx]
             b = (s * nj ** 2 + nj * (4 + 2 * s * m) + 12 + s * m * (2 * k) ** d + s * k ** d * nl * ncut).sum()
-            out[(l, col)] = int(b)
+            out[(l, col)] = int(b + copy.get(col, 0))
     return out
 
 
 def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False,
-             ncol: int = 1) -> dict:
-    per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8, ncol)
+             ncol: int = 1, two_buffer: bool = True) -> dict:
+    per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8, ncol, two_buffer)
     bytes_per_vcycle = sum(per_v.values())
     if kind != "apply":
         # each colour step runs twice per smoothing step for interior patches
@@ -376,7 +393,7 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
     dt = time.perf_counter() - t0
     launches, kms = P.timing_read(args.kernel)
     P.timing([])
-    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs)
+    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs, two_buffer=not fp32)
     tag = "fp32" if fp32 else "fp64"
     print(f"[bench] {tag} x{nrhs}: timed {args.steps} solves: {dt:.3f}s, {vcyc} multi V-cycles", file=sys.stderr,
           flush=True)
