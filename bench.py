@@ -317,8 +317,14 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool 
 
 
 def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False,
-             ncol: int = 1, two_buffer: bool = True) -> dict:
+             ncol: int = 1, two_buffer: bool = True, level: int = None) -> dict:
+    """Live roofline of one kernel kind: algorithmic bytes per launch over the
+    average HIP-event duration of its launches, on one level (the launches
+    timed) or on all of them."""
     per_v = algorithmic_bytes(P, w, kind, 4 if fp32 else 8, ncol, two_buffer)
+    if level is not None:
+        per_v = {key: v for key, v in per_v.items()
+                 if (key[0] if isinstance(key, tuple) else (w.n_levels - 1 if key == "cg" else key)) == level}
     bytes_per_vcycle = sum(per_v.values())
     if kind != "apply":
         # each colour step runs twice per smoothing step for interior patches
@@ -336,6 +342,7 @@ def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32
             traffic = t.get("bytes_per_launch")
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kind,
+            "level": "all" if level is None else level,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": ms_per_launch * 1e3,
             "launches_timed": launches}
 
@@ -379,7 +386,8 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
     for _ in range(args.warmup):
         P.solve_multi(B, X, rtol=1e-8)
     torch.cuda.synchronize()
-    P.timing([args.kernel])
+    fine = w.n_levels - 1
+    P.timing([args.kernel], level=fine)
     vcyc = 0
     lat = []
     infos = None
@@ -391,9 +399,9 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
         vcyc += max(i["iterations"] for i in infos)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, kms = P.timing_read(args.kernel)
+    launches, kms = P.timing_read(args.kernel, fine)
     P.timing([])
-    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs, two_buffer=not fp32)
+    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs, two_buffer=not fp32, level=fine)
     tag = "fp32" if fp32 else "fp64"
     print(f"[bench] {tag} x{nrhs}: timed {args.steps} solves: {dt:.3f}s, {vcyc} multi V-cycles", file=sys.stderr,
           flush=True)
@@ -429,7 +437,8 @@ def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
     for _ in range(args.warmup):
         P.solve(b, x, rtol=1e-8)
     torch.cuda.synchronize()
-    P.timing([args.kernel])
+    fine = w.n_levels - 1
+    P.timing([args.kernel], level=fine)  # the finest level's launches only: few events, no host stall
     its = 0
     rel = None
     lat = []
@@ -442,9 +451,9 @@ def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
         rel = info["rel_residual"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, kms = P.timing_read(args.kernel)
+    launches, kms = P.timing_read(args.kernel, fine)
     P.timing([])
-    roof = roofline(P, w, args.kernel, launches, kms, its, fp32)
+    roof = roofline(P, w, args.kernel, launches, kms, its, fp32, level=fine)
     tag = "fp32" if fp32 else "fp64"
     print(f"[bench] {tag}: timed {args.steps} solves: {dt:.3f}s, {its} V-cycles", file=sys.stderr, flush=True)
     r = torch.randn(n, dtype=torch.float64, device="cuda")

@@ -191,8 +191,11 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
  * Kinds: 0 operator apply / residual, 1 interior colour step, 2 cut colour
  * step (residual + dense solve), 3 cut colour update, 4 prolongation,
  * 5 restriction, 6 coarse solve, 7 layout (zero / scatter / gather),
- * 8 CG vector operations.  cmg_timing synchronises the device and clears the
- * records; 0 switches timing off. */
+ * 8 CG vector operations (bits 0..15).  Bits 16..23, when non-zero, hold
+ * 1 + the one level whose launches are timed (CMG_EINVAL beyond the
+ * finest); zero times every level.  cmg_timing synchronises the device,
+ * clears the records and creates the events up front; 0 switches timing
+ * off. */
 cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask);
 
 /* Launch count and summed event time (ms) of one kernel kind since the last

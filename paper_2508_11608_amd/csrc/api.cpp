@@ -114,6 +114,7 @@ struct cmg_problem {
   int device = 0;
   // kernel timing: launches of the kinds in timing_mask are bracketed by events
   unsigned timing_mask = 0;
+  int timing_level = -1;  // -1: every level
   struct Rec {
     int kind, level;
     hipEvent_t a, b;
@@ -121,6 +122,7 @@ struct cmg_problem {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
+  hipEvent_t done_ev = nullptr;  // see wait_stream
 };
 
 namespace {
@@ -425,6 +427,7 @@ struct KTimer {
   hipEvent_t b = nullptr;
   KTimer(cmg_problem* P_, int kind, int level, hipStream_t s_) : P(P_), s(s_) {
     if (!(P->timing_mask & (1u << kind))) return;
+    if (P->timing_level >= 0 && level != P->timing_level) return;
     if (P->pool_used + 2 > P->pool.size()) {
       for (int i = 0; i < 1024; ++i) {
         hipEvent_t e;
@@ -624,13 +627,30 @@ cmg_status gather(cmg_problem* P, int l, const T* lat, double* dst, hipStream_t 
   return CMG_OK;
 }
 
+// Wait until the work queued on s so far has finished by polling an event
+// from this thread: the Krylov loops wait for a reduction every iteration,
+// and a blocking stream synchronisation wakes the host up much later than
+// the GPU finishes.  A pending query leaves hipErrorNotReady as the thread's
+// last error, which is cleared once the event has completed.
+cmg_status wait_stream(cmg_problem* P, hipStream_t s) {
+  if (!P->done_ev) HIP_TRY(hipEventCreateWithFlags(&P->done_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(P->done_ev, s));
+  for (;;) {
+    const hipError_t e = hipEventQuery(P->done_ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return fail(CMG_EHIP, hipGetErrorString(e));
+  }
+  (void)hipGetLastError();
+  return CMG_OK;
+}
+
 cmg_status dot(cmg_problem* P, const double* x, const double* y, int64_t n, hipStream_t s, double* out) {
   {
     KTimer t(P, kVector, P->H.cfg.n_levels - 1, s);
     HIP_TRY(cmg::launch_dot_partial(x, y, n, P->part, P->nblk, s));
   }
   HIP_TRY(hipMemcpyAsync(P->part_host, P->part, P->nblk * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  TRY(wait_stream(P, s));
   double acc = 0.0;
   for (int i = 0; i < P->nblk; ++i) acc += P->part_host[i];
   *out = acc;
@@ -646,7 +666,7 @@ cmg_status dot_cols(cmg_problem* P, const double* x, const double* y, int64_t n,
   }
   HIP_TRY(hipMemcpyAsync(P->mpart_host, P->mpart, static_cast<size_t>(ncol) * P->nblk * sizeof(double),
                          hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  TRY(wait_stream(P, s));
   for (int c = 0; c < ncol; ++c) {
     double acc = 0.0;
     for (int i = 0; i < P->nblk; ++i) acc += P->mpart_host[c * P->nblk + i];
@@ -664,7 +684,7 @@ cmg_status rows_dot(cmg_problem* P, const double* V, const double* w, int64_t n,
   }
   HIP_TRY(hipMemcpyAsync(P->gpart_host, P->gpart, static_cast<size_t>(m) * P->nblk * sizeof(double),
                          hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  TRY(wait_stream(P, s));
   for (int j = 0; j < m; ++j) {
     double acc = 0.0;
     for (int i = 0; i < P->nblk; ++i) acc += P->gpart_host[j * P->nblk + i];
@@ -876,6 +896,7 @@ void cmg_destroy(cmg_problem* p) {
   if (p->mpart_host) (void)hipHostFree(p->mpart_host);
   if (p->gpart_host) (void)hipHostFree(p->gpart_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  if (p->done_ev) (void)hipEventDestroy(p->done_ev);
   delete p;
 }
 
@@ -1305,9 +1326,18 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
 cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {
   TRY(check_device(p));
   HIP_TRY(hipDeviceSynchronize());
-  p->timing_mask = kind_mask;
+  const int lv = static_cast<int>((kind_mask >> 16) & 0xffu) - 1;
+  if (lv >= static_cast<int>(p->lv.size())) return fail(CMG_EINVAL, "timing level out of range");
+  p->timing_mask = kind_mask & 0xffffu;
+  p->timing_level = lv;
   p->recs.clear();
   p->pool_used = 0;
+  // create the events now rather than inside the timed launches
+  while (p->timing_mask && p->pool.size() < 8192) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    p->pool.push_back(e);
+  }
   return CMG_OK;
 }
 

@@ -316,11 +316,14 @@ class Problem:
     KERNEL_KINDS = {"apply": 0, "interior_step": 1, "cut_solve": 2, "cut_update": 3, "prolong": 4,
                     "restrict": 5, "coarse": 6, "layout": 7, "vector": 8}
 
-    def timing(self, kinds=()):
-        """Bracket the launches of the named kernel kinds with HIP events (empty: off)."""
+    def timing(self, kinds=(), level: int = None):
+        """Bracket the launches of the named kernel kinds with HIP events (empty:
+        off), on every level or only on `level`."""
         mask = 0
         for k in kinds:
             mask |= 1 << self.KERNEL_KINDS[k]
+        if mask and level is not None:
+            mask |= (level + 1) << 16
         _check(_lib.cmg_timing(self._h, mask))
 
     def timing_read(self, kind: str, level: int = -1):
