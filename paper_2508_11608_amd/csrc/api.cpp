@@ -286,6 +286,34 @@ cmg_status upload_all(cmg_problem* P) {
         uint8_t* nxt;
         TRY(upload(own, g.nxt, &nxt));
         G.nxt = nxt;
+        // the 2^d cells of every patch: cut id and flags | ghost bits << 8
+        const int ncell = 1 << cfg.dim, NV = h.N + 1;
+        std::vector<int32_t> ccut(static_cast<size_t>(G.n_patch) * ncell, -1);
+        std::vector<uint16_t> cfg_bits(static_cast<size_t>(G.n_patch) * ncell, 0);
+        for (int q = 0; q < G.n_patch; ++q) {
+          int V[3] = {0, 0, 0};
+          for (int a = 0, r = g.vertex[q]; a < cfg.dim; ++a) { V[a] = r % NV; r /= NV; }
+          for (int o = 0; o < ncell; ++o) {
+            int64_t cl = 0, st = 1;
+            bool in = true;
+            for (int a = 0; a < cfg.dim; ++a) {
+              const int c = V[a] - 1 + ((o >> a) & 1);
+              in = in && c >= 0 && c < h.N;
+              cl += c * st;
+              st *= h.N;
+            }
+            if (!in) continue;
+            const size_t e = static_cast<size_t>(q) * ncell + o;
+            ccut[e] = h.cut_id[cl];
+            cfg_bits[e] = static_cast<uint16_t>(h.cell_flags[cl] | (h.ghost_mask[cl] << 8));
+          }
+        }
+        int32_t* dccut;
+        uint16_t* dcfg;
+        TRY(upload(own, ccut, &dccut));
+        TRY(upload(own, cfg_bits, &dcfg));
+        G.cell_cut = dccut;
+        G.cell_fg = dcfg;
       }
       d.cut32[c] = G;
       d.cut32[c].inv = nullptr;
@@ -928,7 +956,7 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
     for (int c = 0; c < 8; ++c) {
       const cmg::CutPatchGroup& g = h.cut[c];
       b64 += 4 * (h.int_vertex[c].size() + g.vertex.size() + g.off.size() + g.nodes.size()) + 8 * g.inv_off.size() +
-             8 * g.inv.size() + g.nxt.size();
+             8 * g.inv.size() + g.nxt.size() + 6 * g.vertex.size() * (size_t{1} << cfg.dim);
       b32 += 4 * g.inv.size();
       maxn = std::max(maxn, g.nodes.size());
       if (g.vertex.empty()) continue;

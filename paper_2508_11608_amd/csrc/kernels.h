@@ -43,6 +43,8 @@ struct CutGroupDev {
   const int64_t* inv_off;    // inverse offsets, n_patch + 1
   const int32_t* nodes;      // lattice nodes of the internal DoFs
   const int32_t* vertex;     // vertex index of every patch
+  const int32_t* cell_cut;   // per patch and cell o of its 2^d: cut-cell index, -1 if uncut or outside
+  const uint16_t* cell_fg;   // per patch and cell o: flags | ghost bits << 8 (0 outside the box)
   const void* inv;           // symmetric dense inverses, scalar type of the path
   const float* inv_tiles;    // FP32 inverses in MFMA tile order (see k_cut_solve_mfma), or null
   const int64_t* tile_off;   // tile offsets, n_patch + 1, or null

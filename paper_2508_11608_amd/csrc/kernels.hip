@@ -757,12 +757,11 @@ struct CutSmem {
 };
 
 // Patch set-up of the cut-patch kernel: level tables, the 2^d cells around the
-// vertex (flags, ghost bits, cut ids) and the row of every internal position.  Returns the lattice node of
-// the thread's internal node (tid < nj), else -1, and its patch coordinates
-// (1 .. 2k-1 per direction) in pi.
+// vertex (flags, ghost bits, cut ids) and the vertex coordinates.  Returns the
+// lattice node of the thread's internal node (tid < nj), else -1; the slot
+// table is filled by cut_patch_ax.
 template <int D, int K, typename T>
-__device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, CutSmem<D, K, T>& sm, int* V,
-                               int* pi) {
+__device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, CutSmem<D, K, T>& sm, int* V) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NCELL = 1 << D;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -776,44 +775,14 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
 #pragma unroll
     for (int a = 0; a < D; ++a) { V[a] = vr % NV; vr /= NV; }
   }
-  if (tid < NCELL) {
-    int c[3];
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      c[a] = V[a] - 1 + ((tid >> a) & 1);
-      in = in && c[a] >= 0 && c[a] < L.N;
-    }
-    uint8_t f = 0, g = 0;
-    int32_t cid = -1;
-    if (in) {  // independent loads (ghost bits are zero on inactive cells)
-      const int64_t cl = cell_lin(D, L.N, c);
-      f = L.flags[cl];
-      g = L.ghost[cl];
-      cid = L.cut_id[cl];
-    }
-    sm.cfl[tid] = f;
-    sm.cgh[tid] = g;
-    sm.ccut[tid] = cid;
+  if (tid < NCELL) {  // the patch's cells, indexed by the patch (no wait for its vertex)
+    const uint16_t fg = G.cell_fg[(int64_t)gp * NCELL + tid];
+    sm.cfl[tid] = static_cast<uint8_t>(fg & 0xff);
+    sm.cgh[tid] = static_cast<uint8_t>(fg >> 8);
+    sm.ccut[tid] = G.cell_cut[(int64_t)gp * NCELL + tid];
   }
-  int node = -1;
-  if (tid < nj) {
-    int r = G.nodes[off + tid];
-    node = r;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      pi[a] = r % L.nn - K * (V[a] - 1);
-      r /= L.nn;
-    }
-  }
-  __syncthreads();  // slot initialised
-  if (tid < nj) {
-    int pos = 0;
-#pragma unroll
-    for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (pi[a] - 1);
-    sm.slot[pos] = static_cast<int16_t>(tid);
-  }
-  __syncthreads();
+  const int node = tid < nj ? G.nodes[off + tid] : -1;  // used after the staging loads are issued
+  __syncthreads();  // tables, slot initialisation and cells visible
   return node;
 }
 
@@ -832,8 +801,8 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
 // xold receives x at the thread's node.  Called by all threads of the block
 // (it synchronises); the LDS buffers are reused on the next call.
 template <int D, int K, typename T>
-__device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, const T* __restrict__ x,
-                          CutSmem<D, K, T>& sm, T* xold) {
+__device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* pi, const T* __restrict__ x,
+                          const T* __restrict__ b, CutSmem<D, K, T>& sm, T* xold, T* bval) {
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, W1 = S::NC1, NF = C::NF, NT = C::NT;
@@ -897,6 +866,20 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
       }
       if (in) v[u] = x[lat(D, L.nn, I)];
     }
+  }
+  // the thread's node (its load was issued in the set-up): patch coordinates
+  // 1 .. 2k-1, row in the slot table, and b, whose load overlaps the staging
+  if (tid < nj) {
+    int r = node, pos = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      pi[a] = r % L.nn - K * (V[a] - 1);
+      r /= L.nn;
+    }
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (pi[a] - 1);
+    sm.slot[pos] = static_cast<int16_t>(tid);
+    *bval = b[node];
   }
 #pragma unroll
   for (int u = 0; u < NIT; ++u) {
@@ -1022,6 +1005,20 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, const int* pi, 
       }
       if (in) v[u] = x[lat(D, L.nn, I)];
     }
+  }
+  // the thread's node (its load was issued in the set-up): patch coordinates
+  // 1 .. 2k-1, row in the slot table, and b, whose load overlaps the staging
+  if (tid < nj) {
+    int r = node, pos = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      pi[a] = r % L.nn - K * (V[a] - 1);
+      r /= L.nn;
+    }
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) pos = pos * S::NP1 + (pi[a] - 1);
+    sm.slot[pos] = static_cast<int16_t>(tid);
+    *bval = b[node];
   }
   // mass-contracted jumps W_m(i_t) of every ghost face touching the patch:
   // face (dir, plane 0..2, tangential cell t), plane p between cell layers p-1, p
@@ -1268,12 +1265,11 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   }
   const int gp = blockIdx.x - cj.nblk;
   int V[3] = {0, 0, 0}, pi[3] = {0, 0, 0};
-  const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V, pi);
+  const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V);
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
-  const T bval = node >= 0 ? b[node] : (T)0;  // fetched long before it is needed
-  T xold = 0;
-  const T ax = cut_patch_ax<D, K, T>(L, nj, V, pi, x, sm, &xold);
+  T xold = 0, bval = 0;
+  const T ax = cut_patch_ax<D, K, T>(L, nj, V, node, pi, x, b, sm, &xold, &bval);
   if (tid < nj) rs[tid] = bval - ax;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
