@@ -55,7 +55,7 @@ struct CutGroupDev {
 
 // Copy part of a two-buffer cut step: dst[nodes[i]] = src[nodes[i]] for the i < n
 // whose skip[i] has none of the bits of mask, in nblk extra blocks placed before
-// the patch blocks.
+// the patch blocks (the launcher sets nblk for its block size).
 struct CopyJob {
   const int32_t* nodes = nullptr;
   const uint8_t* skip = nullptr;

@@ -800,7 +800,7 @@ __device__ int cut_patch_setup(const KLevel& L, const CutGroupDev& G, int gp, Cu
 // terms per incident ghost face; each node sums its pairs in a fixed order.
 // xold receives x at the thread's node.  Called by all threads of the block
 // (it synchronises); the LDS buffers are reused on the next call.
-template <int D, int K, typename T>
+template <int D, int K, typename T, int TH>
 __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* pi, const T* __restrict__ x,
                           const T* __restrict__ b, CutSmem<D, K, T>& sm, T* xold, T* bval) {
   using S = Shape<D, K>;
@@ -828,11 +828,11 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
       if (((o >> a) & 1) == 1 && (g & (1 << (2 * a + 1)))) need |= 1u << (2 * a + 1);
     }
   }
-  constexpr int NIT = (NE + C::THREADS - 1) / C::THREADS;
+  constexpr int NIT = (NE + TH - 1) / TH;
   T v[NIT];
 #pragma unroll
   for (int u = 0; u < NIT; ++u) {
-    const int e = tid + C::THREADS * u;
+    const int e = tid + TH * u;
     v[u] = 0;
     int rr[3];
     bool ld = e < NE;
@@ -883,7 +883,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
   }
 #pragma unroll
   for (int u = 0; u < NIT; ++u) {
-    const int e = tid + C::THREADS * u;
+    const int e = tid + TH * u;
     if (e < NE) sm.xs[e] = v[u];
   }
   __syncthreads();
@@ -988,11 +988,11 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
   } else {
   const int64_t nn = L.nn;
   // closure loads first (stored to LDS after the face jumps; blockDim == THREADS)
-  constexpr int NIT = (NC + C::THREADS - 1) / C::THREADS;
+  constexpr int NIT = (NC + TH - 1) / TH;
   T v[NIT];
 #pragma unroll
   for (int u = 0; u < NIT; ++u) {
-    const int e = tid + C::THREADS * u;
+    const int e = tid + TH * u;
     v[u] = 0;
     if (e < NC) {
       int I[3], r = e;
@@ -1112,7 +1112,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
   }
 #pragma unroll
   for (int u = 0; u < NIT; ++u) {
-    const int e = tid + C::THREADS * u;
+    const int e = tid + TH * u;
     if (e < NC) sm.xs[e] = v[u];
   }
   }
@@ -1232,8 +1232,8 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
 // otherwise xb = x + d_j on the patch's internal DoFs (same-coloured patches
 // share none), and the first cj.nblk blocks copy the nodes of the copy job
 // from x to xb instead of solving a patch.
-template <int D, int K, typename T>
-__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel L, CutGroupDev G,
+template <int D, int K, typename T, int TH>
+__global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
                                                                         const T* __restrict__ x,
                                                                         const T* __restrict__ b,
                                                                         T* __restrict__ dbuf, T* __restrict__ xb,
@@ -1252,7 +1252,7 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
     int32_t nd[C::COPY];
 #pragma unroll
     for (int u = 0; u < C::COPY; ++u) {
-      const int64_t i = ((int64_t)blockIdx.x * C::COPY + u) * C::THREADS + tid;
+      const int64_t i = ((int64_t)blockIdx.x * C::COPY + u) * TH + tid;
       nd[u] = (i < cj.n && !(cj.skip[i] & cj.mask)) ? cj.nodes[i] : -1;
     }
     T v[C::COPY];
@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve(KLevel 
   const int off = G.off[gp];
   const int nj = G.off[gp + 1] - off;
   T xold = 0, bval = 0;
-  const T ax = cut_patch_ax<D, K, T>(L, nj, V, node, pi, x, b, sm, &xold, &bval);
+  const T ax = cut_patch_ax<D, K, T, TH>(L, nj, V, node, pi, x, b, sm, &xold, &bval);
   if (tid < nj) rs[tid] = bval - ax;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
@@ -1816,6 +1816,7 @@ inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n
 // Grid cap for the grid-stride kernels that stage level tables in LDS: 256
 // CUs x 8 resident 256-thread blocks, so every block loads the tables once.
 constexpr unsigned kMaxResidentBlocks = 2048;
+constexpr int kLatencyPatches = 1536;  // cut-patch launches below this size use the larger blocks
 
 template <typename F>
 hipError_t dispatch(int d, int k, F&& f) {
@@ -1884,11 +1885,21 @@ hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G,
                             hipStream_t s, int ncol, T* xb, const CopyJob& cj) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
-    if (xb == nullptr && cj.nblk != 0) return hipErrorInvalidValue;  // a copy job needs the second buffer
-    hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T>), dim3(cj.nblk + G.n_patch, ncol), dim3(TH), 0, s, L,
-                       G, x, b, dbuf, xb, cj);
-    return hipGetLastError();
+    using C = dev::CutShape<D.value, K.value>;
+    if (xb == nullptr && cj.n != 0) return hipErrorInvalidValue;  // a copy job needs the second buffer
+    // small launches (the coarse levels) are bound by the latency of one patch
+    // block: twice the threads per patch shortens its serial passes; large
+    // ones keep the smaller blocks for occupancy
+    auto go = [&](auto th) {
+      constexpr int TH = decltype(th)::value;
+      CopyJob c2 = cj;
+      c2.nblk = static_cast<int>((cj.n + TH * C::COPY - 1) / (TH * C::COPY));
+      hipLaunchKernelGGL((dev::k_cut_solve<D.value, K.value, T, TH>), dim3(c2.nblk + G.n_patch, ncol), dim3(TH), 0,
+                         s, L, G, x, b, dbuf, xb, c2);
+      return hipGetLastError();
+    };
+    if (C::THREADS < 256 && G.n_patch < kLatencyPatches) return go(std::integral_constant<int, 2 * C::THREADS>{});
+    return go(std::integral_constant<int, C::THREADS>{});
   });
 }
 
@@ -1899,12 +1910,9 @@ CopyJob cut_copy_job(int d, int k, const CutGroupDev& Gp, int mask) {
   cj.skip = Gp.nxt;
   cj.mask = mask;
   cj.n = Gp.n_nodes;
-  (void)dispatch(d, k, [&](auto D, auto K) {
-    using C = dev::CutShape<D.value, K.value>;
-    cj.nblk = static_cast<int>((Gp.n_nodes + C::THREADS * C::COPY - 1) / (C::THREADS * C::COPY));
-    return hipSuccess;
-  });
-  return cj;
+  (void)d;
+  (void)k;
+  return cj;  // the launcher sizes the copy blocks for its block size
 }
 
 template <typename T>
