@@ -69,127 +69,6 @@ __device__ __forceinline__ int64_t cell_lin(int D, int N, const int* c) {
   return D == 2 ? c[0] + (int64_t)N * c[1] : c[0] + (int64_t)N * (c[1] + (int64_t)N * c[2]);
 }
 
-// Contribution of the ghost face (dir, side) of cell c to the row of its local
-// node il:  sum_m gc[m] sigma_m sum_{tangential b} prod M[il_j, b_j] jump_m(b).
-template <int D, int K, typename T>
-__device__ T ghost_row(const KLevel& L, const T* __restrict__ x, const double* tab, const int* c, const int* il,
-                       int dir, int side) {
-  using S = Shape<D, K>;
-  constexpr int N1 = S::N1;
-  const double* mh = tab + S::T_MHAT;
-  const double* d0 = tab + S::T_D0;
-  const double* d1 = tab + S::T_D1;
-  const double* gc = tab + S::T_GC;
-  int lower[3] = {c[0], c[1], D == 3 ? c[2] : 0};
-  if (side == 0) lower[dir] -= 1;
-  // coefficient of the test function: sign and derivative trace of cell c
-  double sig[K];
-#pragma unroll
-  for (int m = 0; m < K; ++m) sig[m] = gc[m] * (side == 1 ? d1[m * N1 + il[dir]] : -d0[m * N1 + il[dir]]);
-  T acc = 0;
-  constexpr int NT = Pow<N1, D - 1>::v;
-  for (int bt = 0; bt < NT; ++bt) {
-    int b[3];
-    double w = 1.0;
-    {
-      int r = bt;
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        if (j == dir) continue;
-        b[j] = r % N1;
-        r /= N1;
-        w *= mh[il[j] * N1 + b[j]];
-      }
-    }
-    T jm[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) jm[m] = 0;
-#pragma unroll
-    for (int bd = 0; bd <= K; ++bd) {
-      int I[3];
-#pragma unroll
-      for (int j = 0; j < D; ++j) I[j] = K * lower[j] + (j == dir ? bd : b[j]);
-      const T xl = x[lat(D, L.nn, I)];
-      I[dir] += K;  // same tangential node, upper cell
-      const T xu = x[lat(D, L.nn, I)];
-#pragma unroll
-      for (int m = 0; m < K; ++m) jm[m] += (T)d1[m * N1 + bd] * xl - (T)d0[m * N1 + bd] * xu;
-    }
-    T s = 0;
-#pragma unroll
-    for (int m = 0; m < K; ++m) s += (T)sig[m] * jm[m];
-    acc += (T)w * s;
-  }
-  return acc;
-}
-
-// (A x)_i for the lattice node I (general rows: uncut, cut and ghost terms).
-template <int D, int K, typename T>
-__device__ T row_apply(const KLevel& L, const T* __restrict__ x, const double* tab, const int* I) {
-  using S = Shape<D, K>;
-  constexpr int N1 = S::N1, NL = S::NL;
-  int cc[3][2], lc[3][2], nc[3] = {1, 1, 1};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const int i = I[a];
-    if (i % K == 0) {
-      const int v = i / K;
-      int n = 0;
-      if (v - 1 >= 0) { cc[a][n] = v - 1; lc[a][n] = K; ++n; }
-      if (v < L.N) { cc[a][n] = v; lc[a][n] = 0; ++n; }
-      nc[a] = n;
-    } else {
-      cc[a][0] = i / K;
-      lc[a][0] = i % K;
-      nc[a] = 1;
-    }
-  }
-  T acc = 0;
-  const int ncomb = nc[0] * nc[1] * (D == 3 ? nc[2] : 1);
-  for (int comb = 0; comb < ncomb; ++comb) {
-    int c[3], il[3];
-    int r = comb;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int s = r % nc[a];
-      r /= nc[a];
-      c[a] = cc[a][s];
-      il[a] = lc[a][s];
-    }
-    const int64_t cl = cell_lin(D, L.N, c);
-    const uint8_t f = L.flags[cl];
-    if (!(f & 1)) continue;
-    int iloc = il[0] + N1 * il[1];
-    if (D == 3) iloc += N1 * N1 * il[2];
-    const bool cut = f & 2;
-    const double* row = cut ? nullptr : tab + S::T_KCELL + iloc * NL;
-    const T* crow = cut ? L.cut_mats_t<T>() + ((int64_t)L.cut_id[cl] * NL + iloc) * NL : nullptr;
-    int base[3];
-#pragma unroll
-    for (int a = 0; a < D; ++a) base[a] = K * c[a];
-    T s = 0;
-#pragma unroll
-    for (int b = 0; b < NL; ++b) {
-      int J[3];
-      int rb = b;
-#pragma unroll
-      for (int a = 0; a < D; ++a) { J[a] = base[a] + rb % N1; rb /= N1; }
-      const T xv = x[lat(D, L.nn, J)];
-      s += (cut ? crow[b] : (T)row[b]) * xv;
-    }
-    acc += s;
-    const uint8_t g = L.ghost[cl];
-    if (g) {
-#pragma unroll
-      for (int dir = 0; dir < D; ++dir)
-#pragma unroll
-        for (int side = 0; side < 2; ++side)
-          if (g & (1 << (2 * dir + side))) acc += ghost_row<D, K, T>(L, x, tab, c, il, dir, side);
-    }
-  }
-  return acc;
-}
-
 template <int D, int K>
 __device__ void load_tables(const double* __restrict__ g, double* s, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = g[i];
@@ -1816,7 +1695,7 @@ inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n
 // Grid cap for the grid-stride kernels that stage level tables in LDS: 256
 // CUs x 8 resident 256-thread blocks, so every block loads the tables once.
 constexpr unsigned kMaxResidentBlocks = 2048;
-constexpr int kLatencyPatches = 1536;  // cut-patch launches below this size use the larger blocks
+constexpr int kLatencyPatches = 1536;  // cut-patch launches below this size (coarse levels) use larger blocks
 
 template <typename F>
 hipError_t dispatch(int d, int k, F&& f) {
