@@ -228,7 +228,13 @@ cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, 
  * what = 24+c / 32+c / 40+c / 48+c: cut patches of colour c - node offsets
  *           (int32, n_patch + 1), lattice nodes of their internal DoFs (int32),
  *           dense inverses (double, N_j x N_j each, consecutive), vertex
- *           index (int32, n_patch).
+ *           index (int32, n_patch);
+ * what = 56+c: per internal DoF of the cut patches of colour c (order of 32+c),
+ *           uint8: bit 0 set if it is also an internal DoF of a cut patch of
+ *           the next colour (cyclically) that has cut patches, bit 1 of the
+ *           previous one (the copy rule of the two-buffer cut steps);
+ * what = 64: the cut region, the active lattice nodes that a cut colour step
+ *           reads (int32, ascending).
  * *needed receives the byte size; buf may be NULL to query it. */
 cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed);
 

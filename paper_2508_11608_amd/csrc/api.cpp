@@ -1452,6 +1452,12 @@ cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size
   } else if (what >= 48 && what < 56) {
     src = h.cut[what - 48].vertex.data();
     sz = h.cut[what - 48].vertex.size() * sizeof(int32_t);
+  } else if (what >= 56 && what < 64) {
+    src = h.cut[what - 56].nxt.data();
+    sz = h.cut[what - 56].nxt.size();
+  } else if (what == 64) {
+    src = h.cut_region.data();
+    sz = h.cut_region.size() * sizeof(int32_t);
   } else {
     return fail(CMG_EINVAL, "unknown export kind");
   }
