@@ -792,12 +792,52 @@ void manufactured_rhs(const Hierarchy& H, std::vector<double>& b) {
 void fourier_rhs(const Hierarchy& H, int n_modes, const int* kappa, const double* amp, const double* phase,
                  std::vector<double>& b) {
   const int d = H.cfg.dim;
+  int kmax = 0;
+  for (int i = 0; i < n_modes * d; ++i) kmax = std::max(kmax, std::abs(kappa[i]));
+  constexpr int kTab = 16;
+  if (kmax > kTab) {  // direct evaluation
+    auto f = [&](const double* x) {
+      double v = 0.0;
+      for (int q = 0; q < n_modes; ++q) {
+        double arg = phase[q];
+        for (int j = 0; j < d; ++j) arg += M_PI * kappa[q * d + j] * x[j];
+        v += amp[q] * std::cos(arg);
+      }
+      return v;
+    };
+    load_vector(H, f, nullptr, b);
+    return;
+  }
+  // cos(pi kappa.x + theta) = Re(e^{i theta} prod_j e^{i pi kappa_j x_j}): two
+  // trigonometric calls per direction and point, the multiples of pi x_j by
+  // the angle-addition recurrence, a few products per mode
+  std::vector<double> cth(n_modes), sth(n_modes);
+  for (int q = 0; q < n_modes; ++q) {
+    cth[q] = std::cos(phase[q]);
+    sth[q] = std::sin(phase[q]);
+  }
   auto f = [&](const double* x) {
+    double c[kMaxDim][kTab + 1], sn[kMaxDim][kTab + 1];
+    for (int j = 0; j < d; ++j) {
+      const double c1 = std::cos(M_PI * x[j]), s1 = std::sin(M_PI * x[j]);
+      c[j][0] = 1.0;
+      sn[j][0] = 0.0;
+      for (int m = 0; m < kmax; ++m) {
+        c[j][m + 1] = c[j][m] * c1 - sn[j][m] * s1;
+        sn[j][m + 1] = sn[j][m] * c1 + c[j][m] * s1;
+      }
+    }
     double v = 0.0;
     for (int q = 0; q < n_modes; ++q) {
-      double arg = phase[q];
-      for (int j = 0; j < d; ++j) arg += M_PI * kappa[q * d + j] * x[j];
-      v += amp[q] * std::cos(arg);
+      double re = cth[q], im = sth[q];
+      for (int j = 0; j < d; ++j) {
+        const int kq = kappa[q * d + j], ka = std::abs(kq);
+        const double cr = c[j][ka], ci = kq < 0 ? -sn[j][ka] : sn[j][ka];
+        const double t = re * cr - im * ci;
+        im = re * ci + im * cr;
+        re = t;
+      }
+      v += amp[q] * re;
     }
     return v;
   };
