@@ -12,7 +12,10 @@
 //           + sum_{ghost faces F of those cells} row_i(G_F) x_{T1 u T2}
 // with E_T the uncut stiffness (shared, kept in LDS) or the dense matrix of a
 // cut cell, and G_F = sum_m c_m (d^m-jump) x (1-D mass on the face) built from
-// 1-D tables: a face needs no stored data.
+// 1-D tables: a face needs no stored data.  The operator kernel takes the
+// terms of the special cells (cut, or with a ghost face) from two pre-passes:
+// the mass-contracted jumps of every ghost face, then one value per special
+// cell and node.
 //
 // Smoother colour steps (paper eqs. (local-solver), (smoother-split)):
 //   interior patches: one fused kernel - x on the patch closure is staged in
@@ -22,9 +25,11 @@
 //     coloured interior patches read only their own closure, so the fused
 //     update is race free.
 //   cut patches: residual (general rows incl. ghost faces, which may reach into
-//     a same-coloured neighbour) and dense inverse GEMV into a buffer, then a
-//     second kernel adds the corrections: every patch of the colour sees the
-//     state at the start of the step.
+//     a same-coloured neighbour) and dense inverse GEMV; every patch of the
+//     colour must see the state at the start of the step, so the steps of a
+//     smoothing pass alternate between two x buffers (read one, write x + d
+//     and the previous colour's DoFs into the other), or, for the matrix-core
+//     kernel, write the corrections to a buffer that a second kernel adds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
