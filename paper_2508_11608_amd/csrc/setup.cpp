@@ -908,12 +908,29 @@ void load_vector(const Hierarchy& H, const std::function<double(const double*)>&
         double x[kMaxDim], xi[kMaxDim];
         for (int j = 0; j < d; ++j) x[j] = col.x[j];
         if (col.t1 > col.t0) {
+          // along the column only direction e varies: the basis factors of the
+          // other directions are tabulated once, and each point adds
+          // f w psi_{a_e}(xi_e) into a per-(tangential index, a_e) sum
+          for (int j = 0; j < d; ++j) xi[j] = (x[j] - lo[j]) / h;
+          tabulate(xi, false);
+          double acc[kMaxDeg + 1] = {};
+          double ee[kMaxDeg + 1];
           for (int t = 0; t < nq; ++t) {
             x[col.e] = col.t0 + (col.t1 - col.t0) * tx[t];
-            for (int j = 0; j < d; ++j) xi[j] = (x[j] - lo[j]) / h;
             const double fv = f(x) * col.w * (col.t1 - col.t0) * tw[t];
-            tabulate(xi, false);
-            for (int a = 0; a < nl; ++a) loc[a] += fv * phi(a, -1);
+            const double xe = (x[col.e] - lo[col.e]) / h;
+            for (int i = 0; i < n1; ++i) ee[i] = H.basis.eval(i, xe, 0);
+            for (int i = 0; i < n1; ++i) acc[i] += fv * ee[i];
+          }
+          for (int a = 0; a < nl; ++a) {
+            double v = 1.0;
+            int ae = 0;
+            for (int j = 0, r = a; j < d; ++j) {
+              if (j == col.e) ae = r % n1;
+              else v *= e[j][r % n1];
+              r /= n1;
+            }
+            loc[a] += v * acc[ae];
           }
         }
         if (col.surf && u) {
