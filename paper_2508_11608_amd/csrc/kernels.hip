@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
   const int nj = G.off[gp + 1] - off;
   T xold = 0, bval = 0;
   const T ax = cut_patch_ax<D, K, T, TH>(L, nj, V, node, pi, x, b, sm, &xold, &bval);
-  if (tid < nj) rs[tid] = bval - ax;
+  if (tid < S::NP) rs[tid] = tid < nj ? bval - ax : (T)0;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
   // (blockDim >= NP >= nj).  Small patches issue all loads of the row at once,
@@ -1165,10 +1165,10 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
   if constexpr (S::NP <= 32) {
     T v[S::NP];
 #pragma unroll
-    for (int j = 0; j < S::NP; ++j) v[j] = j < nj ? inv[(int64_t)j * nj + tid] : (T)0;
+    for (int j = 0; j < S::NP; ++j) v[j] = inv[(int64_t)(j < nj ? j : nj - 1) * nj + tid];  // rs[j >= nj] = 0
     T acc[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j < nj ? j : 0];
+    for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j];
     dv = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   } else {
     // batches of 32 (FP32) or 16 (FP64) independent loads
