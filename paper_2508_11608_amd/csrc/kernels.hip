@@ -1125,7 +1125,8 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
   using S = Shape<D, K>;
   using C = CutShape<D, K>;
   __shared__ CutSmem<D, K, T> sm;
-  __shared__ T rs[S::NP];
+  constexpr int RSN = (S::NP + 31) / 32 * 32;  // residual rows, padded with zeros to whole GEMV batches
+  __shared__ T rs[RSN];
   const int tid = threadIdx.x;
   x += blockIdx.y * L.n_nodes;
   b += blockIdx.y * L.n_nodes;
@@ -1154,18 +1155,20 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
   const int nj = G.off[gp + 1] - off;
   T xold = 0, bval = 0;
   const T ax = cut_patch_ax<D, K, T, TH>(L, nj, V, node, pi, x, b, sm, &xold, &bval);
-  if (tid < S::NP) rs[tid] = tid < nj ? bval - ax : (T)0;
+  if (tid < nj) rs[tid] = bval - ax;
+  for (int e = nj + tid; e < RSN; e += TH) rs[e] = 0;
   __syncthreads();
   // d = A_j^{-1} r: thread i takes row i (= column i, the inverse is symmetric)
   // (blockDim >= NP >= nj).  Small patches issue all loads of the row at once,
-  // larger ones in batches.
+  // larger ones in batches; loads past the last row re-read it (their
+  // residual entries are zero), so every load of a batch is issued unconditionally.
   if (tid >= nj) return;
   const T* inv = G.inv_t<T>() + G.inv_off[gp];
   T dv;
   if constexpr (S::NP <= 32) {
     T v[S::NP];
 #pragma unroll
-    for (int j = 0; j < S::NP; ++j) v[j] = inv[(int64_t)(j < nj ? j : nj - 1) * nj + tid];  // rs[j >= nj] = 0
+    for (int j = 0; j < S::NP; ++j) v[j] = inv[(int64_t)(j < nj ? j : nj - 1) * nj + tid];
     T acc[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < S::NP; ++j) acc[j % 4] += v[j] * rs[j];
@@ -1180,9 +1183,9 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
     for (int j = 0; j < nj; j += NB) {
       T v[NB];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) v[u] = j + u < nj ? inv[(int64_t)(j + u) * nj + i] : (T)0;
+      for (int u = 0; u < NB; ++u) v[u] = inv[(int64_t)(j + u < nj ? j + u : nj - 1) * nj + i];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) acc[u % 8] += v[u] * rs[j + u < nj ? j + u : 0];
+      for (int u = 0; u < NB; ++u) acc[u % 8] += v[u] * rs[j + u];
     }
     dv = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
