@@ -54,7 +54,7 @@ typedef struct cmg_problem cmg_problem;
  * background box is [box_lo, box_hi]^dim. */
 typedef struct {
   int dim;               /* 2 or 3 */
-  int n_shapes;          /* >= 1; cut-cell quadrature currently needs exactly 1 */
+  int n_shapes;          /* 1..16; Omega is their union (kinked where two surfaces meet) */
   const double* centers;
   const double* semi;
   double box_lo, box_hi;
@@ -81,10 +81,28 @@ typedef struct {
   double n_frac;         /* fractional iteration count n_it * log10(rtol) / log10(rel_residual) */
 } cmg_solve_info;
 
-/* Build the level hierarchy on the host (geometry, cut-cell quadrature,
- * element matrices, vertex patches, FP64 local and coarse inverses) and upload
- * it to the current HIP device.  Synchronous.  On success *out owns the data. */
+/* Build the level hierarchy on the host and upload it to the current HIP
+ * device (paper Section 2.1 for the nested levels, active and cut cells and
+ * the discrete spaces; Section 3 for the upfront CPU part: cut-cell quadrature,
+ * element matrices, and the local matrices of the cut vertex patches of
+ * Section 2.3, here inverted in FP64 by Cholesky; Section 2.2 for the exact
+ * coarse solver, here a dense inverse of A_0).  ls and prm are read only
+ * during the call.  Synchronous: returns when the device copies are complete.
+ * On success *out owns all host and device data until cmg_destroy.  Errors:
+ * CMG_EINVAL (bad arguments), CMG_EGEOM (no active cell on level 0, or an
+ * active cell whose parent is not active), CMG_ENOTSPD (a local or the coarse
+ * matrix is not positive definite), CMG_ENOMEM, CMG_EHIP; nothing is kept. */
 cmg_status cmg_setup(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out);
+
+/* Device footprint of the problem that cmg_setup would build, without
+ * building it: classifies the cells of every level and enumerates DoFs, ghost
+ * faces and vertex patches with their node sets (the cheap part of the
+ * set-up), but computes no cut-cell quadrature, element matrix or inverse.
+ * *bytes receives exactly what cmg_device_bytes(flags) reports after
+ * cmg_setup; n_dofs (may be NULL) the finest level's DoF count.  For callers
+ * that admit work by memory before paying for the set-up (the solve server).
+ * Host only, thread safe.  Errors as cmg_setup (CMG_EINVAL, CMG_EGEOM). */
+cmg_status cmg_footprint(const cmg_levelset* ls, const cmg_params* prm, int flags, size_t* bytes, int64_t* n_dofs);
 
 /* Same set-up without any device work (no HIP call): for inspecting the
  * hierarchy with cmg_export on machines without a GPU.  Device calls on such a
@@ -110,6 +128,15 @@ cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes);
  * convert their FP64 arguments and run in the selected precision. */
 cmg_status cmg_set_precision(cmg_problem* p, int fp32);
 
+/* Launch shapes chosen by launch size: cut colour steps of fewer than
+ * small_cut_launch patches run with twice the threads per patch block
+ * (default 1536; 0 never, a large value always), and the grid-stride operator
+ * and interior-patch kernels launch at most max_blocks blocks per column
+ * (default 2048, >= 1).  The arithmetic of every node is the same in every
+ * configuration, so results are bitwise independent of these choices; tests
+ * use it to run the configurations of large levels on small ones.  Host only. */
+cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks);
+
 /* Number of DoFs on a level (0 = coarsest, n_levels-1 = finest). */
 cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);
 
@@ -134,14 +161,26 @@ cmg_status cmg_smooth(cmg_problem* p, int level, int post, double* x, const doub
  * P_l^T x_l. */
 cmg_status cmg_transfer(cmg_problem* p, int level, int dir, const double* x, double* y, void* stream);
 
-/* Exact coarse solve x_0 = A_0^{-1} b_0 (dense FP64 inverse). */
+/* Exact coarse solve x_0 = A_0^{-1} b_0 on level 0 (paper Section 2.2: the
+ * V-cycle ends in an exact solve on the coarsest level; the paper names no
+ * solver, here a GEMV with the dense inverse from cmg_setup, FP32 in the
+ * mixed-precision mode). */
 cmg_status cmg_coarse_solve(cmg_problem* p, const double* b, double* x, void* stream);
 
-/* One V-cycle on the finest level with zero initial guess: z = B r. */
+/* One V-cycle on the finest level with zero initial guess: z = B r (paper
+ * Section 2.2, the standard V-cycle with one pre- and one post-smoothing step
+ * of the smoother of eq. (smoother-split); Section 4 for the one-step setting).
+ * The post-smoother runs the pre-smoother's colour steps in reverse, so B is
+ * symmetric and usable in CG. */
 cmg_status cmg_vcycle(cmg_problem* p, const double* r, double* z, void* stream);
 
-/* Preconditioned CG on the finest level from x = 0 until ||r|| <= rtol ||b||.
- * Synchronises the stream once per iteration.  info may be NULL. */
+/* Solve A_L x = b (paper Section 2.1, eq. (weak-equation) in matrix form) by
+ * CG preconditioned with the V-cycle (the paper uses the V-cycle inside
+ * GMRES, Section 2.2; the benchmark configurations use CG, which the symmetric
+ * V-cycle allows), from x = 0 until ||b - A x||_2 <= rtol ||b||_2, FP64 Krylov
+ * vectors and operator products.  Synchronises the stream once per iteration.
+ * info may be NULL.  CMG_ENOTCONV after maxit (x holds the last iterate),
+ * CMG_EBREAKDOWN when p^T A p <= 0 or is not finite. */
 cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, int maxit, cmg_solve_info* info,
                      void* stream);
 
@@ -218,11 +257,23 @@ cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, 
  * what = 0: counts, 8 int64 into buf: n_dofs, n_cells_active, n_cut_cells,
  *           n_interior_patches, n_cut_patches, sum of N_j^2 over cut patches,
  *           n_ghost_faces, lattice nodes per direction;
- * what = 1: lattice node index of every DoF (int32, n_dofs);
+ * what = 1 (CMG_EXPORT_PERM): lattice node index of every DoF (int32,
+ *           n_dofs): the permutation from the canonical order of the ABI
+ *           vectors to the lattice order the kernels work in (the canonical
+ *           order is the ascending lattice order of the active nodes);
  * what = 2: cell flags (uint8 per background cell, bit 0 active, bit 1 cut);
  * what = 3: element matrices of the cut cells in the order of their cell
  *           index, (k+1)^d x (k+1)^d row-major each, cell-local nodes x fastest;
  * what = 4: dense inverse of A_0 (level 0 only), row-major;
+ * what = 5 (CMG_EXPORT_QUADRATURE): the cut-cell rule of the element
+ *           matrices, double array: per cut cell in cut-id order the column
+ *           count m, then m columns of 7 + 2 dim doubles each: height
+ *           direction e, base point (dim entries, entry e unused), base
+ *           weight w, inside interval [t0, t1] along e (t1 <= t0: none),
+ *           surface flag, crossing point t_s, surface weight w_s and outward
+ *           unit normal (dim entries).  The volume rule integrates exactly
+ *           along every column; int_{T cap Omega} g = sum w int_{t0}^{t1} g
+ *           and int_{Gamma cap T} g = sum w_s g(x_s) over the surface columns;
  * what = 16+c: vertex index of every interior patch of colour c (int32;
  *           vertex V has index V_0 + (N+1) V_1 [+ (N+1)^2 V_2]);
  * what = 24+c / 32+c / 40+c / 48+c: cut patches of colour c - node offsets
@@ -238,6 +289,9 @@ cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, 
  * *needed receives the byte size; buf may be NULL to query it. */
 cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size_t bytes, size_t* needed);
 
+#define CMG_EXPORT_PERM 1
+#define CMG_EXPORT_QUADRATURE 5
+
 void cmg_destroy(cmg_problem* p);
 
 /* ---- serving: continuous batching of solves on one GPU -------------------
@@ -248,8 +302,10 @@ void cmg_destroy(cmg_problem* p);
  * PCG (cmg_solve_multi), so the V-cycles of the batch share every kernel
  * launch.  A hierarchy stays resident between batches (least-recently-used idle
  * hierarchies are evicted when a new one needs room); a new hierarchy is
- * admitted to the device when its exact footprint (cmg_device_bytes with the
- * multi-column buffers) fits into hbm_budget_bytes.  Batches of different
+ * admitted when its exact footprint (cmg_footprint with the multi-column
+ * buffers, plus the batch's b and x columns), computed before its set-up,
+ * fits into hbm_budget_bytes; one that exceeds the whole budget finishes with
+ * status CMG_ENOMEM without being set up.  Batches of different
  * slots overlap on the device.  Every result is independent of what else runs
  * and of the batch it was solved in, bit for bit (the column arithmetic of
  * cmg_solve_multi does not depend on the other columns).  Intended for callers

@@ -112,6 +112,7 @@ struct cmg_problem {
   double* part_host = nullptr;
   int nblk = 0;
   int device = 0;
+  cmg::LaunchPolicy launch;  // block size / grid cap choices by launch size
   // kernel timing: launches of the kinds in timing_mask are bracketed by events
   unsigned timing_mask = 0;
   int timing_level = -1;  // -1: every level
@@ -187,8 +188,18 @@ cmg_status alloc_zero(std::vector<void*>& owned, size_t n, T** dptr) {
   void* p = nullptr;
   if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return fail(CMG_ENOMEM, "device allocation failed");
   owned.push_back(p);
-  HIP_TRY(hipMemset(p, 0, n * sizeof(T)));
+  HIP_TRY(hipMemsetAsync(p, 0, n * sizeof(T), nullptr));
   *dptr = static_cast<T*>(p);
+  return CMG_OK;
+}
+
+// The uploads and zero fills above run on the null stream.  A caller's stream
+// created with hipStreamNonBlocking (the serving workers use them) is not
+// ordered after the null stream, so every function that allocates on first
+// use waits for that work before it returns and kernels on such a stream can
+// read the buffers.  Only the null stream is waited for, not other streams.
+cmg_status settle() {
+  HIP_TRY(hipStreamSynchronize(nullptr));
   return CMG_OK;
 }
 
@@ -330,7 +341,7 @@ cmg_status upload_all(cmg_problem* P) {
   P->nblk = static_cast<int>(std::min<int64_t>(1024, (n + 255) / 256));
   TRY(alloc_zero(own, static_cast<size_t>(P->nblk), &P->part));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->part_host), P->nblk * sizeof(double), hipHostMallocDefault));
-  return CMG_OK;
+  return settle();
 }
 
 // FP32 copies (rounded from the FP64 set-up) and FP32 work vectors, on first use.
@@ -358,6 +369,7 @@ cmg_status ensure_fp32(cmg_problem* P) {
     if (d.n_region > 0) TRY(alloc_zero(own, h.n_nodes, &d.v32.x1));
   }
   TRY(upload_f32(own, P->H.coarse_inv, &P->coarse32));
+  TRY(settle());
   P->fp32_ready = true;
   return CMG_OK;
 }
@@ -390,6 +402,7 @@ cmg_status ensure_multi(cmg_problem* P) {
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->mpart_host), C * P->nblk * sizeof(double),
                           hipHostMallocDefault));
   }
+  TRY(settle());
   ready = true;
   return CMG_OK;
 }
@@ -432,6 +445,7 @@ cmg_status ensure_tiles(cmg_problem* P) {
       G.tile_off = doff;
     }
   }
+  TRY(settle());
   P->tiles_ready = true;
   return CMG_OK;
 }
@@ -505,7 +519,8 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
   if (interior) {
     if (D.n_int[colour] == 0) return CMG_OK;
     KTimer t(P, kInterior, l, s);
-    HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s, ncol));
+    HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s, ncol,
+                                         P->launch));
     return CMG_OK;
   }
   const cmg::CutGroupDev& G = cutg<T>(D, colour);
@@ -516,10 +531,12 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
       if (multi && G.inv_tiles) {
         HIP_TRY(cmg::launch_cut_solve_mfma(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, ncol, s));
       } else {
-        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+        HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol, nullptr, cmg::CopyJob(),
+                                         P->launch));
       }
     } else {
-      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol));
+      HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol, nullptr, cmg::CopyJob(),
+                                       P->launch));
     }
   }
   KTimer t(P, kCutUpdate, l, s);
@@ -563,7 +580,8 @@ cmg_status cut_steps(cmg_problem* P, int l, bool post, hipStream_t s, int ncol, 
     cmg::CopyJob cj;
     if (i > 0) cj = cmg::cut_copy_job(d, k, cutg<T>(D, seq[i - 1]), post ? 2 : 1);
     KTimer t(P, kCutSolve, l, s);
-    HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, X[i % 2], v.b, v.dbuf, s, ncol, X[(i + 1) % 2], cj));
+    HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, X[i % 2], v.b, v.dbuf, s, ncol, X[(i + 1) % 2], cj,
+                                     P->launch));
   }
   for (size_t i = npp; i < seq.size(); ++i) TRY(colour_step<T>(P, l, false, seq[i], s, ncol, multi));
   return CMG_OK;
@@ -600,7 +618,7 @@ cmg_status apply_lat(cmg_problem* P, int l, const T* x, const T* b, T* y, hipStr
                      bool multi = false) {
   KTimer t(P, kApply, l, s);
   HIP_TRY(cmg::launch_apply<T>(P->H.cfg.dim, P->H.cfg.k, kl<T>(P->lv[l]), x, b, y, work<T>(P->lv[l], multi).W,
-                               work<T>(P->lv[l], multi).C, s, ncol));
+                               work<T>(P->lv[l], multi).C, s, ncol, P->launch));
   return CMG_OK;
 }
 
@@ -733,6 +751,7 @@ cmg_status ensure_gmres(cmg_problem* P, int restart) {
   P->gpart_host = nullptr;
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->gpart_host), (restart + 1) * P->nblk * sizeof(double),
                         hipHostMallocDefault));
+  TRY(settle());
   P->g_restart = restart;
   return CMG_OK;
 }
@@ -834,16 +853,72 @@ cmg_status prepare_multi(cmg_problem* p) {
   return CMG_OK;
 }
 
+
+// Device bytes of a hierarchy once uploaded (see cmg_device_bytes for flags),
+// from its counts only: it also serves hierarchies built without the numeric
+// part (no cut-cell matrices or inverses), which have every count and size.
+size_t hierarchy_bytes(const cmg::Hierarchy& H, int flags) {
+  const bool fp32 = flags & 1, multi = flags & 2;
+  const cmg::Config& cfg = H.cfg;
+  const size_t nt = static_cast<size_t>(cmg::tables_size(cfg.dim, cfg.k));
+  const size_t nw_face = static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
+  const size_t nl = static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+  const size_t C = cmg::kMaxCols;
+  size_t b64 = 0, b32 = 0, m64 = 0, m32 = 0;
+  for (const cmg::HostLevel& h : H.levels) {
+    size_t maxn = 0;
+    const size_t ncm = static_cast<size_t>(h.n_cut) * nl * nl;  // cut-cell matrix entries
+    b64 += h.cell_flags.size() + h.ghost_mask.size() + 4 * (h.cut_id.size() + h.dof_node.size()) +
+           8 * (ncm + nt) + 4 * (h.face_lower.size() + h.cell_gid.size() + h.cell_faces.size() +
+           h.tiles.size()) + h.face_dir.size();
+    b64 += 8 * (3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
+    b32 += 4 * (ncm + 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
+    for (int c = 0; c < 8; ++c) {
+      const cmg::CutPatchGroup& g = h.cut[c];
+      const size_t ninv = g.inv_off.empty() ? 0 : static_cast<size_t>(g.inv_off.back());
+      b64 += 4 * (h.int_vertex[c].size() + g.vertex.size() + g.off.size() + g.nodes.size()) + 8 * g.inv_off.size() +
+             8 * ninv + g.nxt.size() + 6 * g.vertex.size() * (size_t{1} << cfg.dim);
+      b32 += 4 * ninv;
+      maxn = std::max(maxn, g.nodes.size());
+      if (g.vertex.empty()) continue;
+      m32 += 8 * (g.vertex.size() + 1);  // tile offsets
+      for (size_t q = 0; q + 1 < g.off.size(); ++q) {
+        const size_t nj = static_cast<size_t>(g.off[q + 1] - g.off[q]);
+        m32 += 4 * ((nj + 15) / 16) * ((nj + 3) / 4) * 64;
+      }
+    }
+    b64 += 8 * maxn;
+    b32 += 4 * maxn;
+    std::vector<int32_t> spec;
+    special_cells(h, cfg.dim, &spec, nullptr, nullptr);
+    const size_t ncc = spec.size() * nl;
+    b64 += 8 * ncc;  // special-cell products of the operator
+    b32 += 4 * ncc;
+    b64 += 4 * (spec.size() * (2 + 2 * cfg.dim) + static_cast<size_t>(h.n_cells));  // special-cell lists
+    const size_t nx1 = h.cut_region.empty() ? 0 : static_cast<size_t>(h.n_nodes);  // second x buffer
+    b64 += 4 * h.cut_region.size() + 8 * nx1;
+    b32 += 4 * nx1;
+    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc + nx1;
+    m64 += 8 * C * per_col;
+    m32 += 4 * C * per_col;
+  }
+  const size_t nL = static_cast<size_t>(H.levels.back().n_dofs);
+  const size_t n0sq = static_cast<size_t>(H.n_coarse) * static_cast<size_t>(H.n_coarse);
+  b64 += 8 * n0sq + 8 * 4 * nL + 8 * 1024;
+  b32 += 4 * n0sq;
+  m64 += 8 * 4 * C * nL + 8 * C * 1024;
+  return b64 + (fp32 ? b32 : 0) + (multi ? m64 + (fp32 ? m32 : 0) : 0);
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* cmg_last_error(void) { return g_last_error.c_str(); }
 
-static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out, bool device) {
-  g_last_error.clear();
-  if (!ls || !prm || !out) return fail(CMG_EINVAL, "null argument");
-  *out = nullptr;
+// Checks the level set and the parameters and fills the host configuration.
+static cmg_status make_config(const cmg_levelset* ls, const cmg_params* prm, cmg::Config* out) {
+  if (!ls || !prm) return fail(CMG_EINVAL, "null argument");
   if (ls->dim < 2 || ls->dim > 3 || ls->n_shapes < 1 || !ls->centers || !ls->semi || !(ls->box_hi > ls->box_lo))
     return fail(CMG_EINVAL, "bad level set description");
   if (prm->k < 1 || prm->k > 3 || prm->n_levels < 1 || prm->n_levels > 12 || prm->coarse_cells < 1 ||
@@ -876,14 +951,28 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
   cfg.ghost_exp_mode = prm->ghost_exp_mode;
   cfg.n_c = prm->n_c;
   cfg.quad_n = prm->quad_n;
+  *out = cfg;
+  return CMG_OK;
+}
+
+static cmg_status hierarchy_status(const std::string& err) {
+  cmg_status st = CMG_EINVAL;
+  if (err.rfind("EGEOM", 0) == 0) st = CMG_EGEOM;
+  if (err.rfind("ENOTSPD", 0) == 0) st = CMG_ENOTSPD;
+  return fail(st, err);
+}
+
+static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_problem** out, bool device) {
+  g_last_error.clear();
+  if (!out) return fail(CMG_EINVAL, "null argument");
+  *out = nullptr;
+  cmg::Config cfg;
+  TRY(make_config(ls, prm, &cfg));
   auto* P = new cmg_problem();
   std::string err = cmg::build_hierarchy(cfg, P->H);
   if (!err.empty()) {
     delete P;
-    cmg_status st = CMG_EINVAL;
-    if (err.rfind("EGEOM", 0) == 0) st = CMG_EGEOM;
-    if (err.rfind("ENOTSPD", 0) == 0) st = CMG_ENOTSPD;
-    return fail(st, err);
+    return hierarchy_status(err);
   }
   if (!device) {
     P->fp32 = prm->precond_fp32 != 0;
@@ -940,52 +1029,30 @@ cmg_status cmg_upload(cmg_problem* p) {
 cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
   if (!p || !bytes) return fail(CMG_EINVAL, "null argument");
   if (flags < 0 || flags > 3) return fail(CMG_EINVAL, "flags: bit 0 FP32 copies, bit 1 multi-column buffers");
-  const bool fp32 = flags & 1, multi = flags & 2;
-  const cmg::Config& cfg = p->H.cfg;
-  const size_t nt = static_cast<size_t>(cmg::tables_size(cfg.dim, cfg.k));
-  const size_t nw_face = static_cast<size_t>(cfg.k) * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim - 1));
-  const size_t C = cmg::kMaxCols;
-  size_t b64 = 0, b32 = 0, m64 = 0, m32 = 0;
-  for (const cmg::HostLevel& h : p->H.levels) {
-    size_t maxn = 0;
-    b64 += h.cell_flags.size() + h.ghost_mask.size() + 4 * (h.cut_id.size() + h.dof_node.size()) +
-           8 * (h.cut_mats.size() + nt) + 4 * (h.face_lower.size() + h.cell_gid.size() + h.cell_faces.size() +
-           h.tiles.size()) + h.face_dir.size();
-    b64 += 8 * (3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
-    b32 += 4 * (h.cut_mats.size() + 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
-    for (int c = 0; c < 8; ++c) {
-      const cmg::CutPatchGroup& g = h.cut[c];
-      b64 += 4 * (h.int_vertex[c].size() + g.vertex.size() + g.off.size() + g.nodes.size()) + 8 * g.inv_off.size() +
-             8 * g.inv.size() + g.nxt.size() + 6 * g.vertex.size() * (size_t{1} << cfg.dim);
-      b32 += 4 * g.inv.size();
-      maxn = std::max(maxn, g.nodes.size());
-      if (g.vertex.empty()) continue;
-      m32 += 8 * (g.vertex.size() + 1);  // tile offsets
-      for (size_t q = 0; q + 1 < g.off.size(); ++q) {
-        const size_t nj = static_cast<size_t>(g.off[q + 1] - g.off[q]);
-        m32 += 4 * ((nj + 15) / 16) * ((nj + 3) / 4) * 64;
-      }
-    }
-    b64 += 8 * maxn;
-    b32 += 4 * maxn;
-    std::vector<int32_t> spec;
-    special_cells(h, cfg.dim, &spec, nullptr, nullptr);
-    const size_t ncc = spec.size() * static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
-    b64 += 8 * ncc;  // special-cell products of the operator
-    b32 += 4 * ncc;
-    b64 += 4 * (spec.size() * (2 + 2 * cfg.dim) + static_cast<size_t>(h.n_cells));  // special-cell lists
-    const size_t nx1 = h.cut_region.empty() ? 0 : static_cast<size_t>(h.n_nodes);  // second x buffer
-    b64 += 4 * h.cut_region.size() + 8 * nx1;
-    b32 += 4 * nx1;
-    const size_t per_col = 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face + maxn + ncc + nx1;
-    m64 += 8 * C * per_col;
-    m32 += 4 * C * per_col;
-  }
-  const size_t nL = static_cast<size_t>(p->H.levels.back().n_dofs);
-  b64 += 8 * p->H.coarse_inv.size() + 8 * 4 * nL + 8 * 1024;
-  b32 += 4 * p->H.coarse_inv.size();
-  m64 += 8 * 4 * C * nL + 8 * C * 1024;
-  *bytes = b64 + (fp32 ? b32 : 0) + (multi ? m64 + (fp32 ? m32 : 0) : 0);
+  *bytes = hierarchy_bytes(p->H, flags);
+  return CMG_OK;
+}
+
+cmg_status cmg_footprint(const cmg_levelset* ls, const cmg_params* prm, int flags, size_t* bytes,
+                         int64_t* n_dofs) {
+  g_last_error.clear();
+  if (!bytes) return fail(CMG_EINVAL, "null argument");
+  if (flags < 0 || flags > 3) return fail(CMG_EINVAL, "flags: bit 0 FP32 copies, bit 1 multi-column buffers");
+  cmg::Config cfg;
+  TRY(make_config(ls, prm, &cfg));
+  cmg::Hierarchy H;
+  const std::string err = cmg::build_hierarchy(cfg, H, false);
+  if (!err.empty()) return hierarchy_status(err);
+  *bytes = hierarchy_bytes(H, flags);
+  if (n_dofs) *n_dofs = H.levels.back().n_dofs;
+  return CMG_OK;
+}
+
+cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks) {
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (small_cut_launch < 0 || max_blocks < 1) return fail(CMG_EINVAL, "bad launch policy");
+  p->launch.small_cut_launch = small_cut_launch;
+  p->launch.max_blocks = static_cast<unsigned>(max_blocks);
   return CMG_OK;
 }
 
@@ -1408,6 +1475,7 @@ cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size
   if (level < 0 || level >= p->H.cfg.n_levels) return fail(CMG_EINVAL, "level out of range");
   const cmg::HostLevel& h = p->H.levels[level];
   std::vector<int64_t> counts;
+  std::vector<double> quad;
   const void* src = nullptr;
   size_t sz = 0;
   if (what == 0) {
@@ -1433,6 +1501,35 @@ cmg_status cmg_export(const cmg_problem* p, int level, int what, void* buf, size
   } else if (what == 3) {
     src = h.cut_mats.data();
     sz = h.cut_mats.size() * sizeof(double);
+  } else if (what == 5) {
+    // the cut-cell rule of the element matrices (columns), per cut cell in cut-id order
+    const cmg::Config& cfg = p->H.cfg;
+    const int d = cfg.dim;
+    for (int64_t c = 0; c < h.n_cells; ++c) {
+      if (h.cut_id[c] < 0) continue;
+      double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+      for (int j = 0, r = static_cast<int>(c); j < d; ++j) {
+        lo[j] = cfg.lo + (r % h.N) * h.h;
+        hi[j] = lo[j] + h.h;
+        r /= h.N;
+      }
+      std::vector<cmg::Column> cols;
+      cmg::cut_columns_union(d, cfg.shapes, lo, hi, cfg.quad_n, cfg.k + 1, cfg.quad_beta, cfg.union_depth, cols);
+      quad.push_back(static_cast<double>(cols.size()));
+      for (const cmg::Column& col : cols) {
+        quad.push_back(col.e);
+        for (int j = 0; j < d; ++j) quad.push_back(col.x[j]);
+        quad.push_back(col.w);
+        quad.push_back(col.t0);
+        quad.push_back(col.t1);
+        quad.push_back(col.surf ? 1.0 : 0.0);
+        quad.push_back(col.ts);
+        quad.push_back(col.sw);
+        for (int j = 0; j < d; ++j) quad.push_back(col.nrm[j]);
+      }
+    }
+    src = quad.data();
+    sz = quad.size() * sizeof(double);
   } else if (what == 4) {
     if (level != 0) return fail(CMG_EINVAL, "the coarse inverse lives on level 0");
     src = p->H.coarse_inv.data();

@@ -136,8 +136,11 @@ struct Hierarchy {
 };
 
 // Build everything; returns an empty string on success, else an error message
-// prefixed by its status name ("EGEOM:", "ENOTSPD:", "EINVAL:").
-std::string build_hierarchy(const Config& cfg, Hierarchy& H);
+// prefixed by its status name ("EGEOM:", "ENOTSPD:", "EINVAL:").  numeric =
+// false builds geometry, DoFs, ghost faces, patches and their node sets only
+// (no cut-cell quadrature, no element matrices, no inverses): every count and
+// size of the full set-up, for footprint estimates before the expensive part.
+std::string build_hierarchy(const Config& cfg, Hierarchy& H, bool numeric = true);
 
 // Load vector b_i = (f, phi_i)_Omega + (g, (gamma_D/h) phi_i - d_n phi_i)_Gamma on the
 // finest level, canonical order; g may be empty (homogeneous Dirichlet data).

@@ -66,6 +66,15 @@ struct CopyJob {
 
 constexpr int kMaxCols = 8;  // columns (right-hand sides) of one multi-column launch
 
+// Launch shape choices that depend on the size of a launch, settable per
+// problem so that tests can force the configuration a large level runs in on
+// a small one.  Results do not depend on them beyond rounding-free choices:
+// the arithmetic of every node is the same for any block size and grid cap.
+struct LaunchPolicy {
+  int small_cut_launch = 1536;  // cut colour steps with fewer patches use twice the threads per patch block
+  unsigned max_blocks = 2048;   // grid cap of the grid-stride kernels (operator tiles, interior patches)
+};
+
 // Per-column coefficients of the column-wise vector kernels.
 struct ColCoef {
   double v[kMaxCols];
@@ -90,17 +99,18 @@ int tables_size(int d, int k);
 // (n_spec (k+1)^d entries per column).
 template <typename T>
 hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, T* C, hipStream_t s,
-                        int ncol = 1);
+                        int ncol = 1, const LaunchPolicy& lp = LaunchPolicy());
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
-                                hipStream_t s, int ncol = 1);
+                                hipStream_t s, int ncol = 1, const LaunchPolicy& lp = LaunchPolicy());
 // Cut colour step, phase 1.  xb == nullptr: the corrections d_j go to dbuf
 // (launch_cut_update adds them).  Otherwise two-buffer form: x is read, and
 // xb receives x + d_j on the internal DoFs of the colour plus the copy job
 // (build it with cut_copy_job; x and xb are distinct buffers).
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s, int ncol = 1, T* xb = nullptr, const CopyJob& cj = CopyJob());
+                            hipStream_t s, int ncol = 1, T* xb = nullptr, const CopyJob& cj = CopyJob(),
+                            const LaunchPolicy& lp = LaunchPolicy());
 // Copy job of a two-buffer step after the step of colour group Gp: the nodes of
 // Gp that are not internal to the current colour (mask 1: next colour in
 // increasing order, 2: in decreasing order).

@@ -1700,10 +1700,10 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
 
-// Grid cap for the grid-stride kernels that stage level tables in LDS: 256
-// CUs x 8 resident 256-thread blocks, so every block loads the tables once.
-constexpr unsigned kMaxResidentBlocks = 2048;
-constexpr int kLatencyPatches = 1536;  // cut-patch launches below this size (coarse levels) use larger blocks
+// The defaults of LaunchPolicy: a grid cap of 256 CUs x 8 resident 256-thread
+// blocks for the grid-stride kernels that stage level tables in LDS (every
+// block loads the tables once), and larger blocks for cut-patch launches of
+// fewer than 1536 patches (the coarse levels).
 
 template <typename F>
 hipError_t dispatch(int d, int k, F&& f) {
@@ -1729,7 +1729,7 @@ int tables_size(int d, int k) {
 
 template <typename T>
 hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T* y, T* W, T* C, hipStream_t s,
-                        int ncol) {
+                        int ncol, const LaunchPolicy& lp) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     if (L.n_faces > 0) {
@@ -1748,7 +1748,7 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    const unsigned nb = std::min<unsigned>(static_cast<unsigned>(L.n_tiles), kMaxResidentBlocks / ncol + 1);
+    const unsigned nb = std::max(1u, std::min<unsigned>(static_cast<unsigned>(L.n_tiles), lp.max_blocks / ncol + 1));
     hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, C);
     return hipGetLastError();
   });
@@ -1756,11 +1756,11 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
 
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
-                                hipStream_t s, int ncol) {
+                                hipStream_t s, int ncol, const LaunchPolicy& lp) {
   if (nv == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
-    const unsigned nb = std::min<unsigned>(blocks(nv, PPB), kMaxResidentBlocks / ncol + 1);
+    const unsigned nb = std::max(1u, std::min<unsigned>(blocks(nv, PPB), lp.max_blocks / ncol + 1));
     hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, verts, nv,
                        x, b);
     return hipGetLastError();
@@ -1769,7 +1769,7 @@ hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* ve
 
 template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
-                            hipStream_t s, int ncol, T* xb, const CopyJob& cj) {
+                            hipStream_t s, int ncol, T* xb, const CopyJob& cj, const LaunchPolicy& lp) {
   if (G.n_patch == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     using C = dev::CutShape<D.value, K.value>;
@@ -1785,7 +1785,7 @@ hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G,
                          s, L, G, x, b, dbuf, xb, c2);
       return hipGetLastError();
     };
-    if (C::THREADS < 256 && G.n_patch < kLatencyPatches) return go(std::integral_constant<int, 2 * C::THREADS>{});
+    if (C::THREADS < 256 && G.n_patch < lp.small_cut_launch) return go(std::integral_constant<int, 2 * C::THREADS>{});
     return go(std::integral_constant<int, C::THREADS>{});
   });
 }
@@ -1887,11 +1887,12 @@ hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* 
 }
 
 #define CMG_INSTANTIATE(T)                                                                                      \
-  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, T*, hipStream_t, int); \
+  template hipError_t launch_apply<T>(int, int, const KLevel&, const T*, const T*, T*, T*, T*, hipStream_t, int, \
+                                      const LaunchPolicy&);                                                        \
   template hipError_t launch_interior_step<T>(int, int, const KLevel&, const int32_t*, int, T*, const T*,         \
-                                              hipStream_t, int);                                                   \
+                                              hipStream_t, int, const LaunchPolicy&);                              \
   template hipError_t launch_cut_solve<T>(int, int, const KLevel&, const CutGroupDev&, const T*, const T*, T*,    \
-                                          hipStream_t, int, T*, const CopyJob&);                                   \
+                                          hipStream_t, int, T*, const CopyJob&, const LaunchPolicy&);              \
   template hipError_t launch_copy_nodes<T>(const int32_t*, int64_t, const T*, T*, int64_t, hipStream_t, int);      \
   template hipError_t launch_cut_update<T>(const CutGroupDev&, const T*, T*, int64_t, hipStream_t, int);          \
   template hipError_t launch_prolong_add<T>(int, int, const KLevel&, const KLevel&, const T*, T*, hipStream_t,     \

@@ -5,10 +5,12 @@
 // its own HIP stream (default priority).  A free slot takes the oldest request
 // and up to kMaxCols - 1 further queued requests with the same geometry,
 // parameters, tolerance and iteration limit (a batch), looks for a resident
-// hierarchy of that geometry, otherwise sets one up on the host (one set-up at
-// a time; it is OpenMP-parallel itself) and admits it to the device once its
-// exact footprint fits into the HBM budget, evicting least-recently used idle
-// hierarchies.  The batch is solved by one multi-column PCG on the slot's
+// hierarchy of that geometry, otherwise reserves its exact device footprint
+// (cmg_footprint: counts only, before any quadrature or factorisation) in the
+// HBM budget, evicting least-recently used idle hierarchies or waiting for
+// running batches, then sets it up on the host (one set-up at a time; it is
+// OpenMP-parallel itself) and uploads it.  A request larger than the whole
+// budget is refused with CMG_ENOMEM before its set-up.  The batch is solved by one multi-column PCG on the slot's
 // stream: every V-cycle launch carries all requests of the batch, requests
 // that arrive while others run join the next batch, and batches of different
 // slots overlap on the device.  The column arithmetic of the multi-column
@@ -46,15 +48,29 @@ struct OwnedRequest {
   double rtol = 1e-8;
   int maxit = 200;
   double t_submit = 0;
+  // the hierarchy's identity, field by field (no struct padding bytes)
   std::string key() const {
     std::string k;
     auto put = [&k](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
-    put(&dim, sizeof dim);
+    auto put_i = [&put](int v) { put(&v, sizeof v); };
+    auto put_d = [&put](double v) { put(&v, sizeof v); };
+    put_i(dim);
+    put_i(static_cast<int>(centers.size()));
     put(centers.data(), centers.size() * sizeof(double));
     put(semi.data(), semi.size() * sizeof(double));
-    put(&box_lo, sizeof box_lo);
-    put(&box_hi, sizeof box_hi);
-    put(&params, sizeof params);
+    put_d(box_lo);
+    put_d(box_hi);
+    const cmg_params& q = params;
+    put_i(q.k);
+    put_i(q.n_levels);
+    put_i(q.coarse_cells);
+    put_d(q.gamma_D);
+    put_d(q.gamma_g);
+    put_i(q.ghost_exp_mode);
+    put_i(q.n_c);
+    put_i(q.quad_n);
+    put_i(q.precond_fp32);
+    for (double g : q.gamma_m) put_d(g);
     return k;
   }
   // requests that can share one multi-column solve
@@ -77,7 +93,18 @@ struct Entry {
   size_t bytes = 0;
   bool in_use = false;
   uint64_t last_use = 0;
+  double* db = nullptr;  // right-hand sides and solutions of one batch (kBatch columns), kept with the hierarchy
+  double* dx = nullptr;
+  int64_t n = 0;         // finest-level DoFs
 };
+
+void free_entry(Entry& e) {
+  cmg_destroy(e.p);  // synchronises the device before freeing
+  if (e.db) (void)hipFree(e.db);
+  if (e.dx) (void)hipFree(e.dx);
+  e.p = nullptr;
+  e.db = e.dx = nullptr;
+}
 
 }  // namespace
 
@@ -151,15 +178,13 @@ cmg_status acquire(cmg_server* S, const OwnedRequest& rq, Entry** out, cmg_resul
   } guard{S, key};
   cmg_levelset ls{rq.dim, static_cast<int>(rq.centers.size()) / rq.dim, rq.centers.data(), rq.semi.data(),
                   rq.box_lo, rq.box_hi};
-  cmg_problem* p = nullptr;
-  cmg_status st;
-  {
-    std::lock_guard<std::mutex> lk(S->setup_mu);
-    st = cmg_setup_host(&ls, &rq.params, &p);
-  }
-  if (st != CMG_OK) return st;
+  // admission by footprint before the set-up: counts only, no quadrature or
+  // factorisation, so a request that cannot fit costs nothing
   size_t bytes = 0;
-  cmg_device_bytes(p, rq.params.precond_fp32 | 2, &bytes);  // with the multi-column buffers
+  int64_t n = 0;
+  cmg_status st = cmg_footprint(&ls, &rq.params, rq.params.precond_fp32 | 2, &bytes, &n);
+  if (st != CMG_OK) return st;
+  bytes += 2 * kBatch * static_cast<size_t>(n) * sizeof(double);  // the batch's b and x columns
   {
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
@@ -170,37 +195,46 @@ cmg_status acquire(cmg_server* S, const OwnedRequest& rq, Entry** out, cmg_resul
         if (!it->in_use && (victim == S->cache.end() || it->last_use < victim->last_use)) victim = it;
       if (victim != S->cache.end()) {
         S->used -= victim->bytes;
-        cmg_problem* vp = victim->p;
+        Entry dead = *victim;
         S->cache.erase(victim);
         lk.unlock();
-        cmg_destroy(vp);
+        free_entry(dead);
         lk.lock();
         continue;
       }
-      if (S->cache.empty() && S->used == 0) {  // larger than the whole budget
-        cmg_destroy(p);
-        return CMG_ENOMEM;
-      }
+      if (S->cache.empty() && S->used == 0) return CMG_ENOMEM;  // larger than the whole budget
       S->cv.wait(lk);  // wait for running solves to release memory
     }
-    S->used += bytes;
-    S->cache.push_back(Entry{key, p, bytes, true, ++S->use_clock});
-    *out = &S->cache.back();
+    S->used += bytes;  // reserved for the set-up below
   }
-  st = cmg_upload(p);
-  res.t_admitted = S->now();
-  if (st != CMG_OK) {
+  auto unreserve = [S, bytes]() {
     std::lock_guard<std::mutex> lk(S->mu);
     S->used -= bytes;
-    for (auto it = S->cache.begin(); it != S->cache.end(); ++it)
-      if (&*it == *out) {
-        S->cache.erase(it);
-        break;
-      }
-    cmg_destroy(p);
     S->cv.notify_all();
+  };
+  cmg_problem* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->setup_mu);
+    st = cmg_setup_host(&ls, &rq.params, &p);
+  }
+  if (st != CMG_OK) {
+    unreserve();
     return st;
   }
+  Entry e{key, p, bytes, true, 0, nullptr, nullptr, n};
+  st = cmg_upload(p);
+  const size_t vb = kBatch * static_cast<size_t>(n) * sizeof(double);
+  if (st == CMG_OK && (hipMalloc(&e.db, vb) != hipSuccess || hipMalloc(&e.dx, vb) != hipSuccess)) st = CMG_ENOMEM;
+  res.t_admitted = S->now();
+  if (st != CMG_OK) {
+    free_entry(e);
+    unreserve();
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  e.last_use = ++S->use_clock;
+  S->cache.push_back(e);
+  *out = &S->cache.back();
   return CMG_OK;
 }
 
@@ -262,9 +296,8 @@ void worker(cmg_server* S) {
                                                q.phase.data(), bc);
       }
       const size_t bytes = static_cast<size_t>(n) * nb * sizeof(double);
-      double *db = nullptr, *dx = nullptr;
-      if (st == CMG_OK && (hipMalloc(&db, bytes) != hipSuccess || hipMalloc(&dx, bytes) != hipSuccess))
-        st = CMG_ENOMEM;
+      double* db = e->db;
+      double* dx = e->dx;
       if (st == CMG_OK && hipMemcpyAsync(db, B.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         st = CMG_EHIP;
       const double t_solve = S->now();
@@ -276,8 +309,6 @@ void worker(cmg_server* S) {
             hipStreamSynchronize(stream) != hipSuccess)
           st = CMG_EHIP;
       }
-      if (db) (void)hipFree(db);
-      if (dx) (void)hipFree(dx);
       release(S, e);
     }
     for (int c = 0; c < nb; ++c) {
@@ -361,7 +392,7 @@ void cmg_server_destroy(cmg_server* S) {
     S->cv.notify_all();
   }
   for (std::thread& t : S->workers) t.join();
-  for (Entry& e : S->cache) cmg_destroy(e.p);
+  for (Entry& e : S->cache) free_entry(e);
   delete S;
 }
 

@@ -477,7 +477,7 @@ void ghost_face_matrix(const Config& cfg, const Basis1D& B, double h, int dir, s
 
 void cut_step_sets(HostLevel& L, int d, int k);
 
-std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
+std::string build_hierarchy(const Config& cfg, Hierarchy& H, bool numeric) {
   if (cfg.dim < 2 || cfg.dim > 3 || cfg.k < 1 || cfg.k > kMaxDeg || cfg.n_levels < 1 || cfg.coarse_cells < 1)
     return "EINVAL: unsupported dimension, degree or level count";
   if (cfg.shapes.empty()) return "EINVAL: no shapes";
@@ -505,10 +505,11 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
       for (int64_t c = 0; c < L.n_cells; ++c)
         if (L.cell_flags[c] & kCut) { L.cut_id[c] = static_cast<int32_t>(cuts.size()); cuts.push_back(c); }
       L.n_cut = static_cast<int>(cuts.size());
-      L.cut_mats.assign(static_cast<size_t>(L.n_cut) * nl * nl, 0.0);
+      L.cut_mats.assign(numeric ? static_cast<size_t>(L.n_cut) * nl * nl : 0, 0.0);
       std::string qerr;
+      if (!numeric) cuts.clear();  // counts only: no cut-cell quadrature
 #pragma omp parallel for schedule(dynamic, 4)
-      for (int i = 0; i < L.n_cut; ++i) {
+      for (int i = 0; i < static_cast<int>(cuts.size()); ++i) {
         int ci[kMaxDim];
         geo.cell_of(cuts[i], ci);
         double lo[kMaxDim];
@@ -585,6 +586,7 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
       if (l == 0) {
         const int n0 = static_cast<int>(L.n_dofs);
         H.n_coarse = n0;
+        if (!numeric) continue;
         H.coarse_inv.assign(static_cast<size_t>(n0) * n0, 0.0);
         auto pos = [&](int64_t node) { return L.node_dof[node]; };
         for (int64_t c = 0; c < L.n_cells; ++c) {
@@ -673,9 +675,9 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H) {
           const int64_t nj = rec.nodes.size();
           g.inv_off.push_back(g.inv_off.back() + nj * nj);
         }
-        g.inv.assign(g.inv_off.back(), 0.0);
         std::string perr;
-        const int np = static_cast<int>(g.vertex.size());
+        const int np = numeric ? static_cast<int>(g.vertex.size()) : 0;
+        g.inv.assign(numeric ? g.inv_off.back() : 0, 0.0);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int p = 0; p < np; ++p) {
           const int nj = g.off[p + 1] - g.off[p];

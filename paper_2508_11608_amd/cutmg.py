@@ -60,7 +60,8 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_transfer", "cmg_coarse_solve", "cmg_vcycle", "cmg_solve", "cmg_rhs_manufactured", "cmg_rhs_fourier",
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
-            "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve"]
+            "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve", "cmg_footprint",
+            "cmg_set_launch"]
 
 _lib = None
 
@@ -101,6 +102,9 @@ def load_library():
         "cmg_submit": [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)],
         "cmg_poll": [P, ctypes.c_uint64, ctypes.POINTER(Result), V, ctypes.c_int64],
         "cmg_timing_read": [P, I, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+        "cmg_footprint": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), I, ctypes.POINTER(ctypes.c_size_t),
+                          ctypes.POINTER(ctypes.c_int64)],
+        "cmg_set_launch": [P, I, I],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -166,6 +170,15 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def set_launch(self, small_cut_launch: int = 1536, max_blocks: int = 2048):
+        """Launch shapes by launch size (cmg_set_launch); results are bitwise the same for any choice."""
+        _check(_lib.cmg_set_launch(self._h, int(small_cut_launch), int(max_blocks)))
+
+    def device_bytes(self, fp32: bool = False, multi: bool = False) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.cmg_device_bytes(self._h, int(bool(fp32)) | (2 if multi else 0), ctypes.byref(n)))
+        return n.value
 
     def set_precision(self, fp32: bool):
         """Run the multigrid kernels in FP32 (True) or FP64 (False); CG stays FP64."""
@@ -338,6 +351,19 @@ class Problem:
         keys = ["n_dofs", "active_cells", "cut_cells", "interior_patches", "cut_patches", "sum_nj2",
                 "ghost_faces", "nodes_per_dir"]
         return dict(zip(keys, (int(t) for t in v)))
+
+
+def footprint(workload, fp32: bool = False, multi: bool = False, quad_n: int = 14):
+    """(device bytes, finest-level DoFs) of the problem cmg_setup would build,
+    from counts only (cmg_footprint); host only."""
+    lib = load_library()
+    ls, prm, keep = _levelset_params(workload, quad_n, fp32)
+    n = ctypes.c_size_t()
+    nd = ctypes.c_int64()
+    _check(lib.cmg_footprint(ctypes.byref(ls), ctypes.byref(prm), int(bool(fp32)) | (2 if multi else 0),
+                             ctypes.byref(n), ctypes.byref(nd)))
+    del keep
+    return n.value, nd.value
 
 
 def _levelset_params(workload, quad_n=14, fp32=False):

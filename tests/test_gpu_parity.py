@@ -125,7 +125,11 @@ def test_pcg_solve(case):
     xr, it, _ = pcg(mats[-1], OP.rhs(w, levels[-1]), H.vcycle, rtol=1e-8, maxit=300)
     assert abs(info["iterations"] - it) <= 1
     assert info["rel_residual"] <= 1e-8
-    assert _rel(x.cpu().numpy(), xr) < 1e-8
+    # the same iterates up to rounding when the counts agree; one more or less
+    # iteration moves the iterate by up to the tolerance
+    err = _rel(x.cpu().numpy(), xr)
+    print(f"  PCG: {info['iterations']} its (oracle {it}), solution rel diff {err:.2e}")
+    assert err < (1e-10 if info["iterations"] == it else 1e-8)
 
 
 # ---- mixed precision: FP32 multigrid inside FP64 CG --------------------------

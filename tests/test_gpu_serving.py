@@ -29,14 +29,14 @@ def _mix():
 
 
 def _run(server, reqs):
-    from paper_2508_11608_amd import Problem
+    from paper_2508_11608_amd import footprint
 
     tickets = [server.submit(w, fourier=f, fp32=fp32) for w, f, fp32 in reqs]
     sizes = {}
     results = []
     for (w, f, fp32), t in zip(reqs, tickets):
         if w.name not in sizes:
-            sizes[w.name] = Problem(w, device=False).ndofs()
+            sizes[w.name] = footprint(w)[1]
         while True:
             r = server.poll(t, sizes[w.name])
             if r is not None:
@@ -58,11 +58,16 @@ def test_results_alone_equal_results_in_the_mix():
     in_mix = _run(mix, reqs)
     mix.close()
     print("  batch sizes in the mix:", [r["batch"] for r, _ in in_mix], flush=True)
+    for i, ((w, f, fp32), (res, x)) in enumerate(zip(reqs, in_mix)):
+        print(f"  mix request {i} {w.name} fp32={fp32}: status {res['status']}, {res['iterations']} its, "
+              f"rel residual {res['rel_residual']:.2e}, batch {res['batch']}, solution {'yes' if x is not None else 'no'}",
+              flush=True)
     assert max(r["batch"] for r, _ in in_mix) > 1
-    for (w, f, fp32), (res, x) in zip(reqs, in_mix):
+    for i, ((w, f, fp32), (res, x)) in enumerate(zip(reqs, in_mix)):
         alone_srv = Server(8 << 30, 1)
         (res1, x1), = _run(alone_srv, [(w, f, fp32)])
         alone_srv.close()
+        print(f"  alone request {i} {w.name}: status {res1['status']}, {res1['iterations']} its", flush=True)
         assert res1["batch"] == 1
         assert res["status"] == 0 and res1["status"] == 0, (w.name, fp32, res["status"], res1["status"])
         assert res["rel_residual"] <= 1e-8
@@ -94,19 +99,38 @@ def test_server_result_matches_direct_solve():
 def test_admission_under_a_small_budget():
     """A budget that holds one hierarchy at a time still finishes every request
     (eviction of idle hierarchies, waiting for memory)."""
-    from paper_2508_11608_amd import Problem, Server
-    from paper_2508_11608_amd import cutmg
-    import ctypes
+    from paper_2508_11608_amd import Server, footprint
 
     ws = [W.offcentre_disc(2, 4), W.ellipse(2, 4), W.offcentre_disc(3, 3)]
     need = 0
     for w in ws:
-        P = Problem(w, device=False)
-        b = ctypes.c_size_t()
-        cutmg._lib.cmg_device_bytes(P._h, 3, ctypes.byref(b))  # FP32 copies + multi-column buffers
-        need = max(need, b.value)
+        fb, n = footprint(w, fp32=True, multi=True)  # FP32 copies + multi-column buffers
+        need = max(need, fb + 2 * 8 * 8 * n)          # + the batch's b and x columns
     srv = Server(int(need * 1.5), 2)
     reqs = [(w, W.fourier_modes(2, 50 + i), True) for i, w in enumerate(ws * 2)]
     res = _run(srv, reqs)
     srv.close()
     assert all(r["status"] == 0 and r["rel_residual"] <= 1e-8 for r, _ in res)
+
+
+def test_request_larger_than_the_budget_is_refused_before_set_up():
+    """Admission by footprint happens before the set-up: a request that cannot
+    fit into the whole budget finishes with CMG_ENOMEM at once, and a request
+    that fits still runs on the same server."""
+    from paper_2508_11608_amd import Server, footprint
+
+    big = W.ball_q2().with_levels(5)  # 64^3 cells: about 1 GB with the multi-column buffers
+    small = W.offcentre_disc(2, 3)
+    fb, _ = footprint(big, fp32=True, multi=True)
+    fs, n = footprint(small, fp32=True, multi=True)
+    budget = fs + 2 * 8 * 8 * n + (1 << 20)
+    assert budget < fb
+    print(f"\n[case] budget {budget} B, large request {fb} B", flush=True)
+    srv = Server(budget, 1)
+    t0 = time.perf_counter()
+    (rb, xb), (rs, xs) = _run(srv, [(big, W.fourier_modes(3, 5), True), (small, W.fourier_modes(2, 6), True)])
+    dt = time.perf_counter() - t0
+    srv.close()
+    print(f"  large: status {rb['status']}; small: status {rs['status']}, {rs['iterations']} its; {dt:.2f} s", flush=True)
+    assert rb["status"] == -2 and xb is None
+    assert rs["status"] == 0 and rs["rel_residual"] <= 1e-8

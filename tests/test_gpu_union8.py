@@ -1,0 +1,146 @@
+"""The union of 8 seeded spheres with Q3 (the 8-sphere workload's geometry and
+degree; 2 levels, 8^3 cells on the finest, so that the oracle finishes) through
+the C ABI against the CPU oracle: operator, colour steps, smoothers, V-cycle
+and PCG in FP64; the FP32 V-cycle; the 8-column FP32 V-cycle whose cut-patch
+solves run on the matrix cores; and the THREADS-wide cut-patch blocks of the
+finest 64^3 level, forced here.
+
+Every test prints its name first so that a failing GPU run can be located."""
+import numpy as np
+import pytest
+
+import oracle_cache
+import workloads as W
+
+try:  # import at collection time: the first import on a fresh machine is slow
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+WL = W.sphere_union_8(3, 2)
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    from paper_2508_11608_amd import Problem
+
+    print(f"\n[case] {WL.name} dim=3 k=3 levels={WL.n_levels}: oracle build (about 1.5 min) ...", flush=True)
+    levels, mats, prols, H = oracle_cache.build(WL)
+    print(f"[case] {WL.name}: oracle ready, DoFs per level {[l.n_dofs for l in levels]}", flush=True)
+    P = Problem(WL)
+    yield P, levels, mats, H
+    P.close()
+    torch.cuda.synchronize()
+
+
+def _cuda(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_apply(case):
+    P, levels, mats, _ = case
+    for l in range(len(levels)):
+        x = W.random_vector(levels[l].n_dofs, seed=400 + l)
+        assert _rel(P.apply(l, _cuda(x)).cpu().numpy(), mats[l] @ x) < 1e-12, l
+
+
+def test_colour_steps(case):
+    P, levels, _, H = case
+    l = len(levels) - 1
+    n = levels[l].n_dofs
+    b = W.random_vector(n, seed=410)
+    x0 = W.random_vector(n, seed=411)
+    for key in H.schedule(l)[:16]:
+        xr = x0.copy()
+        H.colour_step(l, key, xr, b)
+        xg = _cuda(x0)
+        P.colour_step(l, key[0], key[1], xg, _cuda(b))
+        assert _rel(xg.cpu().numpy(), xr) < 1e-11, key
+
+
+def test_smoothers_and_vcycle(case):
+    P, levels, _, H = case
+    l = len(levels) - 1
+    n = levels[l].n_dofs
+    b = W.random_vector(n, seed=420)
+    for post in (False, True):
+        x0 = W.random_vector(n, seed=421 + post)
+        xr = x0.copy()
+        H.smooth(l, xr, b, post=post)
+        xg = _cuda(x0)
+        P.smooth(l, post, xg, _cuda(b))
+        assert _rel(xg.cpu().numpy(), xr) < 1e-11, post
+    r = W.random_vector(n, seed=423)
+    assert _rel(P.vcycle(_cuda(r)).cpu().numpy(), H.vcycle(r)) < 1e-10
+
+
+def test_threads_wide_cut_blocks_bitwise(case):
+    """The finest 64^3 level of the workload has thousands of cut patches per
+    colour and runs one 128-thread block per patch; force that here."""
+    P, levels, _, _ = case
+    r = _cuda(W.random_vector(levels[-1].n_dofs, seed=430))
+    z0 = P.vcycle(r).clone()
+    P.set_launch(0, 2048)
+    try:
+        z1 = P.vcycle(r)
+    finally:
+        P.set_launch()
+    assert torch.equal(z0, z1)
+
+
+def test_pcg(case):
+    from oracle import problem as OP
+    from oracle.multigrid import pcg
+
+    P, levels, mats, H = case
+    b = P.rhs_manufactured()
+    x, info = P.solve(_cuda(b), rtol=1e-8, maxit=300)
+    xr, it, _ = pcg(mats[-1], OP.rhs(WL, levels[-1]), H.vcycle, rtol=1e-8, maxit=300)
+    err = _rel(x.cpu().numpy(), xr)
+    print(f"  PCG: {info['iterations']} its (oracle {it}), solution rel diff {err:.2e}")
+    assert abs(info["iterations"] - it) <= 1
+    assert info["rel_residual"] <= 1e-8
+    assert err < (1e-10 if info["iterations"] == it else 1e-8)
+
+
+def test_fp32_vcycle_single_and_8_columns(case):
+    """FP32 V-cycle, one column and 8 columns (cut-patch solves on the matrix
+    cores), each column against the float32 oracle with the FP32 tolerance of
+    the other parity tests (10x the oracle's own float32-vs-float64 deviation
+    + 1e-6)."""
+    P, levels, mats, H = case
+    H32 = oracle_cache.hierarchy32(WL)
+    n = levels[-1].n_dofs
+    rs = np.stack([W.random_vector(n, seed=440 + c) for c in range(8)])
+    P.set_precision(True)
+    try:
+        z1 = P.vcycle(_cuda(rs[0])).cpu().numpy()
+        z8 = P.vcycle_multi(_cuda(rs)).cpu().numpy()
+    finally:
+        P.set_precision(False)
+    for c in range(8):
+        z64 = H.vcycle(rs[c])
+        z32 = H32.vcycle(rs[c]).astype(np.float64)
+        tol = 10.0 * _rel(z32, z64) + 1e-6
+        print(f"  column {c}: 8-column vs oracle32 {_rel(z8[c], z32):.2e} (tol {tol:.2e})")
+        assert _rel(z8[c], z32) < tol, c
+        if c == 0:
+            assert _rel(z1, z32) < tol
+
+
+def test_fp64_8_columns_equal_single(case):
+    P, levels, _, _ = case
+    n = levels[-1].n_dofs
+    rs = _cuda(np.stack([W.random_vector(n, seed=450 + c) for c in range(8)]))
+    z = P.vcycle_multi(rs)
+    for c in range(8):
+        assert torch.equal(z[c], P.vcycle(rs[c].contiguous())), c
