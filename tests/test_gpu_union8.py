@@ -46,6 +46,19 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def _vcycle_inverse_coarse(H, r):
+    """The oracle's V-cycle with its coarse solve done as a product with the
+    explicit inverse of A_0 instead of Cholesky triangular solves.  A_0 of
+    this union has condition number ~6e8, so two correct FP64 coarse solves
+    differ by ~1e-9 relative; the spread of the two oracle V-cycles bounds what
+    the library (an explicit Cholesky-based inverse) can match."""
+    cho, H.coarse_cho = H.coarse_cho, None
+    try:
+        return H.vcycle(r)
+    finally:
+        H.coarse_cho = cho
+
+
 def test_apply(case):
     P, levels, mats, _ = case
     for l in range(len(levels)):
@@ -80,7 +93,11 @@ def test_smoothers_and_vcycle(case):
         P.smooth(l, post, xg, _cuda(b))
         assert _rel(xg.cpu().numpy(), xr) < 1e-11, post
     r = W.random_vector(n, seed=423)
-    assert _rel(P.vcycle(_cuda(r)).cpu().numpy(), H.vcycle(r)) < 1e-10
+    z = P.vcycle(_cuda(r)).cpu().numpy()
+    zr = H.vcycle(r)
+    tol = max(1e-10, 4.0 * _rel(_vcycle_inverse_coarse(H, r), zr))
+    print(f"  V-cycle rel diff {_rel(z, zr):.2e} (tol {tol:.2e})")
+    assert _rel(z, zr) < tol
 
 
 def test_threads_wide_cut_blocks_bitwise(case):
@@ -104,12 +121,15 @@ def test_pcg(case):
     P, levels, mats, H = case
     b = P.rhs_manufactured()
     x, info = P.solve(_cuda(b), rtol=1e-8, maxit=300)
-    xr, it, _ = pcg(mats[-1], OP.rhs(WL, levels[-1]), H.vcycle, rtol=1e-8, maxit=300)
+    bo = OP.rhs(WL, levels[-1])
+    xr, it, _ = pcg(mats[-1], bo, H.vcycle, rtol=1e-8, maxit=300)
+    xi, it_i, _ = pcg(mats[-1], bo, lambda v: _vcycle_inverse_coarse(H, v), rtol=1e-8, maxit=300)
     err = _rel(x.cpu().numpy(), xr)
-    print(f"  PCG: {info['iterations']} its (oracle {it}), solution rel diff {err:.2e}")
+    tol = max(1e-10, 4.0 * _rel(xi, xr)) if info["iterations"] == it == it_i else 1e-8
+    print(f"  PCG: {info['iterations']} its (oracle {it}), solution rel diff {err:.2e} (tol {tol:.2e})")
     assert abs(info["iterations"] - it) <= 1
     assert info["rel_residual"] <= 1e-8
-    assert err < (1e-10 if info["iterations"] == it else 1e-8)
+    assert err < tol
 
 
 def test_fp32_vcycle_single_and_8_columns(case):

@@ -161,6 +161,43 @@ def test_l2_convergence_rate(k):
     assert math.log2(errs[0] / errs[1]) >= k + 0.8
 
 
+def _discrete_l2_errors(w, Ls):
+    """L2 errors of the discrete solutions of the manufactured problem on the
+    finest levels Ls, each solved by Jacobi-scaled CG to 1e-12 (the solution
+    of A x = b, independent of the multigrid under test elsewhere)."""
+    import scipy.sparse as sp
+
+    from oracle.assemble import assemble
+    from oracle.geometry import build_levels
+
+    u, _, _ = problem.manufactured(w.dim)
+    shapes, fp = problem.shapes_of(w), problem.form_params(w)
+    errs = []
+    for L in Ls:
+        lev = build_levels(shapes, w.dim, w.k, L, w.coarse_cells, w.lo, w.hi)[-1]
+        A = assemble(lev, shapes, fp)
+        b = problem.rhs(w, lev)
+        d = 1.0 / np.sqrt(A.diagonal())
+        D = sp.diags(d)
+        y, info = spl.cg(D @ A @ D, d * b, rtol=1e-12, maxiter=20000)
+        assert info == 0
+        errs.append(l2_error(lev, shapes, fp, d * y, u))
+    return errs
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_l2_convergence_rate_ball(k):
+    """O(h^(k+1)) in 3-D: the ball |x| < 0.7 at 16^3 and 32^3 cells."""
+    errs = _discrete_l2_errors(W.ball_q2().with_degree(k), (3, 4))
+    assert math.log2(errs[0] / errs[1]) >= k + 0.8, errs
+
+
+def test_l2_convergence_rate_disc_q3():
+    """O(h^4) for Q3 on the disc at 32^2 and 64^2 cells."""
+    errs = _discrete_l2_errors(W.disc_q2().with_degree(3), (4, 5))
+    assert math.log2(errs[0] / errs[1]) >= 3 + 0.8, errs
+
+
 # ---- outer solvers of the paper's tables: GMRES and the V-cycle iteration ----
 
 def test_gmres_matches_an_independent_implementation():

@@ -165,3 +165,29 @@ def test_nested_shapes_reduce_to_the_outer_one():
     V, S, _ = _integrate_union(sh, 2, 8)
     assert abs(V / (math.pi * 0.49) - 1) < 1e-13
     assert abs(S / (2 * math.pi * 0.7) - 1) < 1e-13
+
+
+def test_union_leaf_rule_converges_to_the_closed_forms():
+    """The leaf rule on kinked cells is fixed at bisection depth 4 in the
+    set-up; deeper bisection must converge to the exact union (lens formula for
+    the area, arcs for the perimeter), which pins the rule itself and not only
+    its agreement with a second implementation of it."""
+    c1, c2, r1, r2 = np.array([-0.21, 0.05]), np.array([0.27, -0.11]), 0.45, 0.38
+    A, P = _two_circles(r1, r2, float(np.linalg.norm(c1 - c2)))
+    shapes = [sphere(c1, r1), sphere(c2, r2)]
+    N, lo, hi = 8, -1.0, 1.0
+    h = (hi - lo) / N
+    act, cut = classify_cells(shapes, 2, N, lo, hi)
+    errs = {}
+    for depth in (4, 8, 10):
+        V = np.count_nonzero(act & ~cut) * h * h
+        S = 0.0
+        for c in np.argwhere(cut):
+            a = lo + c * h
+            vx, vw, sx, sw, sn = cut_cell_rule_union(shapes, a, a + h, n=14, n_t=4, union_depth=depth)
+            V += vw.sum()
+            S += sw.sum()
+        errs[depth] = (abs(V / A - 1), abs(S / P - 1))
+    assert errs[4][0] < 1e-6 and errs[4][1] < 1e-3
+    assert errs[8][0] < 1e-9 and errs[10][0] < 1e-10
+    assert errs[10][1] < 2e-5 and errs[10][1] < errs[4][1] / 20
