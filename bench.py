@@ -316,6 +316,28 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool 
     return out
 
 
+def vcycle_bytes(P, w, s: int = 8, m: int = 1) -> int:
+    """Algorithmic bytes of one whole V-cycle (one pre- and one post-smoothing
+    step per level, n_c sweeps over the cut colours):
+        sum_{l >= 1} [2 (S_int + n_c S_cut) + R + T] + s (n_0^2 + 2 n_0)
+    with S_int / S_cut the interior / cut colour steps of a sweep (per patch as
+    in algorithmic_bytes, copy blocks of the two-buffer steps included), R the
+    level residual b - A x, T the transfers s (3 n_l + 2 n_{l-1}) (prolongation
+    reads e and x and writes x, restriction reads r and writes the coarse b),
+    and the coarse solve a GEMV with the dense inverse.  With m columns the
+    matrix terms count once."""
+    inter = algorithmic_bytes(P, w, "interior_step", s, m)
+    cut = algorithmic_bytes(P, w, "cut_solve", s, m, two_buffer=(s == 8 or m == 1))
+    app = algorithmic_bytes(P, w, "apply", s, m)
+    total = 2 * sum(inter.values()) + 2 * w.n_c * sum(cut.values())
+    total += sum(v for key, v in app.items() if key != "cg")
+    n = [P.counts(l)["n_dofs"] for l in range(w.n_levels)]
+    for l in range(1, w.n_levels):
+        total += s * m * (3 * n[l] + 2 * n[l - 1])
+    total += s * n[0] * n[0] + 2 * s * m * n[0]
+    return int(total)
+
+
 def roofline(P, w, kind: str, launches: int, total_ms: float, vcycles: int, fp32: bool = False,
              ncol: int = 1, two_buffer: bool = True, level: int = None) -> dict:
     """Live roofline of one kernel kind: algorithmic bytes per launch over the
@@ -418,7 +440,11 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
     e1.record()
     torch.cuda.synchronize()
     t_v = e0.elapsed_time(e1) / 1e3 / nv
+    bv = vcycle_bytes(P, w, 4 if fp32 else 8, nrhs)
+    vroof = {"bound": "hbm", "algorithmic_bytes": bv, "vcycle_ms": t_v * 1e3, "achieved": bv / t_v / 1e9,
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS}
     return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * nrhs * vcyc / dt,
+            "x": X.clone(), "vcycle_roofline": vroof,
             "ms_per_step": dt / args.steps * 1e3, "iterations_per_column": [i["iterations"] for i in infos],
             "final_rel_residual": max(i["rel_residual"] for i in infos),
             "solve_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
@@ -469,7 +495,11 @@ def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
     e1.record()
     torch.cuda.synchronize()
     t_v = e0.elapsed_time(e1) / 1e3 / nv
+    bv = vcycle_bytes(P, w, 4 if fp32 else 8)
+    vroof = {"bound": "hbm", "algorithmic_bytes": bv, "vcycle_ms": t_v * 1e3, "achieved": bv / t_v / 1e9,
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS}
     return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * its / dt,
+            "x": x.clone(), "vcycle_roofline": vroof,
             "ms_per_step": dt / args.steps * 1e3, "iterations_per_solve": its / args.steps,
             "final_rel_residual": rel,
             "solve_latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
@@ -521,6 +551,26 @@ def main():
         res = {fp32: timed_multi_solves(P, w, B, args, fp32) for fp32 in first}
     else:
         res = {fp32: timed_solves(P, w, b, x, args, fp32) for fp32 in first}
+    # error of every result against the FP64 reference: the FP64 multigrid in
+    # FP64 CG driven to 1e-12 on the same right-hand sides (the FP64 GPU path,
+    # which the parity tests tie to the CPU oracle; the oracle itself does not
+    # run at this size)
+    P.set_precision(False)
+    if args.nrhs > 1:
+        xref = torch.empty_like(B)
+        _, iref = P.solve_multi(B, xref, rtol=1e-12, maxit=400, raise_on_fail=False)
+        ref_note = f"FP64 multigrid + FP64 CG to 1e-12 ({max(i['iterations'] for i in iref)} iterations)"
+    else:
+        xref = torch.empty_like(b)
+        _, iref = P.solve(b, xref, rtol=1e-12, maxit=400, raise_on_fail=False)
+        ref_note = f"FP64 multigrid + FP64 CG to 1e-12 ({iref['iterations']} iterations)"
+    xs = {fp32: res[fp32].pop("x") for fp32 in first}
+    for fp32 in first:
+        res[fp32]["error_vs_fp64_reference"] = float(torch.linalg.norm(xs[fp32] - xref) / torch.linalg.norm(xref))
+        res[fp32]["fp64_reference"] = ref_note
+    # the FP32-preconditioned solution against the FP64-preconditioned one at the same tolerance
+    res[True]["diff_vs_fp64_solve_same_rtol"] = float(torch.linalg.norm(xs[True] - xs[False])
+                                                      / torch.linalg.norm(xs[False]))
     head = res[first[0]]
     other = res[first[1]]
     out = {
@@ -550,6 +600,9 @@ def main():
         "solve_latency_ms_p99": head["solve_latency_ms_p99"],
         "vcycle_ms": head["vcycle_ms"],
         "vcycle_dofs_per_s": head["vcycle_dofs_per_s"],
+        "vcycle_roofline": head["vcycle_roofline"],
+        "error_vs_fp64_reference": head["error_vs_fp64_reference"],
+        "fp64_reference": head["fp64_reference"],
         "setup_s": t_setup,
         ("fp64" if args.fp32 else "fp32_precond"): other,
     }

@@ -137,6 +137,23 @@ cmg_status cmg_set_precision(cmg_problem* p, int fp32);
  * use it to run the configurations of large levels on small ones.  Host only. */
 cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks);
 
+/* Ghost-penalty coupling in the residuals of the cut colour steps (paper
+ * Section 2.3, last paragraph: the parallel smoother ignores the coupling
+ * through ghost penalties between neighbouring vertex patches).
+ * mode 0 (default): every patch of a colour solves with the exact residual
+ *   (b - A x)[I_j], ghost faces on the patch boundary included; only the
+ *   ghost coupling between same-coloured patches, which update at once, is
+ *   ignored.  The V-cycle is symmetric (CG applies).
+ * mode 1: patch-local residual: x beyond the patch closure (the cell layer
+ *   across a ghost face on the patch boundary) counts as zero, i.e. row i of
+ *   the residual is b_i - sum_{j in closure} A_ij x_j.  A patch then reads
+ *   nothing that a same-coloured patch writes, but a smoothing step no longer
+ *   keeps the exact solution fixed and the V-cycle is not symmetric: for
+ *   cmg_gmres, cmg_vcycle_solve, cmg_vcycle and the single-level calls only;
+ *   cmg_solve and the multi-column calls return CMG_EINVAL while it is set.
+ * Host only; takes effect for the following launches. */
+cmg_status cmg_set_ghost_coupling(cmg_problem* p, int mode);
+
 /* Number of DoFs on a level (0 = coarsest, n_levels-1 = finest). */
 cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);
 

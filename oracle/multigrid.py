@@ -54,6 +54,7 @@ class PatchSet:
     dofs: list = field(default_factory=list)      # list of int arrays (internal DoFs)
     invs: list = field(default_factory=list)      # list of dense local inverses
     rows: np.ndarray = None                        # union of all dofs (sorted)
+    closures: list = field(default_factory=list)  # list of int arrays (DoFs of the closed patch box)
 
 
 def patch_vertices(level: Level) -> list:
@@ -85,6 +86,19 @@ def patch_internal_dofs(level: Level, V: tuple) -> np.ndarray:
     for node in itertools.product(*reversed(ranges)):
         node = tuple(reversed(node))
         dof = level.dof_of_node[node]
+        if dof >= 0:
+            out.append(dof)
+    return np.array(out, dtype=np.int64)
+
+
+def patch_closure_dofs(level: Level, V: tuple) -> np.ndarray:
+    """Active DoFs in the closed box [X - h, X + h]^d (the nodes of the patch's cells)."""
+    k = level.k
+    nn = level.n_nodes_1d
+    ranges = [range(max(k * v - k, 0), min(k * v + k, nn - 1) + 1) for v in V]
+    out = []
+    for node in itertools.product(*reversed(ranges)):
+        dof = level.dof_of_node[tuple(reversed(node))]
         if dof >= 0:
             out.append(dof)
     return np.array(out, dtype=np.int64)
@@ -146,6 +160,7 @@ def build_patches(level: Level, A: sp.csr_matrix, require_spd: bool = True) -> d
         ps.vertices.append(V)
         ps.dofs.append(dofs)
         ps.invs.append(inv)
+        ps.closures.append(patch_closure_dofs(level, V))
     for ps in groups.values():
         ps.rows = np.unique(np.concatenate(ps.dofs))
     return groups
@@ -154,8 +169,15 @@ def build_patches(level: Level, A: sp.csr_matrix, require_spd: bool = True) -> d
 class Hierarchy:
     """Matrices, transfers, patches and coarse solver of all levels."""
 
-    def __init__(self, levels, mats, prols, n_c=2, dtype=np.float64, require_spd=True):
+    def __init__(self, levels, mats, prols, n_c=2, dtype=np.float64, require_spd=True, ghost_local=False):
         self.levels = levels
+        # False: exact residual b - A x on the patch interior (ghost halos
+        # included), the variant that keeps the V-cycle symmetric.  True: each
+        # cut patch's residual uses x only on its own closure, i.e. the
+        # ghost-face terms that reach beyond the closed patch box are dropped
+        # (the coupling through ghost penalties between neighbouring patches is
+        # ignored in the residual as well); the V-cycle is then not symmetric.
+        self.ghost_local = ghost_local
         self.A = [m.astype(dtype) for m in mats]
         self.P = [None] + [p.astype(dtype) for p in prols]
         self.n_c = n_c
@@ -187,10 +209,16 @@ class Hierarchy:
         ps = self.patches[l].get(key)
         if ps is None:
             return
+        dx = np.zeros_like(x)
+        if self.ghost_local and not ps.interior:
+            for dofs, clo, inv in zip(ps.dofs, ps.closures, ps.invs):
+                r_j = b[dofs] - self.A[l][dofs][:, clo] @ x[clo]
+                dx[dofs] += inv @ r_j
+            x += dx
+            return
         r_rows = b[ps.rows] - self._row_slices[(l, key)] @ x
         r = np.zeros_like(x)
         r[ps.rows] = r_rows
-        dx = np.zeros_like(x)
         for dofs, inv in zip(ps.dofs, ps.invs):
             dx[dofs] += inv @ r[dofs]
         x += dx

@@ -113,6 +113,7 @@ struct cmg_problem {
   int nblk = 0;
   int device = 0;
   cmg::LaunchPolicy launch;  // block size / grid cap choices by launch size
+  int ghost_local = 0;       // cut-patch residuals: 0 exact, 1 patch-local (see cmg_set_ghost_coupling)
   // kernel timing: launches of the kinds in timing_mask are bracketed by events
   unsigned timing_mask = 0;
   int timing_level = -1;  // -1: every level
@@ -1056,6 +1057,17 @@ cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks) 
   return CMG_OK;
 }
 
+cmg_status cmg_set_ghost_coupling(cmg_problem* p, int mode) {
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (mode != 0 && mode != 1) return fail(CMG_EINVAL, "ghost coupling mode must be 0 or 1");
+  p->ghost_local = mode;
+  for (DevLevel& d : p->lv) {
+    d.kl64.ghost_local = mode;
+    d.kl32.ghost_local = mode;
+  }
+  return CMG_OK;
+}
+
 cmg_status cmg_set_precision(cmg_problem* p, int fp32) {
   TRY(check_device(p));
   if (fp32 != 0 && fp32 != 1) return fail(CMG_EINVAL, "precision flag must be 0 or 1");
@@ -1120,6 +1132,9 @@ cmg_status cmg_solve(cmg_problem* p, const double* b, double* x, double rtol, in
                      void* stream) {
   TRY(check_device(p));
   if (!b || !x || !(rtol > 0.0) || maxit < 1) return fail(CMG_EINVAL, "bad solve arguments");
+  if (p->ghost_local)
+    return fail(CMG_EINVAL, "CG needs the symmetric V-cycle: the patch-local ghost coupling is for GMRES and "
+                            "the V-cycle iteration");
   auto s = static_cast<hipStream_t>(stream);
   const int L = p->H.cfg.n_levels - 1;
   const int64_t n = p->H.levels[L].n_dofs;
@@ -1336,6 +1351,7 @@ cmg_status cmg_vcycle_solve(cmg_problem* p, const double* b, double* x, double r
 cmg_status cmg_vcycle_multi(cmg_problem* p, int nrhs, const double* r, double* z, void* stream) {
   TRY(check_device(p));
   if (!r || !z || nrhs < 1 || nrhs > cmg::kMaxCols) return fail(CMG_EINVAL, "bad multi-column V-cycle arguments");
+  if (p->ghost_local) return fail(CMG_EINVAL, "multi-column calls run with the exact ghost coupling only");
   TRY(prepare_multi(p));
   return vcycle_multi_current(p, nrhs, r, z, static_cast<hipStream_t>(stream));
 }
@@ -1345,6 +1361,7 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
   TRY(check_device(p));
   if (!b || !x || !(rtol > 0.0) || maxit < 1 || nrhs < 1 || nrhs > cmg::kMaxCols)
     return fail(CMG_EINVAL, "bad multi-column solve arguments");
+  if (p->ghost_local) return fail(CMG_EINVAL, "multi-column calls run with the exact ghost coupling only");
   TRY(prepare_multi(p));
   auto s = static_cast<hipStream_t>(stream);
   const int L = p->H.cfg.n_levels - 1;

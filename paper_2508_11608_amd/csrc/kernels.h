@@ -31,6 +31,8 @@ struct KLevel {
   const int32_t* spec_cells; // background cell of every special cell
   const int32_t* spec_info;  // per special cell 1 + 2d entries: cut id (-1: uncut), ghost face ids (-1: none)
   const int32_t* cell_sid;   // per cell: special id, -1 active and regular, -2 inactive
+  int ghost_local;           // cut colour steps: 1 = x beyond the patch closure is taken as zero (the ghost
+                             // faces on the patch boundary contribute only their closure part), 0 = exact
   template <typename T>
   __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
 };

@@ -66,6 +66,21 @@ struct Shape {
   static constexpr int T_SIZE = T_P1D + NC1 * N1;
 };
 
+// Work index of block b out of n such that the blocks of one XCD take one
+// contiguous range of work items.  The chip dispatches workgroups to its 8
+// XCDs round-robin by block index and every XCD has its own L2, so without
+// the remap consecutive (spatially neighbouring) cut patches land on
+// different XCDs and each XCD fetches the x-lines they share separately
+// (measured: finest cut steps 2.5% faster in FP64 and FP32).  The grid-stride
+// operator and interior-patch kernels keep the plain order, which measured
+// faster for them (the remap cost them 8% and 20%).
+// Bijective on [0, n): XCD x < n % 8 takes n / 8 + 1 items, the others n / 8.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  constexpr int NX = 8;
+  const int q = n / NX, r = n % NX, xc = b % NX, s = b / NX;
+  return xc < r ? xc * (q + 1) + s : r * (q + 1) + (xc - r) * q + s;
+}
+
 __device__ __forceinline__ int64_t lat(int D, int nn, const int* I) {
   return D == 2 ? I[0] + (int64_t)nn * I[1] : I[0] + (int64_t)nn * (I[1] + (int64_t)nn * I[2]);
 }
@@ -729,7 +744,7 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
       int r = h % NH;
       const int layer = r % K;
       r /= K;
-      ld = (need >> slab) & 1;
+      ld = ((need >> slab) & 1) && !L.ghost_local;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         if (a == dir) {
@@ -942,11 +957,16 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
       sa *= nn;
     }
     const int64_t base = lat(D, L.nn, I);
+    // patch-local residual: the lower cell of a plane-0 face and the upper
+    // cell of a plane-2 face lie outside the patch; their nodes beyond the
+    // closure (normal layers other than the shared face) get weight zero (the
+    // loads stay unconditional)
+    const bool lo_out = L.ghost_local && plane == 0, hi_out = L.ghost_local && plane == 2;
     T dl[N1], du[N1];
 #pragma unroll
     for (int bd = 0; bd <= K; ++bd) {
-      dl[bd] = (T)d1[m * N1 + bd];
-      du[bd] = (T)d0[m * N1 + bd];
+      dl[bd] = (lo_out && bd < K) ? (T)0 : (T)d1[m * N1 + bd];
+      du[bd] = (hi_out && bd > 0) ? (T)0 : (T)d0[m * N1 + bd];
     }
     T J[NT];
 #pragma unroll
@@ -1148,7 +1168,7 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
       if (nd[u] >= 0) xb[nd[u]] = v[u];
     return;
   }
-  const int gp = blockIdx.x - cj.nblk;
+  const int gp = xcd_block(blockIdx.x - cj.nblk, gridDim.x - cj.nblk);
   int V[3] = {0, 0, 0}, pi[3] = {0, 0, 0};
   const int node = cut_patch_setup<D, K, T>(L, G, gp, sm, V);
   const int off = G.off[gp];
@@ -1453,7 +1473,7 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
   __shared__ PairSmem<D, K, float, kMaxCols> sm;
   __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int gp = blockIdx.x;
+  const int gp = xcd_block(blockIdx.x, gridDim.x);
   for (int e = tid; e < NPK * kMaxCols; e += nth) (&rs[0][0])[e] = 0.f;
   int off, nj;
   cut_residual_cols<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);

@@ -61,7 +61,7 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
             "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve", "cmg_footprint",
-            "cmg_set_launch"]
+            "cmg_set_launch", "cmg_set_ghost_coupling"]
 
 _lib = None
 
@@ -105,6 +105,7 @@ def load_library():
         "cmg_footprint": [ctypes.POINTER(LevelSet), ctypes.POINTER(Params), I, ctypes.POINTER(ctypes.c_size_t),
                           ctypes.POINTER(ctypes.c_int64)],
         "cmg_set_launch": [P, I, I],
+        "cmg_set_ghost_coupling": [P, I],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -174,6 +175,11 @@ class Problem:
     def set_launch(self, small_cut_launch: int = 1536, max_blocks: int = 2048):
         """Launch shapes by launch size (cmg_set_launch); results are bitwise the same for any choice."""
         _check(_lib.cmg_set_launch(self._h, int(small_cut_launch), int(max_blocks)))
+
+    def set_ghost_coupling(self, patch_local: bool):
+        """Cut-patch residuals with the exact ghost coupling (False) or patch-local,
+        with x beyond the patch closure taken as zero (True; cmg_set_ghost_coupling)."""
+        _check(_lib.cmg_set_ghost_coupling(self._h, int(bool(patch_local))))
 
     def device_bytes(self, fp32: bool = False, multi: bool = False) -> int:
         n = ctypes.c_size_t()

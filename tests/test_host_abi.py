@@ -72,6 +72,9 @@ def test_device_calls_on_a_host_problem_are_einval():
     assert lib.cmg_set_launch(P._h, -1, 16) == CMG_EINVAL
     assert lib.cmg_set_launch(P._h, 0, 0) == CMG_EINVAL
     assert lib.cmg_set_launch(P._h, 0, 1) == 0
+    assert lib.cmg_set_ghost_coupling(P._h, 2) == CMG_EINVAL
+    assert lib.cmg_set_ghost_coupling(P._h, 1) == 0
+    assert lib.cmg_set_ghost_coupling(P._h, 0) == 0
     P.close()
 
 

@@ -261,3 +261,75 @@ def test_vcycle_iteration_closed_form():
     x3, it, _ = vcycle_iteration(mats[-1], b, H.vcycle, rtol=0.0, maxit=3)
     assert it == 3
     assert np.abs(x3 - xk).max() <= 1e-12 * np.abs(xk).max()
+
+
+# ---- patch-local residuals (ghost coupling beyond the patch closure dropped) ----
+
+def _ghost_local(H):
+    import copy
+
+    Hl = copy.copy(H)  # shares matrices and patches
+    Hl.ghost_local = True
+    return Hl
+
+
+def test_patch_local_residual_is_the_residual_of_x_masked_to_the_closure(disc3):
+    """Brute force by coordinates: for every cut patch of a colour, the residual
+    of the variant is (b - A x~)[I_j] with x~ = x on the DoFs whose coordinates
+    lie in the closed box [X - h, X + h]^d and zero elsewhere."""
+    _, levels, mats, _, H = disc3
+    Hl = _ghost_local(H)
+    l = len(levels) - 1
+    lev = levels[l]
+    X = lev.dof_coords()
+    A = mats[l].toarray()
+    n = lev.n_dofs
+    rng = np.random.default_rng(5)
+    x0, b = rng.standard_normal(n), rng.standard_normal(n)
+    for key, ps in H.patches[l].items():
+        if key[0]:
+            continue
+        want = x0.copy()
+        for V, dofs, inv in zip(ps.vertices, ps.dofs, ps.invs):
+            centre = lev.lo + np.asarray(V, dtype=np.float64) * lev.h
+            inside = np.all(np.abs(X - centre) <= lev.h * (1 + 1e-12), axis=1)
+            xt = np.where(inside, x0, 0.0)
+            want[dofs] += inv @ (b - A @ xt)[dofs]
+        got = x0.copy()
+        Hl.colour_step(l, key, got, b)
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), key
+
+
+def test_patch_local_residual_without_ghost_penalty_is_exact():
+    """With gamma_g = 0 there is no coupling beyond a patch closure: both
+    variants give the same smoother."""
+    w, levels, mats, _, H = _hier(W.offcentre_disc(2, 3), gamma_g=0.0)
+    Hl = _ghost_local(H)
+    l = len(levels) - 1
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(levels[l].n_dofs)
+    x1, x2 = np.zeros_like(b), np.zeros_like(b)
+    H.smooth(l, x1, b)
+    Hl.smooth(l, x2, b)
+    assert np.abs(x1 - x2).max() <= 1e-13 * np.abs(x1).max()
+
+
+def test_patch_local_smoother_is_inconsistent(disc3):
+    """The exact residual keeps the discrete solution fixed; the patch-local one
+    moves it (the measured inconsistency), and its V-cycle is not symmetric."""
+    w, levels, mats, _, H = disc3
+    Hl = _ghost_local(H)
+    l = len(levels) - 1
+    b = problem.rhs(w, levels[l])
+    xs = spl.spsolve(mats[l].tocsc(), b)
+    x1, x2 = xs.copy(), xs.copy()
+    H.smooth(l, x1, b)
+    Hl.smooth(l, x2, b)
+    assert np.linalg.norm(x1 - xs) <= 1e-11 * np.linalg.norm(xs)
+    assert np.linalg.norm(x2 - xs) >= 1e-6 * np.linalg.norm(xs)
+    n = levels[l].n_dofs
+    B = np.column_stack([Hl.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - B.T).max() > 1e-6 * np.abs(B).max()
+    # as a preconditioner it still works: GMRES converges to the discrete solution
+    x, it, _ = gmres(mats[l], b, Hl.vcycle, rtol=1e-10)
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs) and it <= 30
