@@ -160,6 +160,22 @@ cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);
 /* y = A_l x on one level (paper eq. (cutfem-ghost) in matrix form). */
 cmg_status cmg_apply(cmg_problem* p, int level, const double* x, double* y, void* stream);
 
+/* y = A_l x like cmg_apply, for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no hipMalloc, hipFree or other allocating call, and no kernel
+ * timers.  Its intermediates (the level's lattice vectors of x and A x, the
+ * ghost-face jumps and the special-cell products) live in one file-scope
+ * device array of 32 MiB per device (CMG_NOALLOC_SCRATCH_BYTES), held until
+ * the process ends; its device address is taken once per device when a
+ * problem is set up or uploaded there.  A level whose intermediates exceed it
+ * returns CMG_EINVAL (nothing launched); so does a call from another device
+ * than the problem's.  Every call on a GPU uses that GPU's one array: calls
+ * that overlap in time on one GPU (other streams, other problems, other
+ * threads) race and must be serialised by the caller.  Results equal
+ * cmg_apply's bit for bit (same kernels). */
+#define CMG_NOALLOC_SCRATCH_BYTES (32u << 20)
+cmg_status cmg_apply_noalloc(cmg_problem* p, int level, const double* x, double* y, void* stream);
+
 /* One colour step of the smoother on level >= 1 (paper eq. (local-solver)):
  * for all patches j of the given class (interior != 0: interior patches with
  * fast diagonalisation; 0: cut patches with dense inverses) and colour

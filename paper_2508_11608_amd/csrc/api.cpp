@@ -767,6 +767,42 @@ cmg_status op_apply(cmg_problem* p, int level, const double* x, double* y, hipSt
   return gather<T>(p, level, v.r, y, s);
 }
 
+// The operator product with every intermediate in the per-device scratch
+// array instead of the problem's work vectors: lattice x | lattice y | ghost
+// face jumps W | special-cell products C, each at a 256-byte boundary.  The
+// lattice x is cleared first (its inactive nodes must read zero; the array
+// keeps what the previous call left); y, W and C are written in full before
+// they are read.  No device or host allocation on the success path (no
+// kernel timers either).
+template <typename T>
+cmg_status op_apply_noalloc(cmg_problem* p, int level, const double* x, double* y, hipStream_t s) {
+  DevLevel& D = p->lv[level];
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t nn = static_cast<size_t>(D.kl64.n_nodes);
+  const size_t bx = up(nn * sizeof(T)), bw = up(D.n_w * sizeof(T)), bc = up(D.n_c * sizeof(T));
+  const size_t need = 2 * bx + bw + bc;
+  if (need > cmg::kNoallocScratchBytes)
+    return fail(CMG_EINVAL, "level " + std::to_string(level) + " needs " + std::to_string(need) +
+                                " bytes of scratch; cmg_apply_noalloc holds at most " +
+                                std::to_string(cmg::kNoallocScratchBytes));
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != p->device) return fail(CMG_EINVAL, "cmg_apply_noalloc: the problem lives on another device");
+  unsigned char* base = static_cast<unsigned char*>(cmg::noalloc_scratch(cur));
+  if (!base) return fail(CMG_EINVAL, "cmg_apply_noalloc: no scratch address for this device (set-up missing)");
+  T* xl = reinterpret_cast<T*>(base);
+  T* yl = reinterpret_cast<T*>(base + bx);
+  T* W = reinterpret_cast<T*>(base + 2 * bx);
+  T* C = reinterpret_cast<T*>(base + 2 * bx + bw);
+  const int64_t nd = D.kl64.n_dofs, ld = D.kl64.n_nodes;
+  HIP_TRY(cmg::launch_fill(static_cast<int64_t>(bx / sizeof(double)), 0.0, reinterpret_cast<double*>(xl), s));
+  HIP_TRY(cmg::launch_scatter<double, T>(D.kl64.dof_node, nd, x, xl, ld, s));
+  HIP_TRY(cmg::launch_apply<T>(p->H.cfg.dim, p->H.cfg.k, kl<T>(D), xl, static_cast<const T*>(nullptr), yl, W, C, s,
+                               1, p->launch));
+  HIP_TRY(cmg::launch_gather<T, double>(D.kl64.dof_node, nd, yl, y, ld, s));
+  return CMG_OK;
+}
+
 template <typename T>
 cmg_status op_colour_step(cmg_problem* p, int level, bool interior, int colour, double* x, const double* b,
                           hipStream_t s) {
@@ -985,6 +1021,8 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
     return fail(CMG_EHIP, "no HIP device");
   }
   cmg_status st = upload_all(P);
+  if (st == CMG_OK && cmg::noalloc_scratch_init(P->device) != hipSuccess)
+    st = fail(CMG_EHIP, "device address of the allocation-free scratch");
   if (st == CMG_OK && prm->precond_fp32) {
     st = ensure_fp32(P);
     P->fp32 = true;
@@ -1023,6 +1061,8 @@ cmg_status cmg_upload(cmg_problem* p) {
   if (!p->lv.empty()) return CMG_OK;
   if (hipGetDevice(&p->device) != hipSuccess) return fail(CMG_EHIP, "no HIP device");
   cmg_status st = upload_all(p);
+  if (st == CMG_OK && cmg::noalloc_scratch_init(p->device) != hipSuccess)
+    st = fail(CMG_EHIP, "device address of the allocation-free scratch");
   if (st == CMG_OK && p->fp32) st = ensure_fp32(p);
   return st;
 }
@@ -1055,6 +1095,13 @@ cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks) 
   p->launch.small_cut_launch = small_cut_launch;
   p->launch.max_blocks = static_cast<unsigned>(max_blocks);
   return CMG_OK;
+}
+
+cmg_status cmg_apply_noalloc(cmg_problem* p, int level, const double* x, double* y, void* stream) {
+  TRY(check_level(p, level, false));
+  if (!x || !y) return fail(CMG_EINVAL, "null vector");
+  auto s = static_cast<hipStream_t>(stream);
+  return p->fp32 ? op_apply_noalloc<float>(p, level, x, y, s) : op_apply_noalloc<double>(p, level, x, y, s);
 }
 
 cmg_status cmg_set_ghost_coupling(cmg_problem* p, int mode) {

@@ -164,6 +164,13 @@ hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStrea
 }  // namespace cmg
 
 namespace cmg {
+// Scratch of cmg_apply_noalloc: one file-scope device array per device, held
+// for the life of the process.  noalloc_scratch_init, called with the device
+// current (at set-up), takes its device address with hipGetSymbolAddress once
+// per device; noalloc_scratch returns that address (nullptr before the init).
+constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s);                    // y = v
 hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t s);             // y = x
 }  // namespace cmg

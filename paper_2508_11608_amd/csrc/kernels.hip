@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -2081,6 +2082,38 @@ __global__ __launch_bounds__(256) void k_copy(int64_t n, const double* __restric
 }
 
 }  // namespace dev
+
+// The array behind cmg_apply_noalloc.  In host code its name is a host-side
+// stand-in, not a device address: the address is taken per device with
+// hipGetSymbolAddress and only that address is passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the address is per device: take it with that device current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s) {
   if (n == 0) return hipSuccess;

@@ -61,7 +61,7 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
             "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve", "cmg_footprint",
-            "cmg_set_launch", "cmg_set_ghost_coupling"]
+            "cmg_set_launch", "cmg_set_ghost_coupling", "cmg_apply_noalloc"]
 
 _lib = None
 
@@ -82,6 +82,7 @@ def load_library():
         "cmg_ndofs": [P, I, ctypes.POINTER(ctypes.c_int64)],
         "cmg_set_precision": [P, I],
         "cmg_apply": [P, I, V, V, V],
+        "cmg_apply_noalloc": [P, I, V, V, V],
         "cmg_colour_step": [P, I, I, I, V, V, V],
         "cmg_smooth": [P, I, I, V, V, V],
         "cmg_transfer": [P, I, I, V, V, V],
@@ -208,6 +209,14 @@ class Problem:
         y = self._empty(level) if y is None else y
         n = self.ndofs(level)
         _check(_lib.cmg_apply(self._h, level, _dev(x, n), _dev(y, n), _stream()))
+        return y
+
+    def apply_noalloc(self, level, x, y):
+        """y = A_l x with the library's fixed scratch array (cmg_apply_noalloc);
+        y must be given (this call allocates nothing)."""
+        level = self._lvl(level)
+        n = self.ndofs(level)
+        _check(_lib.cmg_apply_noalloc(self._h, level, _dev(x, n), _dev(y, n), _stream()))
         return y
 
     def colour_step(self, level, interior: bool, colour: int, x, b):
