@@ -68,6 +68,8 @@ def parse():
                     help="iteration counts of GMRES and of the stand-alone V-cycle on the paper's circle protocol "
                          "for the comma-separated finest levels L (k = 1..3, n_c = 1..4), beside the paper's numbers")
     ap.add_argument("--rate", type=float, default=0.8, help="arrival rate as a fraction of the saturation rate")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every V-cycle kernel by kernel instead of replaying captured HIP graphs")
     return ap.parse_args()
 
 
@@ -279,7 +281,7 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool 
         flags = N.reshape((Nc,) * d)  # index order (z, y, x) / (y, x)
         cut = (flags & 2) != 0
         copy = {}
-        if kind == "cut_solve" and two_buffer:  # (the matrix-core step has no copy blocks)
+        if kind == "cut_solve" and two_buffer:  # (the multi-column steps have no copy blocks)
             nodes = {c: P.export(l, 32 + c, np.int32) for c in range(2 ** d)}
             present = [c for c in range(2 ** d) if len(nodes[c])]
             for i, c in enumerate(present):
@@ -327,7 +329,7 @@ def vcycle_bytes(P, w, s: int = 8, m: int = 1) -> int:
     and the coarse solve a GEMV with the dense inverse.  With m columns the
     matrix terms count once."""
     inter = algorithmic_bytes(P, w, "interior_step", s, m)
-    cut = algorithmic_bytes(P, w, "cut_solve", s, m, two_buffer=(s == 8 or m == 1))
+    cut = algorithmic_bytes(P, w, "cut_solve", s, m, two_buffer=(m == 1))
     app = algorithmic_bytes(P, w, "apply", s, m)
     total = 2 * sum(inter.values()) + 2 * w.n_c * sum(cut.values())
     total += sum(v for key, v in app.items() if key != "cg")
@@ -423,7 +425,7 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
     dt = time.perf_counter() - t0
     launches, kms = P.timing_read(args.kernel, fine)
     P.timing([])
-    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs, two_buffer=not fp32, level=fine)
+    roof = roofline(P, w, args.kernel, launches, kms, vcyc, fp32, ncol=nrhs, two_buffer=False, level=fine)
     tag = "fp32" if fp32 else "fp64"
     print(f"[bench] {tag} x{nrhs}: timed {args.steps} solves: {dt:.3f}s, {vcyc} multi V-cycles", file=sys.stderr,
           flush=True)
@@ -538,6 +540,8 @@ def main():
     t0 = time.perf_counter()
     P = Problem(w)
     t_setup = time.perf_counter() - t0
+    if args.no_graphs:
+        P.set_graphs(False)
     n = P.ndofs()
     print(f"[bench] {w.name}: {n} DoFs, setup {t_setup:.1f}s", file=sys.stderr, flush=True)
     b = torch.from_numpy(P.rhs_manufactured()).cuda()
@@ -591,7 +595,7 @@ def main():
                                + (f"{args.nrhs} seeded Fourier right-hand sides per solve (independent PCG per "
                                   f"column, shared multi-column V-cycles)" if args.nrhs > 1 else "manufactured f")
                                + ", FP64 CG to 1e-8",
-                   "active_dofs": n, "n_c": w.n_c, "nrhs": args.nrhs,
+                   "active_dofs": n, "n_c": w.n_c, "nrhs": args.nrhs, "vcycle_graphs": not args.no_graphs,
                    "precision": "fp32 preconditioner, fp64 CG" if args.fp32 else "fp64"},
         "roofline": head["roofline"],
         "cg_iterations_per_solve": head.get("iterations_per_solve", head.get("iterations_per_column")),

@@ -116,7 +116,9 @@ cmg_status cmg_upload(cmg_problem* p);
 /* Device memory in bytes that the problem occupies once uploaded.  flags bit 0:
  * include the FP32 copies of the mixed-precision V-cycle; bit 1: include the
  * buffers of the multi-column calls (8 columns of work vectors on every level,
- * the multi-column Krylov vectors and, with bit 0, the tiled FP32 inverses). */
+ * the multi-column Krylov vectors and, with bit 0, the tiled FP32 inverses);
+ * bit 2: include the quadrature plan of cmg_rhs_fourier_device once it has been
+ * built (zero before its first call). */
 cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes);
 
 /* Precision of the multigrid part: fp32 = 0 runs every V-cycle kernel in FP64;
@@ -153,6 +155,18 @@ cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks);
  *   cmg_solve and the multi-column calls return CMG_EINVAL while it is set.
  * Host only; takes effect for the following launches. */
 cmg_status cmg_set_ghost_coupling(cmg_problem* p, int mode);
+
+/* V-cycles (cmg_vcycle, cmg_vcycle_multi and those inside the solvers) run
+ * as replays of HIP graphs: the kernel sequence of a V-cycle is captured once
+ * per precision and column count (on a stream of the problem's own) and each
+ * V-cycle is one graph launch on the caller's stream, so the host does not
+ * issue ~270 kernel launches per V-cycle.  The graphs hold kernel nodes only
+ * (no memset nodes); while kernels are timed (cmg_timing), every timed launch
+ * is a graph of its own, launched between two events recorded on the stream.
+ * Results are bit for bit those of kernel-by-kernel launches.  enable = 0 launches kernel by
+ * kernel (default 1).  cmg_set_launch, cmg_set_ghost_coupling, cmg_timing
+ * and this call drop the captured graphs.  Host only. */
+cmg_status cmg_set_graphs(cmg_problem* p, int enable);
 
 /* Number of DoFs on a level (0 = coarsest, n_levels-1 = finest). */
 cmg_status cmg_ndofs(const cmg_problem* p, int level, int64_t* n);
@@ -285,6 +299,20 @@ cmg_status cmg_rhs_manufactured(const cmg_problem* p, double* b_host);
  * cmg_ndofs(finest) doubles; kappa holds n_modes * dim integers. */
 cmg_status cmg_rhs_fourier(const cmg_problem* p, int n_modes, const int* kappa, const double* amp,
                            const double* phase, double* b_host);
+
+/* The load vector of cmg_rhs_fourier (f = sum_q amp[q] cos(pi kappa_q . x +
+ * phase[q]), g = 0, paper eq. (weak-equation)) assembled on the device into
+ * b (device pointer, cmg_ndofs(finest) doubles, canonical order), stream
+ * ordered.  Same quadrature as the host assembly: tensor Gauss with k+3 points
+ * per direction on uncut cells, the columns of the cut-cell rule with quad_n
+ * points per smooth piece on cut cells.  Cell vectors are summed in a fixed
+ * order, so b is the same bit for bit in every call and on every stream; it
+ * differs from the host assembly by rounding only.  kappa, amp and phase are
+ * host arrays (n_modes <= 32, quad_n <= 16).  The first call on a problem
+ * builds the cut cells' quadrature columns on the host and uploads them
+ * (synchronous, allocates; accounted by cmg_device_bytes flag bit 2). */
+cmg_status cmg_rhs_fourier_device(cmg_problem* p, int n_modes, const int* kappa, const double* amp,
+                                  const double* phase, double* b, void* stream);
 
 /* Host-side description of a level for tests and diagnostics.
  * what = 0: counts, 8 int64 into buf: n_dofs, n_cells_active, n_cut_cells,

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -114,17 +116,47 @@ struct cmg_problem {
   int device = 0;
   cmg::LaunchPolicy launch;  // block size / grid cap choices by launch size
   int ghost_local = 0;       // cut-patch residuals: 0 exact, 1 patch-local (see cmg_set_ghost_coupling)
+  // device quadrature plan of the finest level's load vector (cmg_rhs_fourier_device), on first use
+  bool rhs_ready = false;
+  cmg::RhsPlanDev rhs{};
+  size_t rhs_bytes = 0;
   // kernel timing: launches of the kinds in timing_mask are bracketed by events
   unsigned timing_mask = 0;
   int timing_level = -1;  // -1: every level
   struct Rec {
     int kind, level;
     hipEvent_t a, b;
+    int n;  // launches between the two events
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
   hipEvent_t done_ev = nullptr;  // see wait_stream
+  // V-cycles replayed from captured HIP graphs (see vcycle_graph), keyed by
+  // precision, column count and single/multi-column buffers
+  // While kernels are timed, a V-cycle is captured in pieces: every run of
+  // consecutive timed launches of one kind and level forms a piece of its own,
+  // launched between two eagerly recorded events at replay, and the launches
+  // between such runs form the others.
+  struct Piece {
+    hipGraphExec_t exec = nullptr;
+    int kind = -1, level = -1;  // kind >= 0: timed launches of one kind and level
+    int n = 0;                  // their number
+  };
+  struct VGraph {
+    std::vector<Piece> pieces;
+  };
+  std::map<int, VGraph> vgraphs;
+  bool use_graphs = true;
+  bool graphs_broken = false;        // a capture failed: kernel-by-kernel launches from then on
+  hipStream_t cap_stream = nullptr;  // capture only; the graphs run on the caller's stream
+  hipEvent_t cap_ev = nullptr;       // orders the capture stream with the caller's stream
+  struct Capture {
+    bool on = false, ok = true;
+    int kind = -1, level = -1;       // the piece being captured holds timed launches of this kind and level
+    int n = 0;
+    std::vector<Piece> pieces;
+  } cap;
 };
 
 namespace {
@@ -204,7 +236,22 @@ cmg_status settle() {
   return CMG_OK;
 }
 
+}  // namespace
+
+// Serialises the library's device allocations, null-stream uploads and
+// synchronisations with the capture of V-cycle graphs: a capture in one
+// thread (a solve server's worker) and a null-stream copy or device-wide
+// synchronisation in another must not overlap.  Recursive: the ensure_*
+// helpers call each other.
+std::recursive_mutex& cmg::device_mutex() {
+  static std::recursive_mutex m;
+  return m;
+}
+
+namespace {
+
 cmg_status upload_all(cmg_problem* P) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   const cmg::Config& cfg = P->H.cfg;
   const int L = cfg.n_levels;
   auto& own = P->owned;
@@ -347,6 +394,7 @@ cmg_status upload_all(cmg_problem* P) {
 
 // FP32 copies (rounded from the FP64 set-up) and FP32 work vectors, on first use.
 cmg_status ensure_fp32(cmg_problem* P) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   if (P->fp32_ready) return CMG_OK;
   auto& own = P->owned;
   for (size_t l = 0; l < P->lv.size(); ++l) {
@@ -379,6 +427,7 @@ cmg_status ensure_fp32(cmg_problem* P) {
 // and the multi-column Krylov vectors, on first use.
 template <typename T>
 cmg_status ensure_multi(cmg_problem* P) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   bool& ready = std::is_same<T, float>::value ? P->m32_ready : P->m64_ready;
   if (ready) return CMG_OK;
   if (std::is_same<T, float>::value) TRY(ensure_fp32(P));
@@ -412,6 +461,7 @@ cmg_status ensure_multi(cmg_problem* P) {
 // per patch, row blocks of 16 x column blocks of 4, each tile 64 floats with
 // lane l = row l%16 + 16 * column l/16, zero beyond the patch size.
 cmg_status ensure_tiles(cmg_problem* P) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   if (P->tiles_ready) return CMG_OK;
   TRY(ensure_fp32(P));
   auto& own = P->owned;
@@ -463,25 +513,75 @@ cmg_status check_level(const cmg_problem* p, int level, bool need_fine) {
   return CMG_OK;
 }
 
+// Ends the capture of the current piece of a V-cycle graph and starts the
+// next one (see cmg_problem::Capture); pieces without nodes are dropped.
+void cap_cut(cmg_problem* P, bool restart) {
+  cmg_problem::Capture& c = P->cap;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(P->cap_stream, &g) != hipSuccess || !g) {
+    c.ok = false;
+  } else {
+    size_t n = 0;
+    if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess) c.ok = false;
+    if (c.ok && n > 0) {
+      cmg_problem::Piece pc;
+      pc.kind = c.kind;
+      pc.level = c.level;
+      pc.n = c.n;
+      if (hipGraphInstantiate(&pc.exec, g, nullptr, nullptr, 0) != hipSuccess) c.ok = false;
+      else c.pieces.push_back(pc);
+    }
+    (void)hipGraphDestroy(g);
+  }
+  if (restart && hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) c.ok = false;
+}
+
+// Takes the next two timing events of the pool (which grows when used up).
+bool timing_events(cmg_problem* P, hipEvent_t* a, hipEvent_t* b) {
+  if (P->pool_used + 2 > P->pool.size()) {
+    for (int i = 0; i < 1024; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      P->pool.push_back(e);
+    }
+  }
+  *a = P->pool[P->pool_used++];
+  *b = P->pool[P->pool_used++];
+  return true;
+}
+
 // Brackets one kernel launch with HIP events when its kind is being timed.
+// Every launch of a V-cycle capture passes through one: a timed launch opens
+// a timed piece (or joins the open one of its kind and level), any other
+// launch closes it.
 struct KTimer {
   cmg_problem* P;
   hipStream_t s;
   hipEvent_t b = nullptr;
   KTimer(cmg_problem* P_, int kind, int level, hipStream_t s_) : P(P_), s(s_) {
-    if (!(P->timing_mask & (1u << kind))) return;
-    if (P->timing_level >= 0 && level != P->timing_level) return;
-    if (P->pool_used + 2 > P->pool.size()) {
-      for (int i = 0; i < 1024; ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        P->pool.push_back(e);
+    const bool timed = (P->timing_mask & (1u << kind)) && (P->timing_level < 0 || level == P->timing_level);
+    cmg_problem::Capture& c = P->cap;
+    if (c.on) {
+      if (!c.ok) return;
+      if (timed && c.kind == kind && c.level == level) {
+        ++c.n;
+      } else if (timed) {
+        cap_cut(P, true);
+        c.kind = kind;
+        c.level = level;
+        c.n = 1;
+      } else if (c.kind >= 0) {
+        cap_cut(P, true);
+        c.kind = c.level = -1;
+        c.n = 0;
       }
+      return;
     }
-    hipEvent_t a = P->pool[P->pool_used++];
-    b = P->pool[P->pool_used++];
+    if (!timed) return;
+    hipEvent_t a;
+    if (!timing_events(P, &a, &b)) return;
     (void)hipEventRecord(a, s);
-    P->recs.push_back({kind, level, a, b});
+    P->recs.push_back({kind, level, a, b, 1});
   }
   ~KTimer() {
     if (b) (void)hipEventRecord(b, s);
@@ -535,6 +635,8 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
         HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol, nullptr, cmg::CopyJob(),
                                          P->launch));
       }
+    } else if (multi) {
+      HIP_TRY(cmg::launch_cut_solve_cols(d, k, kl<T>(D), G, v.x, v.b, v.W, v.dbuf, ncol, s));
     } else {
       HIP_TRY(cmg::launch_cut_solve<T>(d, k, kl<T>(D), G, v.x, v.b, v.dbuf, s, ncol, nullptr, cmg::CopyJob(),
                                        P->launch));
@@ -566,11 +668,15 @@ cmg_status cut_steps(cmg_problem* P, int l, bool post, hipStream_t s, int ncol, 
     for (int c = 0; c < C; ++c)
       if (cutg<T>(D, c).n_patch > 0) seq.push_back(c);
   if (post) std::reverse(seq.begin(), seq.end());
-  bool mfma = false;
-  if constexpr (std::is_same<T, float>::value)
-    for (int c = 0; c < C; ++c) mfma = mfma || (multi && cutg<T>(D, c).inv_tiles);
+  // the multi-column kernels (FP32 matrix cores, FP64 all columns per block)
+  // write corrections and take the separate update
+  bool cols = multi;
+  if constexpr (std::is_same<T, float>::value) {
+    cols = false;
+    for (int c = 0; c < C; ++c) cols = cols || (multi && cutg<T>(D, c).inv_tiles);
+  }
   size_t npp = seq.size() - seq.size() % 2;
-  if (mfma || !v.x1 || npp == 0) npp = 0;
+  if (cols || !v.x1 || npp == 0) npp = 0;
   if (npp > 0) {
     KTimer t(P, kCutUpdate, l, s);
     HIP_TRY(cmg::launch_copy_nodes<T>(D.region, D.n_region, v.x, v.x1, D.kl64.n_nodes, s, ncol));
@@ -741,6 +847,7 @@ cmg_status rows_dot(cmg_problem* P, const double* V, const double* w, int64_t n,
 }
 
 cmg_status ensure_gmres(cmg_problem* P, int restart) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   if (P->g_restart >= restart) return CMG_OK;
   auto& own = P->owned;
   const size_t n = static_cast<size_t>(P->H.levels.back().n_dofs);
@@ -845,12 +952,84 @@ cmg_status op_coarse(cmg_problem* p, const double* b, double* x, hipStream_t s) 
   return gather<T>(p, 0, v.x, x, s);
 }
 
+void drop_graphs(cmg_problem* P) {
+  for (auto& kv : P->vgraphs)
+    for (auto& pc : kv.second.pieces) (void)hipGraphExecDestroy(pc.exec);
+  P->vgraphs.clear();
+}
+
+// The lattice V-cycle as one graph launch on s.  The kernel sequence of a
+// V-cycle is fixed for a problem, a precision and a column count, so it is
+// captured once (on the problem's own capture stream: the caller's stream may
+// be the null stream, which cannot be captured) and replayed: one host call
+// instead of ~270 kernel launches, whose host cost otherwise exceeds the GPU
+// time of the short coarse-level kernels.  The graph holds kernel nodes only
+// (every buffer is cleared by kernels; no memset nodes).  While kernels are
+// timed, the timed launches are pieces of their own, bracketed by events
+// recorded on s at every replay.  Launch settings, ghost coupling and timing
+// changes drop the graphs; a failed capture falls back to kernel-by-kernel
+// launches for good.
+template <typename T>
+cmg_status vcycle_graph(cmg_problem* P, hipStream_t s, int ncol, bool multi) {
+  if (!P->use_graphs || P->graphs_broken) return vcycle_lattice<T>(P, s, ncol, multi);
+  const int key = (std::is_same<T, float>::value ? 1000 : 0) + (multi ? 100 : 0) + ncol;
+  auto it = P->vgraphs.find(key);
+  if (it == P->vgraphs.end()) {
+    std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+    if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    if (!P->cap_ev) HIP_TRY(hipEventCreateWithFlags(&P->cap_ev, hipEventDisableTiming));
+    // should a capture break off, the launches after it would run on the
+    // capture stream: order that stream after s now, and s after it below
+    HIP_TRY(hipEventRecord(P->cap_ev, s));
+    HIP_TRY(hipStreamWaitEvent(P->cap_stream, P->cap_ev, 0));
+    cmg_problem::Capture& c = P->cap;
+    c = cmg_problem::Capture{};
+    c.on = true;
+    if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) c.ok = false;
+    const cmg_status st = c.ok ? vcycle_lattice<T>(P, P->cap_stream, ncol, multi) : CMG_OK;
+    if (c.ok) cap_cut(P, false);
+    c.on = false;
+    if (st != CMG_OK || !c.ok) {
+      // nothing of the capture ran: launch this V-cycle (and all later ones)
+      // kernel by kernel
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(P->cap_stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(P->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+      }
+      for (auto& pc : c.pieces) (void)hipGraphExecDestroy(pc.exec);
+      c.pieces.clear();
+      (void)hipGetLastError();
+      g_last_error.clear();
+      P->graphs_broken = true;
+      HIP_TRY(hipEventRecord(P->cap_ev, P->cap_stream));
+      HIP_TRY(hipStreamWaitEvent(s, P->cap_ev, 0));
+      return vcycle_lattice<T>(P, s, ncol, multi);
+    }
+    cmg_problem::VGraph g;
+    g.pieces = std::move(c.pieces);
+    it = P->vgraphs.emplace(key, std::move(g)).first;
+  }
+  for (const cmg_problem::Piece& pc : it->second.pieces) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool timed = pc.kind >= 0 && timing_events(P, &a, &b);
+    if (timed) HIP_TRY(hipEventRecord(a, s));
+    HIP_TRY(hipGraphLaunch(pc.exec, s));
+    if (timed) {
+      HIP_TRY(hipEventRecord(b, s));
+      P->recs.push_back({pc.kind, pc.level, a, b, pc.n});
+    }
+  }
+  return CMG_OK;
+}
+
 template <typename T>
 cmg_status op_vcycle(cmg_problem* p, const double* r, double* z, hipStream_t s) {
   const int L = p->H.cfg.n_levels - 1;
   Vecs<T>& v = vecs<T>(p->lv[L]);
   TRY(scatter<T>(p, L, r, v.b, s));
-  TRY(vcycle_lattice<T>(p, s));
+  TRY(vcycle_graph<T>(p, s, 1, false));
   return gather<T>(p, L, v.x, z, s);
 }
 
@@ -864,7 +1043,7 @@ cmg_status op_vcycle_multi(cmg_problem* p, int ncol, const double* r, double* z,
   const int L = p->H.cfg.n_levels - 1;
   Vecs<T>& v = mvecs<T>(p->lv[L]);
   TRY(scatter<T>(p, L, r, v.b, s, ncol));
-  TRY(vcycle_lattice<T>(p, s, ncol, true));
+  TRY(vcycle_graph<T>(p, s, ncol, true));
   return gather<T>(p, L, v.x, z, s, ncol);
 }
 
@@ -1020,6 +1199,7 @@ static cmg_status setup_impl(const cmg_levelset* ls, const cmg_params* prm, cmg_
     delete P;
     return fail(CMG_EHIP, "no HIP device");
   }
+  std::unique_lock<std::recursive_mutex> lock(cmg::device_mutex());
   cmg_status st = upload_all(P);
   if (st == CMG_OK && cmg::noalloc_scratch_init(P->device) != hipSuccess)
     st = fail(CMG_EHIP, "device address of the allocation-free scratch");
@@ -1046,6 +1226,7 @@ cmg_status cmg_setup_host(const cmg_levelset* ls, const cmg_params* prm, cmg_pro
 
 void cmg_destroy(cmg_problem* p) {
   if (!p) return;
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   if (!p->lv.empty()) (void)hipDeviceSynchronize();
   for (void* v : p->owned) (void)hipFree(v);
   if (p->part_host) (void)hipHostFree(p->part_host);
@@ -1053,6 +1234,9 @@ void cmg_destroy(cmg_problem* p) {
   if (p->gpart_host) (void)hipHostFree(p->gpart_host);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   if (p->done_ev) (void)hipEventDestroy(p->done_ev);
+  drop_graphs(p);
+  if (p->cap_ev) (void)hipEventDestroy(p->cap_ev);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -1060,6 +1244,7 @@ cmg_status cmg_upload(cmg_problem* p) {
   if (!p) return fail(CMG_EINVAL, "null problem");
   if (!p->lv.empty()) return CMG_OK;
   if (hipGetDevice(&p->device) != hipSuccess) return fail(CMG_EHIP, "no HIP device");
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   cmg_status st = upload_all(p);
   if (st == CMG_OK && cmg::noalloc_scratch_init(p->device) != hipSuccess)
     st = fail(CMG_EHIP, "device address of the allocation-free scratch");
@@ -1069,8 +1254,9 @@ cmg_status cmg_upload(cmg_problem* p) {
 
 cmg_status cmg_device_bytes(const cmg_problem* p, int flags, size_t* bytes) {
   if (!p || !bytes) return fail(CMG_EINVAL, "null argument");
-  if (flags < 0 || flags > 3) return fail(CMG_EINVAL, "flags: bit 0 FP32 copies, bit 1 multi-column buffers");
-  *bytes = hierarchy_bytes(p->H, flags);
+  if (flags < 0 || flags > 7)
+    return fail(CMG_EINVAL, "flags: bit 0 FP32 copies, bit 1 multi-column buffers, bit 2 load-vector plan");
+  *bytes = hierarchy_bytes(p->H, flags & 3) + ((flags & 4) && p->rhs_ready ? p->rhs_bytes : 0);
   return CMG_OK;
 }
 
@@ -1094,6 +1280,85 @@ cmg_status cmg_set_launch(cmg_problem* p, int small_cut_launch, int max_blocks) 
   if (small_cut_launch < 0 || max_blocks < 1) return fail(CMG_EINVAL, "bad launch policy");
   p->launch.small_cut_launch = small_cut_launch;
   p->launch.max_blocks = static_cast<unsigned>(max_blocks);
+  drop_graphs(p);
+  return CMG_OK;
+}
+
+// Quadrature plan of the device load vector: built on the host (the cut
+// cells' columns, OpenMP) and uploaded on the first call.  Synchronous.
+static cmg_status ensure_rhs_plan(cmg_problem* P) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+  if (P->rhs_ready) return CMG_OK;
+  const cmg::Config& cfg = P->H.cfg;
+  const cmg::HostLevel& L = P->H.levels.back();
+  cmg::RhsPlan R;
+  cmg::build_rhs_plan(P->H, R);
+  cmg::RhsPlanDev& D = P->rhs;
+  D = cmg::RhsPlanDev{};
+  D.N = L.N;
+  D.nn = L.nn;
+  D.lo = cfg.lo;
+  D.h = L.h;
+  D.n_uncut = static_cast<int64_t>(R.uncut.size());
+  D.n_cut = static_cast<int64_t>(R.cut.size());
+  D.n_col = static_cast<int64_t>(R.cw.size());
+  auto& own = P->owned;
+  int32_t *uncut, *cut, *act;
+  int64_t* off;
+  double *cx, *cw, *ct0, *ct1, *loc;
+  uint8_t* ce;
+  TRY(upload(own, R.uncut, &uncut));
+  TRY(upload(own, R.cut, &cut));
+  TRY(upload(own, R.col_off, &off));
+  TRY(upload(own, R.cx, &cx));
+  TRY(upload(own, R.cw, &cw));
+  TRY(upload(own, R.ct0, &ct0));
+  TRY(upload(own, R.ct1, &ct1));
+  TRY(upload(own, R.ce, &ce));
+  TRY(upload(own, R.act_id, &act));
+  const int nl = static_cast<int>(std::pow(cfg.k + 1, cfg.dim));
+  TRY(alloc_zero(own, static_cast<size_t>(R.n_active) * nl, &loc));
+  TRY(settle());
+  D.uncut = uncut;
+  D.cut = cut;
+  D.col_off = off;
+  D.cx = cx;
+  D.cw = cw;
+  D.ct0 = ct0;
+  D.ct1 = ct1;
+  D.ce = ce;
+  D.act_id = act;
+  D.loc = loc;
+  for (int a = 0; a <= cfg.k; ++a)
+    for (int m = 0; m <= cfg.k; ++m) D.coef[a][m] = P->H.basis.coef[a][m];
+  cmg::gauss_legendre(cfg.k + 3, D.gx, D.gw);
+  D.nq = cfg.quad_n;
+  cmg::gauss_legendre(cfg.quad_n, D.tx, D.tw);
+  P->rhs_bytes = R.uncut.size() * 4 + R.cut.size() * 4 + R.col_off.size() * 8 + R.cx.size() * 8 +
+                 R.cw.size() * 24 + R.ce.size() + R.act_id.size() * 4 + static_cast<size_t>(R.n_active) * nl * 8;
+  P->rhs_ready = true;
+  return CMG_OK;
+}
+
+cmg_status cmg_rhs_fourier_device(cmg_problem* p, int n_modes, const int* kappa, const double* amp,
+                                  const double* phase, double* b, void* stream) {
+  TRY(check_device(p));
+  if (!b || n_modes < 0 || n_modes > cmg::kMaxModes || (n_modes > 0 && (!kappa || !amp || !phase)))
+    return fail(CMG_EINVAL, "bad Fourier right-hand side (at most 32 modes)");
+  if (p->H.cfg.quad_n > 16) return fail(CMG_EINVAL, "the device load vector takes at most 16 points per piece");
+  TRY(ensure_rhs_plan(p));
+  cmg::RhsModes M{};
+  M.n = n_modes;
+  const int d = p->H.cfg.dim;
+  for (int q = 0; q < n_modes; ++q) {
+    for (int j = 0; j < d; ++j) M.kappa[q][j] = kappa[q * d + j];
+    M.amp[q] = amp[q];
+    M.phase[q] = phase[q];
+  }
+  const cmg::HostLevel& L = p->H.levels.back();
+  DevLevel& D = p->lv.back();
+  HIP_TRY(cmg::launch_rhs_fourier(d, p->H.cfg.k, p->rhs, M, D.kl64.dof_node, L.n_dofs, b,
+                                  static_cast<hipStream_t>(stream)));
   return CMG_OK;
 }
 
@@ -1112,6 +1377,15 @@ cmg_status cmg_set_ghost_coupling(cmg_problem* p, int mode) {
     d.kl64.ghost_local = mode;
     d.kl32.ghost_local = mode;
   }
+  drop_graphs(p);
+  return CMG_OK;
+}
+
+cmg_status cmg_set_graphs(cmg_problem* p, int enable) {
+  if (!p) return fail(CMG_EINVAL, "null problem");
+  if (enable != 0 && enable != 1) return fail(CMG_EINVAL, "graph flag must be 0 or 1");
+  p->use_graphs = enable != 0;
+  drop_graphs(p);
   return CMG_OK;
 }
 
@@ -1484,6 +1758,7 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
 
 cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {
   TRY(check_device(p));
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
   HIP_TRY(hipDeviceSynchronize());
   const int lv = static_cast<int>((kind_mask >> 16) & 0xffu) - 1;
   if (lv >= static_cast<int>(p->lv.size())) return fail(CMG_EINVAL, "timing level out of range");
@@ -1491,6 +1766,7 @@ cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {
   p->timing_level = lv;
   p->recs.clear();
   p->pool_used = 0;
+  drop_graphs(p);  // recaptured with (or without) the timed launches as pieces of their own
   // create the events now rather than inside the timed launches
   while (p->timing_mask && p->pool.size() < 8192) {
     hipEvent_t e;
@@ -1510,7 +1786,7 @@ cmg_status cmg_timing_read(cmg_problem* p, int kind, int level, int64_t* launche
     HIP_TRY(hipEventSynchronize(r.b));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
-    *launches += 1;
+    *launches += r.n;
     *total_ms += ms;
   }
   return CMG_OK;

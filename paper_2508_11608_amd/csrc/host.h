@@ -152,6 +152,23 @@ void manufactured_rhs(const Hierarchy& H, std::vector<double>& b);
 void fourier_rhs(const Hierarchy& H, int n_modes, const int* kappa, const double* amp, const double* phase,
                  std::vector<double>& b);
 
+// Quadrature plan of the finest level's load vector for data with g = 0, for
+// assembling it on the device: the active cells (uncut ones take the tensor
+// Gauss rule with k+3 points per direction) and the volume columns of the cut
+// cells' rule (the same columns as load_vector, quad_n points per smooth piece
+// of the base and along every column).
+struct RhsPlan {
+  std::vector<int32_t> act_id;   // per background cell: row of the cell vectors, -1 inactive
+  int64_t n_active = 0;
+  std::vector<int32_t> uncut;    // background cells of the active uncut cells
+  std::vector<int32_t> cut;      // background cells of the cut cells
+  std::vector<int64_t> col_off;  // volume columns of cut cell i: col_off[i] .. col_off[i+1]
+  std::vector<double> cx;        // base points, SoA: dim arrays of n_col (component e unused)
+  std::vector<double> cw, ct0, ct1;  // base weight, inside interval along e
+  std::vector<uint8_t> ce;       // height direction e
+};
+void build_rhs_plan(const Hierarchy& H, RhsPlan& R);
+
 // Uncut-cell stiffness, element matrix of a cut cell, ghost-face matrix.
 void uncut_cell_matrix(const Config& cfg, const Basis1D& B, double h, std::vector<double>& K);
 void cut_cell_matrix(const Config& cfg, const Basis1D& B, double h, const double* lo,

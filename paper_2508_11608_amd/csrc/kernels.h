@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cstdint>
 
 namespace cmg {
@@ -123,6 +125,10 @@ hipError_t launch_copy_nodes(const int32_t* nodes, int64_t n, const T* src, T* d
                              int ncol = 1);
 // FP32, ncol <= kMaxCols columns, local solves on the matrix cores (needs
 // inv_tiles); W is the ghost-face work buffer (ncol columns), rewritten here.
+// FP64 counterpart for several columns: every inverse and cell row read once
+// for all columns (plain FMA); corrections into dbuf like the FP32 kernel.
+hipError_t launch_cut_solve_cols(int d, int k, const KLevel& L, const CutGroupDev& G, const double* x,
+                                 const double* b, double* W, double* dbuf, int ncol, hipStream_t s);
 hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDev& G, const float* x, const float* b,
                                  float* W, float* dbuf, int ncol, hipStream_t s);
 template <typename T>
@@ -164,6 +170,43 @@ hipError_t launch_xpay(int64_t n, double a, const double* x, double* y, hipStrea
 }  // namespace cmg
 
 namespace cmg {
+// Held by every device allocation, null-stream upload or device-wide
+// synchronisation of the library and by the capture of V-cycle graphs, so
+// that the two never overlap across threads (api.cpp).
+std::recursive_mutex& device_mutex();
+
+// Load vector of f = sum_q amp_q cos(pi kappa_q . x + phase_q) with g = 0 on
+// the finest level, assembled on the device from the quadrature plan of the
+// host set-up (cell vectors of every active cell, then one gather per DoF;
+// every sum in a fixed order, so the result is the same in every run).
+constexpr int kMaxModes = 32;
+struct RhsModes {
+  int n;
+  int kappa[kMaxModes][3];
+  double amp[kMaxModes], phase[kMaxModes];
+};
+struct RhsPlanDev {
+  int N, nn;                 // cells / lattice nodes per direction
+  double lo, h;              // box corner and cell size
+  int64_t n_uncut, n_cut, n_col;
+  const int32_t* uncut;      // background cells of the active uncut cells
+  const int32_t* cut;        // background cells of the cut cells
+  const int64_t* col_off;    // volume columns of cut cell i: col_off[i] .. col_off[i+1]
+  const double* cx;          // base points, SoA (dim arrays of n_col)
+  const double* cw;
+  const double* ct0;
+  const double* ct1;
+  const uint8_t* ce;         // height direction of every column
+  const int32_t* act_id;     // per background cell: row of loc, -1 inactive
+  double* loc;               // cell vectors, (k+1)^d per active cell
+  double coef[4][4];         // monomial coefficients of the 1-D GLL basis, psi_a(t) = sum_m coef[a][m] t^m
+  double gx[8], gw[8];       // k+3 Gauss points / weights on [0, 1] (uncut cells)
+  double tx[16], tw[16];     // quad_n points / weights on [0, 1] (along a column)
+  int nq;
+};
+hipError_t launch_rhs_fourier(int d, int k, const RhsPlanDev& R, const RhsModes& M, const int32_t* dof_node,
+                              int64_t n_dofs, double* b, hipStream_t s);
+
 // Scratch of cmg_apply_noalloc: one file-scope device array per device, held
 // for the life of the process.  noalloc_scratch_init, called with the device
 // current (at set-up), takes its device address with hipGetSymbolAddress once

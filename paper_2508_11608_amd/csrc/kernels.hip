@@ -1508,6 +1508,49 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
   }
 }
 
+// Cut patches, phase 1 for up to kMaxCols columns in FP64: residuals of all
+// columns by cut_residual_cols (every cell row read once for all columns),
+// then d = A_j^{-1} r for all columns with the inverse read once: thread i
+// takes row i (= column i, the inverse is symmetric) and multiplies each entry
+// into every column's accumulator.  Column c's arithmetic (residual, then the
+// row sum in increasing j) does not depend on the other columns.
+template <int D, int K>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_cols(KLevel L, CutGroupDev G,
+                                                                             const double* __restrict__ x,
+                                                                             const double* __restrict__ b,
+                                                                             const double* __restrict__ W,
+                                                                             double* __restrict__ dbuf, int ncol) {
+  using S = Shape<D, K>;
+  constexpr int NB = 8;                        // independent inverse loads in flight per thread
+  constexpr int NPB = (S::NP + NB - 1) / NB * NB;
+  __shared__ PairSmem<D, K, double, kMaxCols> sm;
+  __shared__ double rs[NPB][kMaxCols];         // rows >= nj and columns >= ncol stay zero
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int gp = xcd_block(blockIdx.x, gridDim.x);
+  for (int e = tid; e < NPB * kMaxCols; e += nth) (&rs[0][0])[e] = 0.0;
+  int off, nj;
+  cut_residual_cols<D, K, double, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
+  const double* inv = G.inv_t<double>() + G.inv_off[gp];
+  for (int i = tid; i < nj; i += nth) {
+    double acc[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) acc[c] = 0.0;
+    for (int j = 0; j < nj; j += NB) {
+      double v[NB];
+      // loads past the last row re-read it; their residual rows are zero
+#pragma unroll
+      for (int u = 0; u < NB; ++u) v[u] = inv[(int64_t)(j + u < nj ? j + u : nj - 1) * nj + i];
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c) acc[c] += v[u] * rs[j + u][c];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c)
+      if (c < ncol) dbuf[c * G.n_nodes + off + i] = acc[c];
+  }
+}
+
 // dst = src on a node list (the cut region before a run of two-buffer cut steps).
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy_nodes(const int32_t* __restrict__ nodes, int64_t n,
@@ -1849,6 +1892,24 @@ hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDe
   });
 }
 
+hipError_t launch_cut_solve_cols(int d, int k, const KLevel& L, const CutGroupDev& G, const double* x,
+                                 const double* b, double* W, double* dbuf, int ncol, hipStream_t s) {
+  if (G.n_patch == 0) return hipSuccess;
+  if (ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
+  return dispatch(d, k, [&](auto D, auto K) {
+    if (L.n_faces > 0) {  // ghost-face jumps of the current x, all columns
+      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, double>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s,
+                         L, x, W);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+    hipLaunchKernelGGL((dev::k_cut_solve_cols<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, W,
+                       dbuf, ncol);
+    return hipGetLastError();
+  });
+}
+
 template <typename T>
 hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, int64_t ldx, hipStream_t s, int ncol) {
   if (G.n_nodes == 0) return hipSuccess;
@@ -2125,6 +2186,227 @@ hipError_t launch_copy(int64_t n, const double* x, double* y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(dev::k_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y);
   return hipGetLastError();
+}
+
+}  // namespace cmg
+
+// ---- load vector of Fourier data on the device -----------------------------
+namespace cmg {
+namespace dev {
+
+__device__ __forceinline__ double rhs_f(const RhsModes& M, int D, const double* x) {
+  double v = 0.0;
+  for (int q = 0; q < M.n; ++q) {
+    double arg = M.phase[q];
+    for (int j = 0; j < D; ++j) arg += M_PI * M.kappa[q][j] * x[j];
+    v += M.amp[q] * cos(arg);
+  }
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void rhs_basis(const RhsPlanDev& R, double t, double* psi) {
+#pragma unroll
+  for (int a = 0; a <= K; ++a) {
+    double v = R.coef[a][K];
+#pragma unroll
+    for (int m = K - 1; m >= 0; --m) v = v * t + R.coef[a][m];
+    psi[a] = v;
+  }
+}
+
+// Cell vectors of the uncut active cells: tensor Gauss rule with k+3 points
+// per direction, one thread per cell.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_rhs_uncut(RhsPlanDev R, RhsModes M) {
+  constexpr int N1 = K + 1, NL = Pow<N1, D>::v, NG = K + 3;
+  const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= R.n_uncut) return;
+  const int c = R.uncut[u];
+  double lo[3];
+  {
+    int r = c;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      lo[j] = R.lo + (r % R.N) * R.h;
+      r /= R.N;
+    }
+  }
+  double hd = 1.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) hd *= R.h;
+  double acc[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) acc[a] = 0.0;
+  constexpr int NPT = Pow<NG, D>::v;
+  for (int p = 0; p < NPT; ++p) {
+    double x[3], psi[3][N1], w = hd;
+    int r = p;  // the same for every thread: the table loads are scalar
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int m = r % NG;
+      r /= NG;
+      x[j] = lo[j] + R.h * R.gx[m];
+      w *= R.gw[m];
+      rhs_basis<K>(R, R.gx[m], psi[j]);
+    }
+    const double fv = rhs_f(M, D, x) * w;
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      double v = fv;
+      int ra = a;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        v *= psi[j][ra % N1];
+        ra /= N1;
+      }
+      acc[a] += v;
+    }
+  }
+  double* out = R.loc + (int64_t)R.act_id[c] * NL;
+#pragma unroll
+  for (int a = 0; a < NL; ++a) out[a] = acc[a];
+}
+
+// Cell vectors of the cut cells: one block per cut cell, thread t takes the
+// columns t, t + 256, ... of the cell; along a column only direction e varies,
+// so each column sums f w psi_{a_e} per a_e and spreads it with the basis
+// factors of the other directions.  The block's partial vectors are reduced
+// in a fixed order (butterfly within each wavefront, then the four
+// wavefronts in order).
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_rhs_cut(RhsPlanDev R, RhsModes M) {
+  constexpr int N1 = K + 1, NL = Pow<N1, D>::v;
+  const int i = blockIdx.x;
+  const int c = R.cut[i];
+  double lo[3];
+  {
+    int r = c;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      lo[j] = R.lo + (r % R.N) * R.h;
+      r /= R.N;
+    }
+  }
+  double acc[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) acc[a] = 0.0;
+  const int64_t c0 = R.col_off[i], c1 = R.col_off[i + 1];
+  for (int64_t col = c0 + threadIdx.x; col < c1; col += blockDim.x) {
+    const int e = R.ce[col];
+    double x[3], psi[3][N1];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      x[j] = R.cx[j * R.n_col + col];
+      rhs_basis<K>(R, (x[j] - lo[j]) / R.h, psi[j]);
+    }
+    const double w = R.cw[col], t0 = R.ct0[col], t1 = R.ct1[col];
+    double ae[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) ae[a] = 0.0;
+    for (int t = 0; t < R.nq; ++t) {
+      double xt[3];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xt[j] = j == e ? t0 + (t1 - t0) * R.tx[t] : x[j];
+      const double fv = rhs_f(M, D, xt) * w * (t1 - t0) * R.tw[t];
+      double pe[N1];
+      rhs_basis<K>(R, (xt[e] - lo[e]) / R.h, pe);
+#pragma unroll
+      for (int a = 0; a < N1; ++a) ae[a] += fv * pe[a];
+    }
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      double v = 1.0, s = 0.0;
+      int ra = a;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int aj = ra % N1;
+        ra /= N1;
+        if (j == e) s = ae[aj];
+        else v *= psi[j][aj];
+      }
+      acc[a] += v * s;
+    }
+  }
+  __shared__ double wsum[4][NL];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int a = 0; a < NL; ++a) {
+    double v = acc[a];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) wsum[wave][a] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NL) {
+    const int a = threadIdx.x;
+    R.loc[(int64_t)R.act_id[c] * NL + a] = (wsum[0][a] + wsum[1][a]) + (wsum[2][a] + wsum[3][a]);
+  }
+}
+
+// b at every DoF: the cell vectors of the (up to 2^d) active cells that
+// contain its node, in a fixed order.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_rhs_gather(RhsPlanDev R, const int32_t* __restrict__ dof_node,
+                                                    int64_t n, double* __restrict__ b) {
+  constexpr int N1 = K + 1;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int I[3];
+  {
+    int r = dof_node[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      I[j] = r % R.nn;
+      r /= R.nn;
+    }
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int comb = 0; comb < (1 << D); ++comb) {
+    int cell = 0, loc = 0, sc = 1, sl = 1;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int sel = (comb >> j) & 1;  // 0: the cell below the node (or the one holding it), 1: above
+      int cj, lj;
+      if (I[j] % K == 0) {
+        cj = I[j] / K - 1 + sel;
+        lj = sel ? 0 : K;
+      } else {
+        ok = ok && sel == 0;
+        cj = I[j] / K;
+        lj = I[j] % K;
+      }
+      ok = ok && cj >= 0 && cj < R.N;
+      cell += cj * sc;
+      loc += lj * sl;
+      sc *= R.N;
+      sl *= N1;
+    }
+    if (!ok) continue;
+    const int a = R.act_id[cell];
+    if (a >= 0) v += R.loc[(int64_t)a * Pow<N1, D>::v + loc];
+  }
+  b[i] = v;
+}
+
+}  // namespace dev
+
+hipError_t launch_rhs_fourier(int d, int k, const RhsPlanDev& R, const RhsModes& M, const int32_t* dof_node,
+                              int64_t n_dofs, double* b, hipStream_t s) {
+  return dispatch(d, k, [&](auto D, auto K) {
+    if (R.n_uncut > 0)
+      hipLaunchKernelGGL((dev::k_rhs_uncut<D.value, K.value>), dim3(static_cast<unsigned>((R.n_uncut + 255) / 256)),
+                         dim3(256), 0, s, R, M);
+    if (R.n_cut > 0)
+      hipLaunchKernelGGL((dev::k_rhs_cut<D.value, K.value>), dim3(static_cast<unsigned>(R.n_cut)), dim3(256), 0, s,
+                         R, M);
+    if (n_dofs > 0)
+      hipLaunchKernelGGL((dev::k_rhs_gather<D.value, K.value>), dim3(static_cast<unsigned>((n_dofs + 255) / 256)),
+                         dim3(256), 0, s, R, dof_node, n_dofs, b);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace cmg

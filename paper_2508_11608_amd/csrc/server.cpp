@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdio>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -32,6 +33,7 @@
 #include <vector>
 
 #include "../../include/cutmg.h"
+#include "kernels.h"
 
 namespace {
 
@@ -99,6 +101,7 @@ struct Entry {
 };
 
 void free_entry(Entry& e) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());  // no graph capture meanwhile
   cmg_destroy(e.p);  // synchronises the device before freeing
   if (e.db) (void)hipFree(e.db);
   if (e.dx) (void)hipFree(e.dx);
@@ -224,7 +227,10 @@ cmg_status acquire(cmg_server* S, const OwnedRequest& rq, Entry** out, cmg_resul
   Entry e{key, p, bytes, true, 0, nullptr, nullptr, n};
   st = cmg_upload(p);
   const size_t vb = kBatch * static_cast<size_t>(n) * sizeof(double);
-  if (st == CMG_OK && (hipMalloc(&e.db, vb) != hipSuccess || hipMalloc(&e.dx, vb) != hipSuccess)) st = CMG_ENOMEM;
+  if (st == CMG_OK) {
+    std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+    if (hipMalloc(&e.db, vb) != hipSuccess || hipMalloc(&e.dx, vb) != hipSuccess) st = CMG_ENOMEM;
+  }
   res.t_admitted = S->now();
   if (st != CMG_OK) {
     free_entry(e);
@@ -287,19 +293,36 @@ void worker(cmg_server* S) {
     std::vector<cmg_solve_info> info(nb, cmg_solve_info{0, 0.0, 0.0});
     if (st == CMG_OK) {
       cmg_ndofs(e->p, rq.params.n_levels - 1, &n);
-      std::vector<double> B(static_cast<size_t>(n) * nb);
-      for (int c = 0; c < nb && st == CMG_OK; ++c) {
-        const OwnedRequest& q = batch[c];
-        double* bc = B.data() + static_cast<size_t>(c) * n;
-        st = q.kappa.empty() ? cmg_rhs_manufactured(e->p, bc)
-                             : cmg_rhs_fourier(e->p, static_cast<int>(q.amp.size()), q.kappa.data(), q.amp.data(),
-                                               q.phase.data(), bc);
-      }
       const size_t bytes = static_cast<size_t>(n) * nb * sizeof(double);
       double* db = e->db;
       double* dx = e->dx;
-      if (st == CMG_OK && hipMemcpyAsync(db, B.data(), bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
-        st = CMG_EHIP;
+      // Fourier loads are assembled on the device, on the worker's stream (the
+      // hierarchy's quadrature plan is built on its first use and then
+      // accounted in the memory in use); the manufactured load on the host
+      std::vector<double> B;
+      for (int c = 0; c < nb && st == CMG_OK; ++c) {
+        const OwnedRequest& q = batch[c];
+        double* bc = db + static_cast<size_t>(c) * n;
+        if (!q.kappa.empty()) {
+          size_t before = 0, after = 0;
+          cmg_device_bytes(e->p, 7, &before);
+          st = cmg_rhs_fourier_device(e->p, static_cast<int>(q.amp.size()), q.kappa.data(), q.amp.data(),
+                                      q.phase.data(), bc, stream);
+          cmg_device_bytes(e->p, 7, &after);
+          if (after > before) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->used += after - before;
+            e->bytes += after - before;
+          }
+          continue;
+        }
+        B.resize(static_cast<size_t>(n));
+        st = cmg_rhs_manufactured(e->p, B.data());
+        if (st == CMG_OK &&
+            (hipMemcpyAsync(bc, B.data(), B.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
+             hipStreamSynchronize(stream) != hipSuccess))
+          st = CMG_EHIP;
+      }
       const double t_solve = S->now();
       for (int c = 0; c < nb; ++c) res[c].t_solve_start = t_solve;
       if (st == CMG_OK) st = cmg_solve_multi(e->p, nb, db, dx, rq.rtol, rq.maxit, info.data(), stream);
@@ -311,6 +334,9 @@ void worker(cmg_server* S) {
       }
       release(S, e);
     }
+    if (st != CMG_OK && st != CMG_ENOTCONV && st != CMG_ENOMEM)
+      std::fprintf(stderr, "cutmg server: batch of %d request(s) failed with status %d: %s\n", nb,
+                   static_cast<int>(st), cmg_last_error());
     for (int c = 0; c < nb; ++c) {
       res[c].n_dofs = n;
       res[c].info = info[c];

@@ -846,6 +846,54 @@ void fourier_rhs(const Hierarchy& H, int n_modes, const int* kappa, const double
   load_vector(H, f, nullptr, b);
 }
 
+void build_rhs_plan(const Hierarchy& H, RhsPlan& R) {
+  const Config& cfg = H.cfg;
+  const HostLevel& L = H.levels.back();
+  const int d = cfg.dim;
+  LevelGeom geo{d, cfg.k, L.N, L.nn};
+  R = RhsPlan{};
+  R.act_id.assign(static_cast<size_t>(L.n_cells), -1);
+  for (int64_t c = 0; c < L.n_cells; ++c) {
+    if (!(L.cell_flags[c] & kActive)) continue;
+    R.act_id[c] = static_cast<int32_t>(R.n_active++);
+    if (L.cell_flags[c] & kCut) R.cut.push_back(static_cast<int32_t>(c));
+    else R.uncut.push_back(static_cast<int32_t>(c));
+  }
+  // columns per cut cell in parallel, concatenated in cut-cell order
+  const int64_t nc = static_cast<int64_t>(R.cut.size());
+  std::vector<std::vector<Column>> per(static_cast<size_t>(nc));
+  const int nq = cfg.quad_n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nc; ++i) {
+    int ci[kMaxDim];
+    geo.cell_of(R.cut[i], ci);
+    double lo[kMaxDim], hi[kMaxDim];
+    for (int j = 0; j < d; ++j) { lo[j] = cfg.lo + ci[j] * L.h; hi[j] = lo[j] + L.h; }
+    std::vector<Column> cols;
+    cut_columns_union(d, cfg.shapes, lo, hi, nq, nq, cfg.quad_beta, cfg.union_depth, cols);
+    for (const Column& col : cols)
+      if (col.t1 > col.t0) per[i].push_back(col);
+  }
+  R.col_off.assign(static_cast<size_t>(nc) + 1, 0);
+  for (int64_t i = 0; i < nc; ++i) R.col_off[i + 1] = R.col_off[i] + static_cast<int64_t>(per[i].size());
+  const int64_t n = R.col_off[nc];
+  R.cx.resize(static_cast<size_t>(d * n));
+  R.cw.resize(n);
+  R.ct0.resize(n);
+  R.ct1.resize(n);
+  R.ce.resize(n);
+  for (int64_t i = 0; i < nc; ++i)
+    for (size_t t = 0; t < per[i].size(); ++t) {
+      const Column& col = per[i][t];
+      const int64_t o = R.col_off[i] + static_cast<int64_t>(t);
+      for (int j = 0; j < d; ++j) R.cx[j * n + o] = col.x[j];
+      R.cw[o] = col.w;
+      R.ct0[o] = col.t0;
+      R.ct1[o] = col.t1;
+      R.ce[o] = static_cast<uint8_t>(col.e);
+    }
+}
+
 void load_vector(const Hierarchy& H, const std::function<double(const double*)>& f,
                  const std::function<double(const double*)>& u, std::vector<double>& b) {
   const Config& cfg = H.cfg;

@@ -61,7 +61,7 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
             "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve", "cmg_footprint",
-            "cmg_set_launch", "cmg_set_ghost_coupling", "cmg_apply_noalloc"]
+            "cmg_set_launch", "cmg_set_ghost_coupling", "cmg_apply_noalloc", "cmg_rhs_fourier_device", "cmg_set_graphs"]
 
 _lib = None
 
@@ -83,6 +83,7 @@ def load_library():
         "cmg_set_precision": [P, I],
         "cmg_apply": [P, I, V, V, V],
         "cmg_apply_noalloc": [P, I, V, V, V],
+        "cmg_rhs_fourier_device": [P, I, V, V, V, V, V],
         "cmg_colour_step": [P, I, I, I, V, V, V],
         "cmg_smooth": [P, I, I, V, V, V],
         "cmg_transfer": [P, I, I, V, V, V],
@@ -107,6 +108,7 @@ def load_library():
                           ctypes.POINTER(ctypes.c_int64)],
         "cmg_set_launch": [P, I, I],
         "cmg_set_ghost_coupling": [P, I],
+        "cmg_set_graphs": [P, I],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -181,6 +183,10 @@ class Problem:
         """Cut-patch residuals with the exact ghost coupling (False) or patch-local,
         with x beyond the patch closure taken as zero (True; cmg_set_ghost_coupling)."""
         _check(_lib.cmg_set_ghost_coupling(self._h, int(bool(patch_local))))
+
+    def set_graphs(self, enable: bool):
+        """V-cycles as replays of captured HIP graphs (True, default) or kernel by kernel."""
+        _check(_lib.cmg_set_graphs(self._h, int(bool(enable))))
 
     def device_bytes(self, fp32: bool = False, multi: bool = False) -> int:
         n = ctypes.c_size_t()
@@ -329,6 +335,22 @@ class Problem:
         _check(_lib.cmg_rhs_fourier(self._h, len(amp), kappa.ctypes.data_as(ctypes.c_void_p),
                                     amp.ctypes.data_as(ctypes.c_void_p), phase.ctypes.data_as(ctypes.c_void_p),
                                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return b
+
+    def rhs_fourier_device(self, kappa, amp, phase, b=None):
+        """The same load vector assembled on the device (cmg_rhs_fourier_device)
+        into b (a float64 CUDA tensor, allocated when not given)."""
+        import torch
+
+        kappa = np.ascontiguousarray(kappa, dtype=np.int32)
+        amp = np.ascontiguousarray(amp, dtype=np.float64)
+        phase = np.ascontiguousarray(phase, dtype=np.float64)
+        n = self.ndofs(None)
+        if b is None:
+            b = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(_lib.cmg_rhs_fourier_device(self._h, len(amp), kappa.ctypes.data_as(ctypes.c_void_p),
+                                           amp.ctypes.data_as(ctypes.c_void_p),
+                                           phase.ctypes.data_as(ctypes.c_void_p), _dev(b, n), _stream()))
         return b
 
     def export(self, level, what: int, dtype) -> np.ndarray:
