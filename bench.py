@@ -68,6 +68,8 @@ def parse():
                     help="iteration counts of GMRES and of the stand-alone V-cycle on the paper's circle protocol "
                          "for the comma-separated finest levels L (k = 1..3, n_c = 1..4), beside the paper's numbers")
     ap.add_argument("--rate", type=float, default=0.8, help="arrival rate as a fraction of the saturation rate")
+    ap.add_argument("--small-cut-launch", type=int, default=None,
+                    help="cut colour steps with fewer patches run with twice the threads per patch (default 1536)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every V-cycle kernel by kernel instead of replaying captured HIP graphs")
     return ap.parse_args()
@@ -542,6 +544,8 @@ def main():
     t_setup = time.perf_counter() - t0
     if args.no_graphs:
         P.set_graphs(False)
+    if args.small_cut_launch is not None:
+        P.set_launch(args.small_cut_launch, 2048)
     n = P.ndofs()
     print(f"[bench] {w.name}: {n} DoFs, setup {t_setup:.1f}s", file=sys.stderr, flush=True)
     b = torch.from_numpy(P.rhs_manufactured()).cuda()
