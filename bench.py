@@ -247,7 +247,8 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool = True) -> dict:
+def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool = True,
+                      dense: bool = False) -> dict:
     """Algorithmic HBM bytes of every launch of one kernel kind in one V-cycle,
     keyed by (level, colour) (or level for 'apply'); s = 8 B (FP64 multigrid)
     or 4 B (FP32 multigrid), indices 4 B.  With m columns the matrix and index
@@ -264,19 +265,23 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool 
         after colour p: 5 B (node, flag) per DoF of p and 2 s per DoF of p
         that the current colour does not own (every step of a pass but the
         first, in both passes; averaged over the colour's launches).
-    apply (residual), per DoF: 4 + 3 s, plus s (k+1)^{2d} per cut cell; the
-        CG product A p once per iteration on the finest level, always FP64:
-        4 + 2*8 per DoF plus 8 (k+1)^{2d} per cut cell.
+    apply (residual), per DoF: 4 + 3 s, plus s (k+1)^d ((k+1)^d + 1) / 2 per
+        cut cell (its packed symmetric matrix); the CG product A p once per
+        iteration on the finest level, always FP64: 4 + 2*8 per DoF plus the
+        packed matrix in FP64 per cut cell.
+    dense=True gives the operator terms for dense cut-cell matrices ((k+1)^{2d}
+    per cut cell).
     """
     d, k = w.dim, w.k
     nl = (k + 1) ** d
+    ncm = nl * nl if dense else nl * (nl + 1) // 2  # entries read per cut-cell matrix
     out = {}
     for l in range(1, w.n_levels):
         c = P.counts(l)
         if kind == "apply":
-            out[l] = c["n_dofs"] * (4 + 3 * s * m) + c["cut_cells"] * nl * nl * s
+            out[l] = c["n_dofs"] * (4 + 3 * s * m) + c["cut_cells"] * ncm * s
             if l == w.n_levels - 1:  # the CG product A p on the finest level (no b)
-                out["cg"] = c["n_dofs"] * (4 + 2 * 8 * m) + c["cut_cells"] * nl * nl * 8
+                out["cg"] = c["n_dofs"] * (4 + 2 * 8 * m) + c["cut_cells"] * ncm * 8
             continue
         N = P.export(l, 2, np.uint8)  # cell flags, x fastest
         Nc = round(len(N) ** (1.0 / d))
@@ -320,7 +325,7 @@ def algorithmic_bytes(P, w, kind: str, s: int = 8, m: int = 1, two_buffer: bool 
     return out
 
 
-def vcycle_bytes(P, w, s: int = 8, m: int = 1) -> int:
+def vcycle_bytes(P, w, s: int = 8, m: int = 1, dense: bool = False) -> int:
     """Algorithmic bytes of one whole V-cycle (one pre- and one post-smoothing
     step per level, n_c sweeps over the cut colours):
         sum_{l >= 1} [2 (S_int + n_c S_cut) + R + T] + s (n_0^2 + 2 n_0)
@@ -329,10 +334,10 @@ def vcycle_bytes(P, w, s: int = 8, m: int = 1) -> int:
     level residual b - A x, T the transfers s (3 n_l + 2 n_{l-1}) (prolongation
     reads e and x and writes x, restriction reads r and writes the coarse b),
     and the coarse solve a GEMV with the dense inverse.  With m columns the
-    matrix terms count once."""
+    matrix terms count once; dense as in algorithmic_bytes."""
     inter = algorithmic_bytes(P, w, "interior_step", s, m)
     cut = algorithmic_bytes(P, w, "cut_solve", s, m, two_buffer=(m == 1))
-    app = algorithmic_bytes(P, w, "apply", s, m)
+    app = algorithmic_bytes(P, w, "apply", s, m, dense=dense)
     total = 2 * sum(inter.values()) + 2 * w.n_c * sum(cut.values())
     total += sum(v for key, v in app.items() if key != "cg")
     n = [P.counts(l)["n_dofs"] for l in range(w.n_levels)]
@@ -445,8 +450,10 @@ def timed_multi_solves(P, w, B, args, fp32: bool) -> dict:
     torch.cuda.synchronize()
     t_v = e0.elapsed_time(e1) / 1e3 / nv
     bv = vcycle_bytes(P, w, 4 if fp32 else 8, nrhs)
+    bv_dense = vcycle_bytes(P, w, 4 if fp32 else 8, nrhs, dense=True)
     vroof = {"bound": "hbm", "algorithmic_bytes": bv, "vcycle_ms": t_v * 1e3, "achieved": bv / t_v / 1e9,
-             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS}
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS,
+             "algorithmic_bytes_dense_storage": bv_dense}
     return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * nrhs * vcyc / dt,
             "x": X.clone(), "vcycle_roofline": vroof,
             "ms_per_step": dt / args.steps * 1e3, "iterations_per_column": [i["iterations"] for i in infos],
@@ -500,8 +507,10 @@ def timed_solves(P, w, b, x, args, fp32: bool) -> dict:
     torch.cuda.synchronize()
     t_v = e0.elapsed_time(e1) / 1e3 / nv
     bv = vcycle_bytes(P, w, 4 if fp32 else 8)
+    bv_dense = vcycle_bytes(P, w, 4 if fp32 else 8, dense=True)
     vroof = {"bound": "hbm", "algorithmic_bytes": bv, "vcycle_ms": t_v * 1e3, "achieved": bv / t_v / 1e9,
-             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS}
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bv / t_v / 1e9 / HBM_PEAK_GBS,
+             "algorithmic_bytes_dense_storage": bv_dense}
     return {"precision": "fp32 multigrid, fp64 CG" if fp32 else "fp64", "value": n * its / dt,
             "x": x.clone(), "vcycle_roofline": vroof,
             "ms_per_step": dt / args.steps * 1e3, "iterations_per_solve": its / args.steps,

@@ -214,6 +214,20 @@ cmg_status upload_f32(std::vector<void*>& owned, const std::vector<double>& host
   return upload(owned, f, dptr);
 }
 
+// Upper triangles (diagonal included, row-major) of n consecutive symmetric
+// nl x nl matrices: the cut-cell matrices as the operator's cell pre-pass
+// reads them.
+template <typename T>
+std::vector<T> pack_upper(const std::vector<double>& full, size_t nl) {
+  const size_t n = nl == 0 ? 0 : full.size() / (nl * nl);
+  std::vector<T> out;
+  out.reserve(n * nl * (nl + 1) / 2);
+  for (size_t m = 0; m < n; ++m)
+    for (size_t a = 0; a < nl; ++a)
+      for (size_t b = a; b < nl; ++b) out.push_back(static_cast<T>(full[(m * nl + a) * nl + b]));
+  return out;
+}
+
 template <typename T>
 cmg_status alloc_zero(std::vector<void*>& owned, size_t n, T** dptr) {
   *dptr = nullptr;
@@ -271,6 +285,9 @@ cmg_status upload_all(cmg_problem* P) {
     TRY(upload(own, h.cut_id, &cut_id));
     TRY(upload(own, h.ghost_mask, &ghost));
     TRY(upload(own, h.cut_mats, &cm));
+    double* cpk;
+    const size_t nl = static_cast<size_t>(std::pow(cfg.k + 1, cfg.dim));
+    TRY(upload(own, pack_upper<double>(h.cut_mats, nl), &cpk));
     TRY(upload(own, h.dof_node, &dn));
     const cmg::LevelTables& t = P->H.tables[l];
     std::vector<double> packed;
@@ -283,6 +300,7 @@ cmg_status upload_all(cmg_problem* P) {
     k.cut_id = cut_id;
     k.ghost = ghost;
     k.cut_mats = cm;
+    k.cut_packed = cpk;
     k.dof_node = dn;
     k.tables = tab;
     int32_t *flow, *cgid, *cfaces, *tiles;
@@ -314,6 +332,7 @@ cmg_status upload_all(cmg_problem* P) {
     }
     d.kl32 = k;
     d.kl32.cut_mats = nullptr;
+    d.kl32.cut_packed = nullptr;
     TRY(alloc_zero(own, h.n_nodes, &d.v64.x));
     TRY(alloc_zero(own, h.n_nodes, &d.v64.b));
     TRY(alloc_zero(own, h.n_nodes, &d.v64.r));
@@ -403,6 +422,10 @@ cmg_status ensure_fp32(cmg_problem* P) {
     float* cm;
     TRY(upload_f32(own, h.cut_mats, &cm));
     d.kl32.cut_mats = cm;
+    float* cpk;
+    const size_t nl = static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim));
+    TRY(upload(own, pack_upper<float>(h.cut_mats, nl), &cpk));
+    d.kl32.cut_packed = cpk;
     for (int c = 0; c < 8; ++c) {
       if (d.cut32[c].n_patch == 0) continue;
       float* inv;
@@ -1083,7 +1106,8 @@ size_t hierarchy_bytes(const cmg::Hierarchy& H, int flags) {
   size_t b64 = 0, b32 = 0, m64 = 0, m32 = 0;
   for (const cmg::HostLevel& h : H.levels) {
     size_t maxn = 0;
-    const size_t ncm = static_cast<size_t>(h.n_cut) * nl * nl;  // cut-cell matrix entries
+    // cut-cell matrix entries: full (rows of the cut steps) and packed upper triangles (operator)
+    const size_t ncm = static_cast<size_t>(h.n_cut) * (nl * nl + nl * (nl + 1) / 2);
     b64 += h.cell_flags.size() + h.ghost_mask.size() + 4 * (h.cut_id.size() + h.dof_node.size()) +
            8 * (ncm + nt) + 4 * (h.face_lower.size() + h.cell_gid.size() + h.cell_faces.size() +
            h.tiles.size()) + h.face_dir.size();

@@ -19,6 +19,7 @@ struct KLevel {
   const int32_t* cut_id;     // per cell: index of its cut-cell matrix or -1
   const uint8_t* ghost;      // per cell: bit 2*dir+side marks a ghost face
   const void* cut_mats;      // n_cut x (k+1)^d x (k+1)^d, scalar type of the path (symmetric)
+  const void* cut_packed;    // the same matrices as upper triangles, row-major, (k+1)^d ((k+1)^d + 1) / 2 each
   int64_t n_cut;             // cut cells
   const int32_t* dof_node;   // lattice node of each DoF, ascending
   const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
@@ -37,6 +38,8 @@ struct KLevel {
                              // faces on the patch boundary contribute only their closure part), 0 = exact
   template <typename T>
   __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
+  template <typename T>
+  __host__ __device__ const T* cut_packed_t() const { return static_cast<const T*>(cut_packed); }
 };
 
 // Cut patches of one colour.

@@ -195,8 +195,9 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
 // with E_T the cut-cell matrix or the uncut stiffness and W the face pre-pass
 // output, so that the operator kernel adds one value per special cell and
 // node.  CPB cells per 64-thread block, one thread per cell node, the columns
-// together; E_T is symmetric, so a thread reads column i and consecutive
-// threads read consecutive entries.
+// together.  A cut cell's E_T is symmetric and read as its packed upper
+// triangle, (k+1)^d ((k+1)^d + 1) / 2 entries instead of (k+1)^{2d}, staged in
+// LDS by the cell's threads (consecutive threads, consecutive entries).
 template <int D, int K>
 struct CellShape {
   static constexpr int NL = Shape<D, K>::NL;
@@ -210,7 +211,9 @@ __global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ 
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, CPB = CellShape<D, K>::CPB, NF = 2 * D;
   constexpr int NT = Pow<N1, D - 1>::v;
+  constexpr int NPK = NL * (NL + 1) / 2;  // entries of a packed symmetric cell matrix
   __shared__ T xs[CPB][NL][NCOL];
+  __shared__ T epk[CPB][NPK];
   const int lc = threadIdx.x / NL;
   const int i = threadIdx.x % NL;
   const int64_t t = (int64_t)blockIdx.x * CPB + lc;
@@ -233,6 +236,27 @@ __global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ 
     const int64_t node = lat(D, L.nn, I);
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) xs[lc][i][c] = c < ncol ? x[c * L.n_nodes + node] : (T)0;
+    // a cut cell's matrix, read once as its packed upper triangle (the cell's
+    // threads read consecutive entries, G loads in flight per thread) and
+    // staged for all rows
+    if (info[0] >= 0) {
+      const T* P = L.cut_packed_t<T>() + (int64_t)info[0] * NPK;
+      constexpr int NR = (NPK + NL - 1) / NL, G = 8;
+#pragma unroll
+      for (int r0 = 0; r0 < NR; r0 += G) {
+        T v[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const int e = (r0 + r) * NL + i;
+          v[r] = (r0 + r < NR && e < NPK) ? P[e] : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const int e = (r0 + r) * NL + i;
+          if (r0 + r < NR && e < NPK) epk[lc][e] = v[r];
+        }
+      }
+    }
   }
   __syncthreads();
   if (!on) return;
@@ -271,10 +295,13 @@ __global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ 
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) cell[c] = 0;
   if (info[0] >= 0) {
-    const T* E = L.cut_mats_t<T>() + (int64_t)info[0] * NL * NL + i;
+    // entry (a, b), a <= b, of the packed upper triangle sits at a (2 NL - a + 1) / 2 + b - a;
+    // row i of E is (j, i) for j < i and (i, j) from the diagonal on
+    const int rowi = i * (2 * NL - i + 1) / 2;
 #pragma unroll 4
     for (int j = 0; j < NL; ++j) {
-      const T e = E[j * NL];
+      const int q = j < i ? j * (2 * NL - j + 1) / 2 + (i - j) : rowi + (j - i);
+      const T e = epk[lc][q];
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) cell[c] += e * xs[lc][j][c];
     }
