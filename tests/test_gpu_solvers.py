@@ -84,3 +84,29 @@ def test_gmres_in_fp32_multigrid(case):
         P.set_precision(False)
     assert abs(i32["iterations"] - i64["iterations"]) <= 1
     assert np.linalg.norm(b - mats[-1] @ x.cpu().numpy()) <= 1.01e-9 * np.linalg.norm(b)
+
+
+def test_cg_stopped_at_maxit_is_enotconv_with_the_last_iterate(case):
+    """An unreachable tolerance with maxit = 2: CMG_ENOTCONV, two iterations
+    reported, and x is the oracle's PCG iterate after two steps."""
+    import torch
+    from oracle.multigrid import pcg
+
+    w, P, levels, mats, H, b = case
+    x, info = P.solve(torch.from_numpy(b).cuda(), rtol=1e-15, maxit=2, raise_on_fail=False)
+    xr, it, hist = pcg(mats[-1], b, H.vcycle, rtol=1e-15, maxit=2)
+    print(f"  CG maxit 2: status {info['status']}, residual {info['rel_residual']:.3e} (oracle {hist[-1]:.3e})")
+    assert info["status"] == -5 and info["iterations"] == 2 and it == 2
+    assert abs(info["rel_residual"] - hist[-1]) <= 1e-8 * hist[-1]
+    assert _rel(x.cpu().numpy(), xr) < 1e-8
+
+
+def test_non_finite_right_hand_side_is_einval(case):
+    """A NaN in b is refused before any iteration (CMG_EINVAL)."""
+    import torch
+
+    w, P, levels, mats, H, b = case
+    bn = b.copy()
+    bn[len(bn) // 2] = np.nan
+    _, info = P.solve(torch.from_numpy(bn).cuda(), raise_on_fail=False)
+    assert info["status"] == -1 and info["iterations"] == 0

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2508_11608_amd", "libcutmg.so")
 pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcutmg.so not built")
 
-CMG_EINVAL, CMG_EGEOM = -1, -3
+CMG_EINVAL, CMG_EGEOM, CMG_ENOTSPD = -1, -3, -4
 
 
 @pytest.mark.parametrize("w", [W.disc_q2(), W.offcentre_ball(3, 2), W.ball_union(2, 3), W.sphere_union_8(3, 2),
@@ -41,6 +41,15 @@ def _status(fn):
     except CutmgError as e:
         return e.status
     return 0
+
+
+def test_indefinite_form_is_enotspd():
+    """A negative ghost penalty makes the bilinear form indefinite: the set-up
+    stops at the first Cholesky factorisation that fails (CMG_ENOTSPD)."""
+    from paper_2508_11608_amd import Problem
+
+    w = W.Workload(**{**W.disc_q2().__dict__, "gamma_g": -0.5, "name": "negative-ghost"})
+    assert _status(lambda: Problem(w, device=False)) == CMG_ENOTSPD
 
 
 def test_geometry_outside_the_box_is_egeom():
