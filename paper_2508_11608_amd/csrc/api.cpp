@@ -291,7 +291,7 @@ cmg_status upload_all(cmg_problem* P) {
     TRY(upload(own, h.dof_node, &dn));
     const cmg::LevelTables& t = P->H.tables[l];
     std::vector<double> packed;
-    for (const auto* v : {&t.kcell, &t.mhat, &t.d0, &t.d1, &t.gcoef, &t.fd_s, &t.fd_dinv, &t.p1d})
+    for (const auto* v : {&t.kcell, &t.mhat, &t.d0, &t.d1, &t.gcoef, &t.fd_s, &t.fd_dinv, &t.p1d, &t.k1s})
       packed.insert(packed.end(), v->begin(), v->end());
     if (static_cast<int>(packed.size()) != cmg::tables_size(cfg.dim, cfg.k))
       return fail(CMG_EINVAL, "internal: table layout mismatch");

@@ -124,6 +124,7 @@ struct LevelTables {
   std::vector<double> fd_s;      // (2k-1)^2 fast-diagonalisation eigenvectors (row-major S)
   std::vector<double> fd_dinv;   // (2k-1)^d inverse eigenvalue sums incl. h scaling
   std::vector<double> p1d;       // (2k+1) x (k+1) prolongation weights
+  std::vector<double> k1s;       // (k+1)^2 reference 1-D stiffness times h^(d-2)
 };
 
 struct Hierarchy {

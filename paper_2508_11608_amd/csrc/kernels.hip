@@ -64,7 +64,8 @@ struct Shape {
   static constexpr int T_FDS = T_GC + K;
   static constexpr int T_FDD = T_FDS + NP1 * NP1;
   static constexpr int T_P1D = T_FDD + NP;
-  static constexpr int T_SIZE = T_P1D + NC1 * N1;
+  static constexpr int T_K1S = T_P1D + NC1 * N1;
+  static constexpr int T_SIZE = T_K1S + N1 * N1;
 };
 
 // Work index of block b out of n such that the blocks of one XCD take one
@@ -475,6 +476,29 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   }
 }
 
+// Entry (r, j) of a 1-D matrix assembled on the 2k+1 closure nodes of a patch
+// from the element matrix e ((k+1) x (k+1), row-major) of its two cells, the
+// second cell starting at node k.  patch1d_nz tells whether some cell holds
+// both nodes; with compile-time r and j both fold to constants.
+template <int K>
+__device__ __forceinline__ constexpr bool patch1d_nz(int r, int j) {
+  return (r <= K && j <= K) || (r >= K && j >= K);
+}
+template <int K>
+__device__ __forceinline__ double patch1d(const double* e, int r, int j) {
+  double v = 0;
+  if (r <= K && j <= K) v += e[r * (K + 1) + j];
+  if (r >= K && j >= K) v += e[(r - K) * (K + 1) + (j - K)];
+  return v;
+}
+// The same with a run-time row r: each term is read when its cell holds both nodes.
+template <int K>
+__device__ __forceinline__ double patch1d_rt(const double* e, int r, int j) {
+  const double lo = (r <= K && j <= K) ? e[(r <= K ? r : 0) * (K + 1) + (j <= K ? j : 0)] : 0.0;
+  const double hi = (r >= K && j >= K) ? e[(r >= K ? r - K : 0) * (K + 1) + (j >= K ? j - K : 0)] : 0.0;
+  return lo + hi;
+}
+
 // Fused colour step over interior patches.
 template <int D, int K, typename T>
 __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* __restrict__ verts, int nv,
@@ -486,8 +510,12 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   __shared__ T ra[PPB][NP];
   __shared__ T rb[PPB][NP];
   __shared__ int64_t pbase[PPB];  // lattice index of each patch's closure corner (-1: no patch)
-  constexpr int NPAIR = Pow<2 * K, D>::v;  // (node, cell) pairs of a patch, as in the cut-patch step
-  __shared__ T parts[PPB][NPAIR];
+  // sum-factorisation intermediates: after the slowest direction (3-D only) and
+  // after the next one, per closure line of the remaining directions
+  __shared__ T su[D == 3 ? PPB : 1][D == 3 ? NC1 * NC1 : 1][NP1];
+  __shared__ T sk[D == 3 ? PPB : 1][D == 3 ? NC1 * NC1 : 1][NP1];
+  __shared__ T vm[PPB][NC1][D == 3 ? NP1 * NP1 : NP1];
+  __shared__ T vx[PPB][NC1][D == 3 ? NP1 * NP1 : NP1];
   load_tables<D, K>(L.tables, tab, S::T_SIZE);
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   b += blockIdx.y * L.n_nodes;
@@ -556,67 +584,97 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
     node = pbase[p] + ioff;
     bnode = b[node];
   }
-  // residual with the Cartesian stiffness, split into (node, cell) pairs: along
-  // each direction a node at patch coordinate p in 1..2k-1 lies in cell layer 0
-  // (p <= k) and/or 1 (p >= k), 2k choices per direction; one pair is one row
-  // of the cell stiffness times the cell's x
-  for (int t = threadIdx.x; t < PPB * NPAIR; t += blockDim.x) {
-    const int pp = t / NPAIR, tt = t % NPAIR;
-    if (gp0 + pp >= nv) continue;
-    int il[3], c[3];
-    {
-      int r = tt;
+  // residual b - A x at the internal nodes by sum factorisation on the closure.
+  // An interior patch's 2^d cells are all uncut, so A restricted to it is the
+  // sum over directions a of tensor products with the assembled 1-D stiffness
+  // (h^(d-2) K1) along a and the assembled 1-D mass along the others (each 1-D
+  // matrix on the 2k+1 closure nodes is the sum of the two cells' element
+  // matrices).  Contractions run from the slowest direction to the fastest;
+  // only the internal rows 1..2k-1 of each direction are formed.
+  {
+    const double* m1 = tab + S::T_MHAT;
+    const double* k1 = tab + S::T_K1S;
+    if constexpr (D == 3) {
+      // direction 2: um = Mhat_2 x, uk = Khat_2 x on every (q0, q1) line
+      for (int t = threadIdx.x; t < PPB * NC1 * NC1; t += blockDim.x) {
+        const int pp = t / (NC1 * NC1), l = t % (NC1 * NC1);
+        if (gp0 + pp >= nv) continue;
+        T xv[NC1];
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int j = r % (2 * K);
-        r /= 2 * K;
-        c[a] = j >= K ? 1 : 0;
-        il[a] = (j < K ? j + 1 : j) - K * c[a];
+        for (int j = 0; j < NC1; ++j) xv[j] = xs[pp][l + NC1 * NC1 * j];
+#pragma unroll
+        for (int r = 1; r <= NP1; ++r) {
+          T um = 0, uk = 0;
+#pragma unroll
+          for (int j = 0; j < NC1; ++j) {
+            if (!patch1d_nz<K>(r, j)) continue;
+            um += (T)patch1d<K>(m1, r, j) * xv[j];
+            uk += (T)patch1d<K>(k1, r, j) * xv[j];
+          }
+          su[pp][l][r - 1] = um;
+          sk[pp][l][r - 1] = uk;
+        }
+      }
+      __syncthreads();
+      // direction 1: vm = Mhat_1 um, vx = Khat_1 um + Mhat_1 uk on every (q0, r2) line
+      for (int t = threadIdx.x; t < PPB * NC1 * NP1; t += blockDim.x) {
+        const int pp = t / (NC1 * NP1), q0 = (t / NP1) % NC1, r2 = t % NP1;
+        if (gp0 + pp >= nv) continue;
+        T uv[NC1], kv[NC1];
+#pragma unroll
+        for (int j = 0; j < NC1; ++j) {
+          uv[j] = su[pp][q0 + NC1 * j][r2];
+          kv[j] = sk[pp][q0 + NC1 * j][r2];
+        }
+#pragma unroll
+        for (int r = 1; r <= NP1; ++r) {
+          T vmv = 0, vxv = 0;
+#pragma unroll
+          for (int j = 0; j < NC1; ++j) {
+            if (!patch1d_nz<K>(r, j)) continue;
+            vmv += (T)patch1d<K>(m1, r, j) * uv[j];
+            vxv += (T)patch1d<K>(k1, r, j) * uv[j];
+            vxv += (T)patch1d<K>(m1, r, j) * kv[j];
+          }
+          vm[pp][q0][(r - 1) + NP1 * r2] = vmv;
+          vx[pp][q0][(r - 1) + NP1 * r2] = vxv;
+        }
+      }
+    } else {
+      // direction 1: um = Mhat_1 x, uk = Khat_1 x on every q0 line
+      for (int t = threadIdx.x; t < PPB * NC1; t += blockDim.x) {
+        const int pp = t / NC1, q0 = t % NC1;
+        if (gp0 + pp >= nv) continue;
+        T xv[NC1];
+#pragma unroll
+        for (int j = 0; j < NC1; ++j) xv[j] = xs[pp][q0 + NC1 * j];
+#pragma unroll
+        for (int r = 1; r <= NP1; ++r) {
+          T um = 0, uk = 0;
+#pragma unroll
+          for (int j = 0; j < NC1; ++j) {
+            if (!patch1d_nz<K>(r, j)) continue;
+            um += (T)patch1d<K>(m1, r, j) * xv[j];
+            uk += (T)patch1d<K>(k1, r, j) * xv[j];
+          }
+          vm[pp][q0][r - 1] = um;
+          vx[pp][q0][r - 1] = uk;
+        }
       }
     }
-    int iloc = il[0] + N1 * il[1];
-    if (D == 3) iloc += N1 * N1 * il[2];
-    const double* row = tab + S::T_KCELL + iloc * NL;
-    int qb = K * c[0] + NC1 * K * c[1];
-    if (D == 3) qb += NC1 * NC1 * K * c[2];
-    constexpr int NRW = N1 * (D == 3 ? N1 : 1);
-    T acc[NRW];
+    __syncthreads();
+    // direction 0, at the thread's own node: (A x)(node) = Khat_0 vm + Mhat_0 vx
+    if (active) {
+      const int rw = (pi[1] - 1) + (D == 3 ? NP1 * (pi[2] - 1) : 0);
+      T ax = 0;
 #pragma unroll
-    for (int a = 0; a < NRW; ++a) acc[a] = 0;
-#pragma unroll
-    for (int bq = 0; bq < NL; ++bq) {
-      const int b0 = bq % N1, b12 = bq / N1;
-      const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
-      acc[b12] += (T)row[bq] * xs[pp][q];
-    }
-    T part = 0;
-#pragma unroll
-    for (int a = 0; a < NRW; ++a) part += acc[a];
-    parts[pp][tt] = part;
-  }
-  __syncthreads();
-  if (active) {
-    // the node's pairs in increasing pair index
-    int jlo[3], jn[3];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      jlo[a] = pi[a] <= K ? pi[a] - 1 : pi[a];
-      jn[a] = pi[a] == K ? 2 : 1;
-    }
-    T ax = 0;
-    const int ncomb = jn[0] * jn[1] * (D == 3 ? jn[2] : 1);
-    for (int comb = 0; comb < ncomb; ++comb) {
-      int t = 0, r = comb, st = 1;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const int sel = r % jn[a];
-        r /= jn[a];
-        t += (jlo[a] + sel) * st;
-        st *= 2 * K;
+      for (int j = 0; j < NC1; ++j) {
+        if (j < pi[0] - K || j > pi[0] + K) continue;
+        ax += (T)patch1d_rt<K>(k1, pi[0], j) * vm[p][j][rw];
+        ax += (T)patch1d_rt<K>(m1, pi[0], j) * vx[p][j][rw];
       }
-      ax += parts[p][t];
+      ra[p][i] = bnode - ax;
     }
-    ra[p][i] = bnode - ax;
   }
   __syncthreads();
   // fast diagonalisation: apply S^T along every direction, scale, apply S

@@ -574,6 +574,11 @@ std::string build_hierarchy(const Config& cfg, Hierarchy& H, bool numeric) {
         const double eta = q == 2 * k ? 1.0 : 0.5 * (f + H.basis.node[a]);
         for (int b = 0; b <= k; ++b) T.p1d[q * n1 + b] = H.basis.eval(b, eta);
       }
+      // reference 1-D stiffness times h^(d-2): the uncut cell stiffness is the
+      // sum over directions a of the tensor products with this factor along a
+      // and the reference 1-D mass along the others
+      T.k1s.assign(n1 * n1, 0.0);
+      for (int i = 0; i < n1 * n1; ++i) T.k1s[i] = std::pow(L.h, d - 2) * K1[i];
     }
     // Patches and their inverses (levels >= 1), coarse inverse (level 0).
     for (int l = 0; l < cfg.n_levels; ++l) {
