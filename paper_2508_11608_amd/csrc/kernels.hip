@@ -644,18 +644,18 @@ template <int K>
 __device__ __forceinline__ constexpr bool patch1d_nz(int r, int j) {
   return (r <= K && j <= K) || (r >= K && j >= K);
 }
-template <int K>
-__device__ __forceinline__ double patch1d(const double* e, int r, int j) {
-  double v = 0;
+template <int K, typename E>
+__device__ __forceinline__ E patch1d(const E* e, int r, int j) {
+  E v = 0;
   if (r <= K && j <= K) v += e[r * (K + 1) + j];
   if (r >= K && j >= K) v += e[(r - K) * (K + 1) + (j - K)];
   return v;
 }
 // The same with a run-time row r: each term is read when its cell holds both nodes.
-template <int K>
-__device__ __forceinline__ double patch1d_rt(const double* e, int r, int j) {
-  const double lo = (r <= K && j <= K) ? e[(r <= K ? r : 0) * (K + 1) + (j <= K ? j : 0)] : 0.0;
-  const double hi = (r >= K && j >= K) ? e[(r >= K ? r - K : 0) * (K + 1) + (j >= K ? j - K : 0)] : 0.0;
+template <int K, typename E>
+__device__ __forceinline__ E patch1d_rt(const E* e, int r, int j) {
+  const E lo = (r <= K && j <= K) ? e[(r <= K ? r : 0) * (K + 1) + (j <= K ? j : 0)] : E(0);
+  const E hi = (r >= K && j >= K) ? e[(r >= K ? r - K : 0) * (K + 1) + (j >= K ? j - K : 0)] : E(0);
   return lo + hi;
 }
 
@@ -665,7 +665,9 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
                                                        T* __restrict__ x, const T* __restrict__ b) {
   using S = Shape<D, K>;
   constexpr int NP = S::NP, NP1 = S::NP1, NC = S::NC, NC1 = S::NC1, PPB = S::PPB, N1 = S::N1, NL = S::NL;
-  __shared__ double tab[S::T_SIZE];
+  // the level tables this kernel reads, in the precision of the path: 1-D mass,
+  // scaled 1-D stiffness, fast-diagonalisation eigenvectors and inverse sums
+  __shared__ T cm1[N1 * N1], ck1[N1 * N1], cfs[NP1 * NP1], cfd[NP];
   __shared__ T xs[PPB][NC];
   __shared__ T ra[PPB][NP];
   __shared__ T rb[PPB][NP];
@@ -676,7 +678,12 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   __shared__ T sk[D == 3 ? PPB : 1][D == 3 ? NC1 * NC1 : 1][NP1];
   __shared__ T vm[PPB][NC1][D == 3 ? NP1 * NP1 : NP1];
   __shared__ T vx[PPB][NC1][D == 3 ? NP1 * NP1 : NP1];
-  load_tables<D, K>(L.tables, tab, S::T_SIZE);
+  for (int i = threadIdx.x; i < N1 * N1; i += blockDim.x) {
+    cm1[i] = (T)L.tables[S::T_MHAT + i];
+    ck1[i] = (T)L.tables[S::T_K1S + i];
+  }
+  for (int i = threadIdx.x; i < NP1 * NP1; i += blockDim.x) cfs[i] = (T)L.tables[S::T_FDS + i];
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) cfd[i] = (T)L.tables[S::T_FDD + i];
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   b += blockIdx.y * L.n_nodes;
   const int p = threadIdx.x / NP, i = threadIdx.x % NP;
@@ -752,8 +759,8 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   // matrices).  Contractions run from the slowest direction to the fastest;
   // only the internal rows 1..2k-1 of each direction are formed.
   {
-    const double* m1 = tab + S::T_MHAT;
-    const double* k1 = tab + S::T_K1S;
+    const T* m1 = cm1;
+    const T* k1 = ck1;
     if constexpr (D == 3) {
       // direction 2: um = Mhat_2 x, uk = Khat_2 x on every (q0, q1) line
       for (int t = threadIdx.x; t < PPB * NC1 * NC1; t += blockDim.x) {
@@ -838,7 +845,7 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   }
   __syncthreads();
   // fast diagonalisation: apply S^T along every direction, scale, apply S
-  const double* fs = tab + S::T_FDS;
+  const T* fs = cfs;
   T* src = &ra[0][0];
   T* dst = &rb[0][0];
   for (int stage = 0; stage < 2 * D; ++stage) {
@@ -855,10 +862,10 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
       T s = 0;
 #pragma unroll
       for (int q = 0; q < NP1; ++q) {
-        const double m = transpose ? fs[q * NP1 + ia[a]] : fs[ia[a] * NP1 + q];
-        s += (T)m * src[p * NP + baseIdx + q * strideA];
+        const T m = transpose ? fs[q * NP1 + ia[a]] : fs[ia[a] * NP1 + q];
+        s += m * src[p * NP + baseIdx + q * strideA];
       }
-      if (stage == D - 1) s *= (T)tab[S::T_FDD + i];
+      if (stage == D - 1) s *= cfd[i];
       dst[p * NP + i] = s;
     }
     __syncthreads();
