@@ -331,6 +331,7 @@ cmg_status upload_all(cmg_problem* P) {
     k.cut_packed = cpk;
     k.dof_node = dn;
     k.tables = tab;
+    k.kcell32 = nullptr;
     int32_t *flow, *cgid, *cfaces, *tiles;
     uint8_t* fdir;
     TRY(upload(own, h.face_lower, &flow));
@@ -460,6 +461,9 @@ cmg_status ensure_fp32(cmg_problem* P) {
     const size_t nl = static_cast<size_t>(std::pow(P->H.cfg.k + 1, P->H.cfg.dim));
     TRY(upload(own, pack_upper<float>(h.cut_mats, nl), &cpk));
     d.kl32.cut_packed = cpk;
+    float* kc32;
+    TRY(upload_f32(own, P->H.tables[l].kcell, &kc32));
+    d.kl32.kcell32 = kc32;
     for (int c = 0; c < 8; ++c) {
       if (d.cut32[c].n_patch == 0) continue;
       float* inv;
@@ -1146,7 +1150,7 @@ size_t hierarchy_bytes(const cmg::Hierarchy& H, int flags) {
            8 * (ncm + nt) + 4 * (h.face_lower.size() + h.cell_gid.size() + h.cell_faces.size() +
            h.tiles.size()) + h.face_dir.size();
     b64 += 8 * (3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
-    b32 += 4 * (ncm + 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
+    b32 += 4 * (ncm + nl * nl + 3 * static_cast<size_t>(h.n_nodes) + h.face_lower.size() * nw_face);
     for (int c = 0; c < 8; ++c) {
       const cmg::CutPatchGroup& g = h.cut[c];
       const size_t ninv = g.inv_off.empty() ? 0 : static_cast<size_t>(g.inv_off.back());

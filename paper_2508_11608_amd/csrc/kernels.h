@@ -23,6 +23,7 @@ struct KLevel {
   int64_t n_cut;             // cut cells
   const int32_t* dof_node;   // lattice node of each DoF, ascending
   const double* tables;      // constant tables (uncut stiffness, 1-D factors, FD, prolongation)
+  const float* kcell32;      // FP32 path: the uncut cell stiffness of the tables rounded to FP32 (else null)
   int64_t n_faces;           // ghost faces
   const int32_t* face_lower; // lower cell of every ghost face
   const uint8_t* face_dir;   // its normal direction
@@ -40,6 +41,12 @@ struct KLevel {
                              // faces on the patch boundary contribute only their closure part), 0 = exact
   template <typename T>
   __host__ __device__ const T* cut_mats_t() const { return static_cast<const T*>(cut_mats); }
+  // the uncut cell stiffness (row-major (k+1)^d x (k+1)^d) in the path's precision
+  template <typename T>
+  __host__ __device__ const T* kcell_t() const {
+    if constexpr (sizeof(T) == 4) return kcell32;
+    else return tables;
+  }
   template <typename T>
   __host__ __device__ const T* cut_packed_t() const { return static_cast<const T*>(cut_packed); }
 };

@@ -307,10 +307,10 @@ __global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ 
       for (int c = 0; c < NCOL; ++c) cell[c] += e * xs[lc][j][c];
     }
   } else {
-    const double* row = L.tables + S::T_KCELL + i * NL;
+    const T* row = L.kcell_t<T>() + S::T_KCELL + i * NL;
 #pragma unroll 4
     for (int j = 0; j < NL; ++j) {
-      const T e = (T)row[j];
+      const T e = row[j];
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) cell[c] += e * xs[lc][j][c];
     }
@@ -344,10 +344,10 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   constexpr int N1 = S::N1, NL = S::NL, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
   constexpr int NCB = 1 << D;
   constexpr int NRW = N1 * (D == 3 ? N1 : 1);
-  __shared__ double tab[S::T_MHAT];  // uncut stiffness
+  __shared__ T tab[S::T_MHAT];  // uncut stiffness, in the path's precision
   __shared__ T xs[A::NR];
   __shared__ int32_t csid[A::NCC];
-  for (int i = threadIdx.x; i < S::T_MHAT; i += blockDim.x) tab[i] = L.tables[i];
+  for (int i = threadIdx.x; i < S::T_MHAT; i += blockDim.x) tab[i] = L.kcell_t<T>()[i];
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   if (b) b += blockIdx.y * L.n_nodes;
   y += blockIdx.y * L.n_nodes;
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
         if (D == 3) iloc += N1 * N1 * il[2];
         int xb = K * c[0] + R1 * K * c[1];
         if (D == 3) xb += R1 * R1 * K * c[2];
-        const double* row = tab + iloc * NL;
+        const T* row = tab + iloc * NL;
         T acc[NRW];
 #pragma unroll
         for (int a = 0; a < NRW; ++a) acc[a] = 0;
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int xi = xb + b0 + R1 * (b12 % N1) + (D == 3 ? R1 * R1 * (b12 / N1) : 0);
-          acc[b12] += (T)row[bq] * xs[xi];
+          acc[b12] += row[bq] * xs[xi];
         }
         T sacc = 0;
 #pragma unroll
@@ -486,9 +486,9 @@ __host__ __device__ constexpr bool tile1d_nz(int s, int j) {
     if (s >= K * c && s <= K * c + K && j >= K * c && j <= K * c + K) return true;
   return false;
 }
-template <int K, int NCELL>
-__device__ __forceinline__ double tile1d(const double* e, int s, int j) {
-  double v = 0;
+template <int K, int NCELL, typename E>
+__device__ __forceinline__ E tile1d(const E* e, int s, int j) {
+  E v = 0;
 #pragma unroll
   for (int c = 0; c < NCELL; ++c)
     if (s >= K * c && s <= K * c + K && j >= K * c && j <= K * c + K) v += e[(s - K * c) * (K + 1) + (j - K * c)];
@@ -496,10 +496,10 @@ __device__ __forceinline__ double tile1d(const double* e, int s, int j) {
 }
 // The same for a run-time row s: the cells holding s are s/K - 1 and s/K when
 // s is a cell boundary, else s/K.
-template <int K, int NCELL>
-__device__ __forceinline__ double tile1d_rt(const double* e, int s, int j) {
+template <int K, int NCELL, typename E>
+__device__ __forceinline__ E tile1d_rt(const E* e, int s, int j) {
   const int c1 = s / K, c0 = s % K == 0 ? c1 - 1 : c1;
-  double v = 0;
+  E v = 0;
   for (int c = c0; c <= c1; ++c)
     if (c >= 0 && c < NCELL && j >= K * c && j <= K * c + K) v += e[(s - K * c) * (K + 1) + (j - K * c)];
   return v;
@@ -523,12 +523,12 @@ __global__ __launch_bounds__(256) void k_apply_sf(KLevel L, const T* __restrict_
   constexpr int NW = D == 3 ? R1 * O1 * O1 : 1;                      // values per second-pass array
   constexpr int NXV = D == 3 ? (A::NR > 2 * NW ? A::NR : 2 * NW) : A::NR;
   constexpr int NU = D == 3 ? R1 * R1 * O1 : R1 * O1;                // values per first-pass array
-  __shared__ double m1[N1 * N1], k1[N1 * N1];
+  __shared__ T m1[N1 * N1], k1[N1 * N1];
   __shared__ T xv[NXV];     // x staged; in 3-D then the second pass: [0, NW) and [NW, 2 NW)
   __shared__ T ua[2][NU];   // first pass: Mhat x and Khat x along the slowest direction
   for (int i = threadIdx.x; i < N1 * N1; i += blockDim.x) {
-    m1[i] = L.tables[S::T_MHAT + i];
-    k1[i] = L.tables[S::T_K1S + i];
+    m1[i] = (T)L.tables[S::T_MHAT + i];
+    k1[i] = (T)L.tables[S::T_K1S + i];
   }
   x += blockIdx.y * L.n_nodes;  // column blockIdx.y
   if (b) b += blockIdx.y * L.n_nodes;
@@ -1314,12 +1314,12 @@ __device__ T cut_patch_ax(const KLevel& L, int nj, const int* V, int node, int* 
           acc[b12] += row[bq] * sm.xs[xi];
         }
       } else {
-        const double* row = L.tables + S::T_KCELL + iloc * NL;
+        const T* row = L.kcell_t<T>() + S::T_KCELL + iloc * NL;
 #pragma unroll
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int xi = xb + b0 + W1 * (b12 % N1) + (D == 3 ? W1 * W1 * (b12 / N1) : 0);
-          acc[b12] += (T)row[bq] * sm.xs[xi];
+          acc[b12] += row[bq] * sm.xs[xi];
         }
       }
 #pragma unroll
@@ -1630,12 +1630,12 @@ __device__ void cut_residual_cols(const KLevel& L, const CutGroupDev& G, int gp,
           for (int c = 0; c < NCOL; ++c) acc[c] += m * sm.xs[q][c];
         }
       } else {
-        const double* row = L.tables + S::T_KCELL + iloc * NL;
+        const T* row = L.kcell_t<T>() + S::T_KCELL + iloc * NL;
 #pragma unroll 8
         for (int bq = 0; bq < NL; ++bq) {
           const int b0 = bq % N1, b12 = bq / N1;
           const int q = qb + b0 + NC1 * (b12 % N1) + (D == 3 ? NC1 * NC1 * (b12 / N1) : 0);
-          const T m = (T)row[bq];
+          const T m = row[bq];
 #pragma unroll
           for (int c = 0; c < NCOL; ++c) acc[c] += m * sm.xs[q][c];
         }
