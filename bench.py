@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="serving run: N seeded requests with Poisson arrivals instead of the solve benchmark")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--group", type=int, default=0, metavar="G",
+                    help="grouped-V-cycle run: G problems of one lattice shape, alone against grouped")
     ap.add_argument("--ghost-sweep", default="", metavar="LEVELS",
                     help="the paper's ghost-parameter study (gamma_1 for Q1, then gamma_2 for Q2, then gamma_3 for Q3 "
                          "over 0.05..0.15) with fractional GMRES counts, for the comma-separated finest levels L")
@@ -144,6 +146,77 @@ def serve(args):
         "all_converged": ok, "saturation_req_per_s": sat_rate,
         "saturation_mean_batch": float(np.mean(sat_batch)), "saturation_max_batch": int(max(sat_batch)),
         "poisson_mean_batch": float(np.mean([r["batch"] for *_, r in out])),
+    }
+
+
+def group_bench(args):
+    """Grouped V-cycles: G problems of one lattice shape (3-D, Q2, 4 levels to
+    32^3 cells; ellipsoids and unions of two from workloads.shape_family), FP32
+    multigrid in FP64 CG to 1e-8 as in the solve server.  The G solves one
+    after another (cmg_solve_multi with one column each, every V-cycle a graph
+    replay) against one grouped solve (cmg_group_solve: every V-cycle step one
+    launch over all G problems); the results must be identical."""
+    import torch
+
+    import workloads as W
+    from paper_2508_11608_amd import Group, Problem
+
+    ws = W.shape_family(args.group, seed=0)
+    ps = [Problem(w) for w in ws]
+    for p in ps:
+        p.set_precision(True)
+    bs = [torch.from_numpy(p.rhs_manufactured()).cuda() for p in ps]
+    g = Group(ps)
+
+    def alone():
+        return [p.solve_multi(b[None, :], rtol=1e-8, maxit=200) for p, b in zip(ps, bs)]
+
+    def grouped():
+        return g.solve(bs, rtol=1e-8, maxit=200)
+
+    def vc_alone():
+        return [p.vcycle_multi(b[None, :]) for p, b in zip(ps, bs)]
+
+    def vc_grouped():
+        return g.vcycle(bs)
+
+    def timed(f, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            out = f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, out
+
+    for _ in range(max(1, args.warmup)):
+        alone()
+        grouped()
+        vc_alone()
+        vc_grouped()
+    t_alone, ra = timed(alone, args.steps)
+    t_group, (xs, infos) = timed(grouped, args.steps)
+    tv_alone, _ = timed(vc_alone, 10 * args.steps)
+    tv_group, _ = timed(vc_grouped, 10 * args.steps)
+    same = all(np.array_equal(x.cpu().numpy(), a[0][0].cpu().numpy()) and i["iterations"] == a[1][0]["iterations"]
+               for x, i, a in zip(xs, infos, ra))
+    nd = [p.ndofs() for p in ps]
+    dofs = sum(n * i["iterations"] for n, i in zip(nd, infos))
+    g.close()
+    for p in ps:
+        p.close()
+    return {
+        "metric": "grouped V-cycles: aggregate DoF/s per CG iteration", "value": dofs / t_group,
+        "unit": "DoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_group * 1e3, "higher_is_better": True, "dtype": "f32 multigrid in f64 CG",
+        "data": "synthetic",
+        "config": {"workload": f"{len(ws)} problems of one lattice shape: 3-D, Q2, 4 levels to 32^3 cells, "
+                               "ellipsoids and unions of two (workloads.shape_family seed 0), manufactured f, "
+                               "rtol 1e-8",
+                   "members": [w.name for w in ws], "n_dofs": nd,
+                   "iterations": [int(i["iterations"]) for i in infos]},
+        "alone_value": dofs / t_alone, "solve_ms_alone": t_alone * 1e3, "solve_ms_grouped": t_group * 1e3,
+        "speedup": t_alone / t_group, "vcycle_ms_alone": tv_alone * 1e3, "vcycle_ms_grouped": tv_group * 1e3,
+        "identical_to_alone": bool(same), "all_converged": all(i["status"] == 0 for i in infos),
     }
 
 
@@ -531,6 +604,10 @@ def main():
     if args.serve:
         torch.cuda.set_device(0)
         print(json.dumps(serve(args)), flush=True)
+        return
+    if args.group:
+        torch.cuda.set_device(0)
+        print(json.dumps(group_bench(args)), flush=True)
         return
     if args.ghost_sweep:
         torch.cuda.set_device(0)

@@ -272,6 +272,40 @@ cmg_status cmg_vcycle_multi(cmg_problem* p, int nrhs, const double* r, double* z
 cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x, double rtol, int maxit,
                            cmg_solve_info* info, void* stream);
 
+/* Grouped V-cycles of several problems (the V-cycle of Section 2.2 for each).
+ * For callers that solve many small problems at once, such as a solve server
+ * (the V-cycle of a small problem is bound by its ~270 kernel launches, not by
+ * memory traffic).  A group holds 1..8 distinct uploaded problems with the same
+ * dimension, degree, level count, coarse mesh, box, V-cycle precision and
+ * device, all with the exact ghost coupling: their levels share one lattice.
+ * cmg_group_create records every member's V-cycle in the form that
+ * cmg_vcycle_multi runs with nrhs = 1 (allocating its multi-column vectors as
+ * that call does) and checks that the members' kernel sequences match step by
+ * step, which holds when every member has cut patches in the same colours on
+ * every level; otherwise it returns CMG_EINVAL and keeps nothing.  It uploads
+ * the members' kernel arguments as one device table.  Each step of the
+ * group's V-cycle is then one launch over all members (blockIdx.z selects the
+ * member), and the grouped V-cycle is replayed from one HIP graph.  A member
+ * stays usable alone, but no other call may run on a member while a call of
+ * its group runs.
+ *
+ * cmg_group_vcycle: z[m] = B_m r[m] for every member m (n_L of that member
+ * entries each, canonical order); bit for bit what
+ * cmg_vcycle_multi(member, 1, r[m], z[m]) returns.
+ * cmg_group_solve: one PCG per member whose V-cycles run grouped; x[m], info[m]
+ * and status[m] (info and status may be NULL) are bit for bit those of
+ * cmg_solve_multi(member, 1, b[m], x[m], rtol, maxit) (for a breakdown or a
+ * non-finite b: that call's status, with x[m] as it left it).  A member that
+ * converged or failed is frozen while the others continue.  Returns CMG_OK
+ * when every member converged, else the status of the first member that did
+ * not. */
+typedef struct cmg_group cmg_group;
+cmg_status cmg_group_create(cmg_problem* const* members, int n, cmg_group** out);
+cmg_status cmg_group_vcycle(cmg_group* g, const double* const* r, double* const* z, void* stream);
+cmg_status cmg_group_solve(cmg_group* g, const double* const* b, double* const* x, double rtol, int maxit,
+                           cmg_solve_info* info, cmg_status* status, void* stream);
+void cmg_group_destroy(cmg_group* g);
+
 /* Kernel timing for measurements.  While kind_mask is non-zero, every kernel
  * launch of a kind whose bit is set is bracketed by HIP events on its stream.
  * Kinds: 0 operator apply / residual, 1 interior colour step, 2 cut colour
@@ -366,10 +400,15 @@ void cmg_destroy(cmg_problem* p);
  * admitted when its exact footprint (cmg_footprint with the multi-column
  * buffers, plus the batch's b and x columns), computed before its set-up,
  * fits into hbm_budget_bytes; one that exceeds the whole budget finishes with
- * status CMG_ENOMEM without being set up.  Batches of different
- * slots overlap on the device.  Every result is independent of what else runs
- * and of the batch it was solved in, bit for bit (the column arithmetic of
- * cmg_solve_multi does not depend on the other columns).  Intended for callers
+ * status CMG_ENOMEM without being set up.  Batches of different slots
+ * overlap on the device.  A batch of one request is joined by the only queued
+ * requests of other resident, idle geometries of the same lattice shape
+ * (dimension, degree, levels, coarse mesh, box, precision, rtol, maxit), up to
+ * 8 problems, and solved by one grouped PCG (cmg_group_solve); a group stays
+ * cached while its members are resident.  Every result is independent of what
+ * else runs and of the batch or group it was solved in, bit for bit (the
+ * column arithmetic of cmg_solve_multi does not depend on the other columns,
+ * and a grouped solve equals each member's one-column solve).  Intended for callers
  * that submit many solves of differing geometries, degrees and depths. */
 typedef struct cmg_server cmg_server;
 
@@ -391,6 +430,7 @@ typedef struct {
   int cache_hit;           /* 1 when the hierarchy was already resident */
   double t_submit, t_start, t_admitted, t_solve_start, t_done;  /* seconds since server creation */
   int batch;               /* number of requests solved together with this one (itself included) */
+  int group;               /* problems whose V-cycles ran grouped with this one's (itself included); 1: none */
 } cmg_result;
 
 cmg_status cmg_server_create(size_t hbm_budget_bytes, int max_slots, cmg_server** out);

@@ -5,6 +5,6 @@ multiplicative vertex-patch smoother, transfers, coarse solve, V-cycle, CG)
 runs in hand-written HIP kernels behind the C ABI of include/cutmg.h; this
 package is its thin Python binding.
 """
-from .cutmg import EXPORTED, LIBRARY_PATH, CutmgError, Problem, Server, footprint, load_library
+from .cutmg import EXPORTED, LIBRARY_PATH, CutmgError, Group, Problem, Server, footprint, load_library
 
-__all__ = ["Problem", "Server", "CutmgError", "footprint", "load_library", "LIBRARY_PATH", "EXPORTED"]
+__all__ = ["Problem", "Group", "Server", "CutmgError", "footprint", "load_library", "LIBRARY_PATH", "EXPORTED"]

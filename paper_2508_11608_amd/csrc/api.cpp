@@ -586,6 +586,7 @@ struct KTimer {
   hipStream_t s;
   hipEvent_t b = nullptr;
   KTimer(cmg_problem* P_, int kind, int level, hipStream_t s_) : P(P_), s(s_) {
+    if (cmg::launch_recording()) return;  // nothing is launched
     const bool timed = (P->timing_mask & (1u << kind)) && (P->timing_level < 0 || level == P->timing_level);
     cmg_problem::Capture& c = P->cap;
     if (c.on) {
@@ -645,7 +646,8 @@ cmg_status colour_step(cmg_problem* P, int l, bool interior, int colour, hipStre
   DevLevel& D = P->lv[l];
   Vecs<T>& v = work<T>(D, multi);
   if (interior) {
-    if (D.n_int[colour] == 0) return CMG_OK;
+    // recorded also without patches, so that one lattice shape records one sequence
+    if (D.n_int[colour] == 0 && !cmg::launch_recording()) return CMG_OK;
     KTimer t(P, kInterior, l, s);
     HIP_TRY(cmg::launch_interior_step<T>(d, k, kl<T>(D), D.int_verts[colour], D.n_int[colour], v.x, v.b, s, ncol,
                                          P->launch));
@@ -837,21 +839,32 @@ cmg_status dot(cmg_problem* P, const double* x, const double* y, int64_t n, hipS
   return CMG_OK;
 }
 
-// Column-wise dot products of ncol columns of n entries (multi-column buffers).
-cmg_status dot_cols(cmg_problem* P, const double* x, const double* y, int64_t n, int ncol, hipStream_t s,
-                    double* out) {
+// Column-wise dot products of ncol columns of n entries (multi-column
+// buffers): the partial sums and their copy to the host are queued on s, and
+// dot_cols_sum adds them up once s has reached that point.
+cmg_status dot_cols_start(cmg_problem* P, const double* x, const double* y, int64_t n, int ncol, hipStream_t s) {
   {
     KTimer t(P, kVector, P->H.cfg.n_levels - 1, s);
     HIP_TRY(cmg::launch_dot_partial(x, y, n, P->mpart, P->nblk, s, ncol));
   }
   HIP_TRY(hipMemcpyAsync(P->mpart_host, P->mpart, static_cast<size_t>(ncol) * P->nblk * sizeof(double),
                          hipMemcpyDeviceToHost, s));
-  TRY(wait_stream(P, s));
+  return CMG_OK;
+}
+
+void dot_cols_sum(const cmg_problem* P, int ncol, double* out) {
   for (int c = 0; c < ncol; ++c) {
     double acc = 0.0;
     for (int i = 0; i < P->nblk; ++i) acc += P->mpart_host[c * P->nblk + i];
     out[c] = acc;
   }
+}
+
+cmg_status dot_cols(cmg_problem* P, const double* x, const double* y, int64_t n, int ncol, hipStream_t s,
+                    double* out) {
+  TRY(dot_cols_start(P, x, y, n, ncol, s));
+  TRY(wait_stream(P, s));
+  dot_cols_sum(P, ncol, out);
   return CMG_OK;
 }
 
@@ -1152,6 +1165,153 @@ size_t hierarchy_bytes(const cmg::Hierarchy& H, int flags) {
   b32 += 4 * n0sq;
   m64 += 8 * 4 * C * nL + 8 * C * 1024;
   return b64 + (fp32 ? b32 : 0) + (multi ? m64 + (fp32 ? m32 : 0) : 0);
+}
+
+}  // namespace
+
+// Grouped V-cycles: the same V-cycle step of every member as one launch.
+struct cmg_group {
+  std::vector<cmg_problem*> m;
+  bool fp32 = false;
+  struct Step {
+    const void* fn;  // grouped kernel
+    dim3 grid;       // largest member grid, z = members
+    dim3 block;
+    size_t off;      // the members' argument records in tab
+  };
+  std::vector<Step> steps;
+  unsigned char* tab = nullptr;  // device: argument records, one array per step
+  bool use_graph = true;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_ev = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxGroup = 8;
+
+void group_release(cmg_group* g) {
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+  if (g->tab || g->exec) (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->cap_ev) (void)hipEventDestroy(g->cap_ev);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->tab) (void)hipFree(g->tab);
+  g->exec = nullptr;
+  g->cap_ev = nullptr;
+  g->cap_stream = nullptr;
+  g->tab = nullptr;
+}
+
+// Records every member's lattice V-cycle (the multi-column form with one
+// column), checks that the members' launch sequences match step by step and
+// uploads the argument records.
+template <typename T>
+cmg_status group_plan(cmg_group* g) {
+  const size_t G = g->m.size();
+  std::vector<std::vector<cmg::LaunchRecord>> rec(G);
+  for (size_t i = 0; i < G; ++i) {
+    cmg::set_launch_recorder(&rec[i]);
+    const cmg_status st = vcycle_lattice<T>(g->m[i], nullptr, 1, true);
+    cmg::set_launch_recorder(nullptr);
+    TRY(st);
+  }
+  const size_t ns = rec[0].size();
+  size_t bytes = 0;
+  for (size_t i = 1; i < G; ++i)
+    if (rec[i].size() != ns)
+      return fail(CMG_EINVAL, "group members differ in their V-cycle steps (member " + std::to_string(i) + ")");
+  for (size_t j = 0; j < ns; ++j) {
+    const cmg::LaunchRecord& r0 = rec[0][j];
+    cmg_group::Step st{r0.fn, dim3(0, 0, static_cast<unsigned>(G)), dim3(r0.block), bytes};
+    for (size_t i = 0; i < G; ++i) {
+      const cmg::LaunchRecord& r = rec[i][j];
+      if (!r.fn || r.fn != r0.fn || r.block != r0.block || r.args.size() != r0.args.size())
+        return fail(CMG_EINVAL, "group members differ in V-cycle step " + std::to_string(j) + " (member " +
+                                    std::to_string(i) + ")");
+      st.grid.x = std::max(st.grid.x, r.grid[0]);
+      st.grid.y = std::max(st.grid.y, r.grid[1]);
+    }
+    g->steps.push_back(st);
+    bytes += (G * r0.args.size() + 255) / 256 * 256;
+  }
+  std::vector<unsigned char> host(bytes);
+  for (size_t j = 0; j < ns; ++j)
+    for (size_t i = 0; i < G; ++i) {
+      const std::vector<unsigned char>& a = rec[i][j].args;
+      std::memcpy(host.data() + g->steps[j].off + i * a.size(), a.data(), a.size());
+    }
+  std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+  HIP_TRY(hipMalloc(&g->tab, bytes));
+  HIP_TRY(hipMemcpy(g->tab, host.data(), bytes, hipMemcpyHostToDevice));
+  return settle();
+}
+
+hipError_t group_launch(cmg_group* g, hipStream_t s) {
+  for (const cmg_group::Step& st : g->steps) {
+    void* a = g->tab + st.off;
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchKernel(st.fn, st.grid, st.block, args, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The grouped lattice V-cycle, replayed from a graph captured at its first run
+// (launched step by step if the capture fails).
+cmg_status group_lattice(cmg_group* g, hipStream_t s) {
+  if (g->use_graph && !g->exec) {
+    std::lock_guard<std::recursive_mutex> lock(cmg::device_mutex());
+    if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    if (!g->cap_ev) HIP_TRY(hipEventCreateWithFlags(&g->cap_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(g->cap_ev, s));
+    HIP_TRY(hipStreamWaitEvent(g->cap_stream, g->cap_ev, 0));
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      ok = group_launch(g, g->cap_stream) == hipSuccess;
+      ok = hipStreamEndCapture(g->cap_stream, &graph) == hipSuccess && ok && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      // nothing of the capture ran: launch step by step from now on
+      g->exec = nullptr;
+      g->use_graph = false;
+      (void)hipGetLastError();
+    }
+    HIP_TRY(hipEventRecord(g->cap_ev, g->cap_stream));
+    HIP_TRY(hipStreamWaitEvent(s, g->cap_ev, 0));
+  }
+  if (g->exec) {
+    HIP_TRY(hipGraphLaunch(g->exec, s));
+  } else {
+    HIP_TRY(group_launch(g, s));
+  }
+  return CMG_OK;
+}
+
+// z[m] = B_m r[m] for every member, in the precision of the group: the steps of
+// op_vcycle_multi with one column, the lattice V-cycle grouped.
+template <typename T>
+cmg_status group_vcycle_t(cmg_group* g, const double* const* r, double* const* z, hipStream_t s) {
+  for (size_t i = 0; i < g->m.size(); ++i) {
+    cmg_problem* p = g->m[i];
+    const int L = p->H.cfg.n_levels - 1;
+    TRY(scatter<T>(p, L, r[i], mvecs<T>(p->lv[L]).b, s, 1));
+  }
+  TRY(group_lattice(g, s));
+  for (size_t i = 0; i < g->m.size(); ++i) {
+    cmg_problem* p = g->m[i];
+    const int L = p->H.cfg.n_levels - 1;
+    TRY(gather<T>(p, L, mvecs<T>(p->lv[L]).x, z[i], s, 1));
+  }
+  return CMG_OK;
+}
+
+cmg_status group_vcycle(cmg_group* g, const double* const* r, double* const* z, hipStream_t s) {
+  return g->fp32 ? group_vcycle_t<float>(g, r, z, s) : group_vcycle_t<double>(g, r, z, s);
 }
 
 }  // namespace
@@ -1782,6 +1942,180 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
     }
   }
   return fail(CMG_ENOTCONV, "CG did not converge within maxit for every column");
+}
+
+cmg_status cmg_group_create(cmg_problem* const* members, int n, cmg_group** out) {
+  if (!out || !members || n < 1 || n > kMaxGroup) return fail(CMG_EINVAL, "bad group arguments (1..8 members)");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    TRY(check_device(members[i]));
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) return fail(CMG_EINVAL, "a problem appears twice in the group");
+  }
+  const cmg_problem* p0 = members[0];
+  for (int i = 1; i < n; ++i) {
+    const cmg_problem* p = members[i];
+    const cmg::Config &a = p0->H.cfg, &b = p->H.cfg;
+    if (a.dim != b.dim || a.k != b.k || a.n_levels != b.n_levels || a.coarse_cells != b.coarse_cells ||
+        a.lo != b.lo || a.hi != b.hi || p->fp32 != p0->fp32 || p->device != p0->device)
+      return fail(CMG_EINVAL, "group members differ in dimension, degree, levels, coarse mesh, box, precision or "
+                              "device");
+  }
+  for (int i = 0; i < n; ++i) {
+    if (members[i]->ghost_local) return fail(CMG_EINVAL, "group members run with the exact ghost coupling only");
+    TRY(prepare_multi(members[i]));
+  }
+  auto* g = new cmg_group();
+  g->m.assign(members, members + n);
+  g->fp32 = p0->fp32;
+  for (int i = 0; i < n; ++i) g->use_graph = g->use_graph && members[i]->use_graphs;
+  const cmg_status st = g->fp32 ? group_plan<float>(g) : group_plan<double>(g);
+  if (st != CMG_OK) {
+    group_release(g);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return CMG_OK;
+}
+
+void cmg_group_destroy(cmg_group* g) {
+  if (!g) return;
+  group_release(g);
+  delete g;
+}
+
+cmg_status cmg_group_vcycle(cmg_group* g, const double* const* r, double* const* z, void* stream) {
+  if (!g || !r || !z) return fail(CMG_EINVAL, "null argument");
+  for (size_t i = 0; i < g->m.size(); ++i)
+    if (!r[i] || !z[i]) return fail(CMG_EINVAL, "null member vector");
+  return group_vcycle(g, r, z, static_cast<hipStream_t>(stream));
+}
+
+cmg_status cmg_group_solve(cmg_group* g, const double* const* b, double* const* x, double rtol, int maxit,
+                           cmg_solve_info* info, cmg_status* status, void* stream) {
+  if (!g || !b || !x || !(rtol > 0.0) || maxit < 1) return fail(CMG_EINVAL, "bad group solve arguments");
+  const int G = static_cast<int>(g->m.size());
+  for (int i = 0; i < G; ++i)
+    if (!b[i] || !x[i]) return fail(CMG_EINVAL, "null member vector");
+  auto s = static_cast<hipStream_t>(stream);
+  // every member runs the recurrence of cmg_solve_multi with one column, on
+  // its own multi-column Krylov vectors; a member that converged or failed is
+  // frozen while the others continue
+  std::vector<int64_t> n(G);
+  std::vector<double> nb(G), rz(G);
+  std::vector<cmg_status> st(G, CMG_OK);
+  std::vector<bool> done(G, false);
+  std::vector<const double*> R(G);
+  std::vector<double*> Zw(G);
+  std::string msg;
+  auto stop = [&](int i, cmg_status code, const char* what) {
+    st[i] = code;
+    done[i] = true;
+    if (msg.empty()) msg = std::string(what) + " (member " + std::to_string(i) + ")";
+  };
+  for (int i = 0; i < G; ++i) {
+    cmg_problem* p = g->m[i];
+    const int L = p->H.cfg.n_levels - 1;
+    n[i] = p->H.levels[L].n_dofs;
+    if (info) info[i] = cmg_solve_info{0, 0.0, 0.0};
+    R[i] = p->mkr;
+    Zw[i] = p->mkz;
+    KTimer t(p, kVector, L, s);
+    HIP_TRY(cmg::launch_fill(n[i], 0.0, x[i], s));     // x = 0
+    HIP_TRY(cmg::launch_copy(n[i], b[i], p->mkr, s));  // r = b
+  }
+  // the dot products of all members are queued together and summed after one
+  // wait (the same partial sums and the same host sums as dot_cols)
+  auto dots = [&](const std::vector<int>& who, auto&& vecs, std::vector<double>& out) -> cmg_status {
+    for (int i : who) {
+      const std::pair<const double*, const double*> v = vecs(i);
+      TRY(dot_cols_start(g->m[i], v.first, v.second, n[i], 1, s));
+    }
+    if (!who.empty()) TRY(wait_stream(g->m[who.front()], s));
+    for (int i : who) dot_cols_sum(g->m[i], 1, &out[i]);
+    return CMG_OK;
+  };
+  auto active = [&]() {
+    std::vector<int> a;
+    for (int i = 0; i < G; ++i)
+      if (!done[i]) a.push_back(i);
+    return a;
+  };
+  std::vector<double> tmp(G, 0.0);
+  std::vector<int> all(G);
+  for (int i = 0; i < G; ++i) all[i] = i;
+  TRY(dots(all, [&](int i) { return std::make_pair(b[i], b[i]); }, tmp));
+  bool all_done = true;
+  for (int i = 0; i < G; ++i) {
+    nb[i] = std::sqrt(tmp[i]);
+    if (!std::isfinite(nb[i])) stop(i, CMG_EINVAL, "right-hand side is not finite");
+    else done[i] = nb[i] == 0.0;
+    all_done = all_done && done[i];
+  }
+  if (!all_done) {
+    TRY(group_vcycle(g, R.data(), Zw.data(), s));
+    const std::vector<int> a = active();
+    for (int i : a) {
+      cmg_problem* p = g->m[i];
+      KTimer t(p, kVector, p->H.cfg.n_levels - 1, s);
+      HIP_TRY(cmg::launch_copy(n[i], p->mkz, p->mkp, s));  // p = z
+    }
+    TRY(dots(a, [&](int i) { return std::pair<const double*, const double*>(g->m[i]->mkr, g->m[i]->mkz); },
+             rz));
+  }
+  for (int it = 1; it <= maxit && !all_done; ++it) {
+    std::vector<int> a = active();
+    for (int i : a) TRY(op_apply_multi(g->m[i], 1, g->m[i]->mkp, g->m[i]->mkq, s));  // q = A p in FP64
+    TRY(dots(a, [&](int i) { return std::pair<const double*, const double*>(g->m[i]->mkp, g->m[i]->mkq); },
+             tmp));
+    std::vector<int> upd;
+    for (int i : a) {
+      if (!(tmp[i] > 0.0) || !std::isfinite(tmp[i])) {
+        stop(i, CMG_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+        continue;
+      }
+      cmg_problem* p = g->m[i];
+      cmg::ColCoef alpha{}, malpha{};
+      alpha.v[0] = rz[i] / tmp[i];
+      malpha.v[0] = -alpha.v[0];
+      KTimer t(p, kVector, p->H.cfg.n_levels - 1, s);
+      HIP_TRY(cmg::launch_axpy_cols(n[i], alpha, p->mkp, x[i], 1, s));
+      HIP_TRY(cmg::launch_axpy_cols(n[i], malpha, p->mkq, p->mkr, 1, s));
+      upd.push_back(i);
+    }
+    TRY(dots(upd, [&](int i) { return std::pair<const double*, const double*>(g->m[i]->mkr, g->m[i]->mkr); },
+             tmp));
+    for (int i : upd) {
+      const double rel = std::sqrt(tmp[i]) / nb[i];
+      if (info) {
+        info[i].iterations = it;
+        info[i].rel_residual = rel;
+        info[i].n_frac = rel > 0.0 ? it * std::log10(rtol) / std::log10(rel) : it;
+      }
+      done[i] = rel <= rtol;
+    }
+    a = active();
+    if (a.empty()) break;
+    TRY(group_vcycle(g, R.data(), Zw.data(), s));
+    TRY(dots(a, [&](int i) { return std::pair<const double*, const double*>(g->m[i]->mkr, g->m[i]->mkz); },
+             tmp));
+    for (int i : a) {
+      cmg_problem* p = g->m[i];
+      cmg::ColCoef beta{};
+      beta.v[0] = tmp[i] / rz[i];
+      rz[i] = tmp[i];
+      KTimer t(p, kVector, p->H.cfg.n_levels - 1, s);
+      HIP_TRY(cmg::launch_xpay_cols(n[i], beta, p->mkz, p->mkp, 1, s));
+    }
+  }
+  for (int i = 0; i < G; ++i)
+    if (!done[i]) stop(i, CMG_ENOTCONV, "CG did not converge within maxit");
+  if (status)
+    for (int i = 0; i < G; ++i) status[i] = st[i];
+  for (int i = 0; i < G; ++i)
+    if (st[i] != CMG_OK) return fail(st[i], msg);
+  return CMG_OK;
 }
 
 cmg_status cmg_timing(cmg_problem* p, unsigned kind_mask) {

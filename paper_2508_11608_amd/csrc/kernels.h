@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <vector>
 
 #include <cstdint>
 
@@ -101,6 +102,24 @@ struct RowCoef {
 };
 
 int tables_size(int d, int k);
+
+// Grouped launches.  While a recorder is set on the calling thread, the
+// multigrid launchers below append their launches to it instead of issuing
+// them: the grouped form of the kernel (one launch over several problems,
+// blockIdx.z selecting the problem's argument record in a device table), the
+// block grid and block size of this problem's launch and its argument record.
+// Launches without a grouped form append an empty record (fn == nullptr).
+// While recording, the operator pre-passes, interior colour steps and zero
+// fills are recorded also where they have no work, so that problems of one
+// lattice shape record the same sequence of kernels.
+struct LaunchRecord {
+  const void* fn = nullptr;
+  unsigned grid[2] = {0, 0};
+  unsigned block = 0;
+  std::vector<unsigned char> args;
+};
+void set_launch_recorder(std::vector<LaunchRecord>* rec);  // nullptr: launch again
+bool launch_recording();
 
 // Every multigrid launcher works on ncol columns at once (blockIdx.y = column):
 // lattice vectors of a level are ncol blocks of KLevel::n_nodes entries, the

@@ -83,6 +83,16 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return xc < r ? xc * (q + 1) + s : r * (q + 1) + (xc - r) * q + s;
 }
 
+// Grouped launch: one launch runs the same kernel for several problems, the
+// problem's argument record being entry blockIdx.z of a device table.  The
+// grid is the largest of the members' grids, so every kernel with a grouped
+// form lets the blocks beyond its own work return (grid-stride loops, index
+// bounds, or a patch index past the colour's patches).
+template <int LB, typename A>
+__global__ __launch_bounds__(LB) void k_grouped(const A* __restrict__ tab) {
+  tab[blockIdx.z].run();
+}
+
 __device__ __forceinline__ int64_t lat(int D, int nn, const int* I) {
   return D == 2 ? I[0] + (int64_t)nn * I[1] : I[0] + (int64_t)nn * (I[1] + (int64_t)nn * I[2]);
 }
@@ -104,7 +114,7 @@ __device__ void load_tables(const double* __restrict__ g, double* s, int n) {
 // One thread per face and column: the 2 (k+1) nodes along the normal at each
 // tangential node are read once for all k orders.
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ x, T* __restrict__ W) {
+__device__ __forceinline__ void face_w_body(KLevel L, const T* __restrict__ x, T* __restrict__ W) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1;
   constexpr int NT = Pow<N1, D - 1>::v;
@@ -189,6 +199,20 @@ __global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ 
   }
 }
 
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_face_w(KLevel L, const T* __restrict__ x, T* __restrict__ W) {
+  face_w_body<D, K, T>(L, x, W);
+}
+
+// argument record of k_face_w for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct FaceWArgs {
+  KLevel L;
+  const T* x;
+  T* W;
+  __device__ void run() const { face_w_body<D, K, T>(L, x, W); }
+};
+
 // Special-cell pre-pass of the operator.  A special cell T is cut or has a
 // ghost face; for each of them and every column it forms the contribution of T
 // to the rows of its nodes,
@@ -207,8 +231,8 @@ struct CellShape {
 };
 
 template <int D, int K, typename T, int NCOL>
-__global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ x, const T* __restrict__ W,
-                                                T* __restrict__ C, int ncol) {
+__device__ __forceinline__ void cell_ax_body(KLevel L, const T* __restrict__ x, const T* __restrict__ W,
+                                             T* __restrict__ C, int ncol) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, CPB = CellShape<D, K>::CPB, NF = 2 * D;
   constexpr int NT = Pow<N1, D - 1>::v;
@@ -320,6 +344,23 @@ __global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ 
     if (c < ncol) C[c * L.n_spec * NL + t * NL + i] = cell[c] + acc[c];
 }
 
+template <int D, int K, typename T, int NCOL>
+__global__ __launch_bounds__(64) void k_cell_ax(KLevel L, const T* __restrict__ x, const T* __restrict__ W,
+                                                T* __restrict__ C, int ncol) {
+  cell_ax_body<D, K, T, NCOL>(L, x, W, C, ncol);
+}
+
+// argument record of k_cell_ax for grouped launches (k_grouped)
+template <int D, int K, typename T, int NCOL>
+struct CellAxArgs {
+  KLevel L;
+  const T* x;
+  const T* W;
+  T* C;
+  int ncol;
+  __device__ void run() const { cell_ax_body<D, K, T, NCOL>(L, x, W, C, ncol); }
+};
+
 template <int D, int K>
 struct ApplyShape {
   static constexpr int B = (D == 3 && K == 3) ? 2 : 4;   // cells per tile and direction
@@ -337,8 +378,8 @@ struct ApplyShape {
 // (from LDS) or the special-cell value of the pre-pass (from C).  The C loads
 // of a node's cells are independent and issued together before the LDS rows.
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, const T* __restrict__ C) {
+__device__ __forceinline__ void apply_body(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
+                                           T* __restrict__ y, const T* __restrict__ C) {
   using S = Shape<D, K>;
   using A = ApplyShape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
@@ -476,6 +517,23 @@ __global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x
   }
 }
 
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_apply(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y, const T* __restrict__ C) {
+  apply_body<D, K, T>(L, x, b, y, C);
+}
+
+// argument record of k_apply for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct ApplyArgs {
+  KLevel L;
+  const T* x;
+  const T* b;
+  T* y;
+  const T* C;
+  __device__ void run() const { apply_body<D, K, T>(L, x, b, y, C); }
+};
+
 // Entry (r, j) of a 1-D matrix assembled on the 2k+1 closure nodes of a patch
 // from the element matrix e ((k+1) x (k+1), row-major) of its two cells, the
 // second cell starting at node k.  patch1d_nz tells whether some cell holds
@@ -501,8 +559,8 @@ __device__ __forceinline__ E patch1d_rt(const E* e, int r, int j) {
 
 // Fused colour step over interior patches.
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* __restrict__ verts, int nv,
-                                                       T* __restrict__ x, const T* __restrict__ b) {
+__device__ __forceinline__ void interior_step_body(KLevel L, const int32_t* __restrict__ verts, int nv,
+                                                   T* __restrict__ x, const T* __restrict__ b) {
   using S = Shape<D, K>;
   constexpr int NP = S::NP, NP1 = S::NP1, NC = S::NC, NC1 = S::NC1, PPB = S::PPB, N1 = S::N1, NL = S::NL;
   // the level tables this kernel reads, in the precision of the path: 1-D mass,
@@ -717,6 +775,23 @@ __global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* 
   if (active) x[node] = xs[p][pi[0] + NC1 * pi[1] + (D == 3 ? NC1 * NC1 * pi[2] : 0)] + src[p * NP + i];
   }
 }
+
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_interior_step(KLevel L, const int32_t* __restrict__ verts, int nv,
+                                                       T* __restrict__ x, const T* __restrict__ b) {
+  interior_step_body<D, K, T>(L, verts, nv, x, b);
+}
+
+// argument record of k_interior_step for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct InteriorStepArgs {
+  KLevel L;
+  const int32_t* verts;
+  int nv;
+  T* x;
+  const T* b;
+  __device__ void run() const { interior_step_body<D, K, T>(L, verts, nv, x, b); }
+};
 
 // Sizes of the cut-patch kernels (one block per patch).
 template <int D, int K>
@@ -1556,17 +1631,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // it is read once for all columns.  Row blocks of 16 are spread over the
 // block's wavefronts.
 template <int D, int K>
-__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KLevel L, CutGroupDev G,
-                                                                             const float* __restrict__ x,
-                                                                             const float* __restrict__ b,
-                                                                             const float* __restrict__ W,
-                                                                             float* __restrict__ dbuf, int ncol) {
+__device__ __forceinline__ void cut_solve_mfma_body(KLevel L, CutGroupDev G, const float* __restrict__ x,
+                                                    const float* __restrict__ b, const float* __restrict__ W,
+                                                    float* __restrict__ dbuf, int ncol) {
   using S = Shape<D, K>;
   constexpr int NPK = (S::NP + 3) / 4 * 4;
   __shared__ PairSmem<D, K, float, kMaxCols> sm;
   __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
   const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = xcd_block(blockIdx.x, gridDim.x);
+  if (gp >= G.n_patch) return;  // grouped launches: a block beyond this problem's patches
   for (int e = tid; e < NPK * kMaxCols; e += nth) (&rs[0][0])[e] = 0.f;
   int off, nj;
   cut_residual_cols<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
@@ -1600,6 +1674,28 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
   }
 }
 
+template <int D, int K>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KLevel L, CutGroupDev G,
+                                                                              const float* __restrict__ x,
+                                                                              const float* __restrict__ b,
+                                                                              const float* __restrict__ W,
+                                                                              float* __restrict__ dbuf, int ncol) {
+  cut_solve_mfma_body<D, K>(L, G, x, b, W, dbuf, ncol);
+}
+
+// argument record of k_cut_solve_mfma for grouped launches (k_grouped)
+template <int D, int K>
+struct CutSolveMfmaArgs {
+  KLevel L;
+  CutGroupDev G;
+  const float* x;
+  const float* b;
+  const float* W;
+  float* dbuf;
+  int ncol;
+  __device__ void run() const { cut_solve_mfma_body<D, K>(L, G, x, b, W, dbuf, ncol); }
+};
+
 // Cut patches, phase 1 for up to kMaxCols columns in FP64: residuals of all
 // columns by cut_residual_cols (every cell row read once for all columns),
 // then d = A_j^{-1} r for all columns with the inverse read once: thread i
@@ -1607,11 +1703,9 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_mfma(KL
 // into every column's accumulator.  Column c's arithmetic (residual, then the
 // row sum in increasing j) does not depend on the other columns.
 template <int D, int K>
-__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_cols(KLevel L, CutGroupDev G,
-                                                                             const double* __restrict__ x,
-                                                                             const double* __restrict__ b,
-                                                                             const double* __restrict__ W,
-                                                                             double* __restrict__ dbuf, int ncol) {
+__device__ __forceinline__ void cut_solve_cols_body(KLevel L, CutGroupDev G, const double* __restrict__ x,
+                                                    const double* __restrict__ b, const double* __restrict__ W,
+                                                    double* __restrict__ dbuf, int ncol) {
   using S = Shape<D, K>;
   constexpr int NB = 8;                        // independent inverse loads in flight per thread
   constexpr int NPB = (S::NP + NB - 1) / NB * NB;
@@ -1619,6 +1713,7 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_cols(KL
   __shared__ double rs[NPB][kMaxCols];         // rows >= nj and columns >= ncol stay zero
   const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = xcd_block(blockIdx.x, gridDim.x);
+  if (gp >= G.n_patch) return;  // grouped launches: a block beyond this problem's patches
   for (int e = tid; e < NPB * kMaxCols; e += nth) (&rs[0][0])[e] = 0.0;
   int off, nj;
   cut_residual_cols<D, K, double, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
@@ -1643,6 +1738,28 @@ __global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_cols(KL
   }
 }
 
+template <int D, int K>
+__global__ __launch_bounds__((CutShape<D, K>::THREADS)) void k_cut_solve_cols(KLevel L, CutGroupDev G,
+                                                                              const double* __restrict__ x,
+                                                                              const double* __restrict__ b,
+                                                                              const double* __restrict__ W,
+                                                                              double* __restrict__ dbuf, int ncol) {
+  cut_solve_cols_body<D, K>(L, G, x, b, W, dbuf, ncol);
+}
+
+// argument record of k_cut_solve_cols for grouped launches (k_grouped)
+template <int D, int K>
+struct CutSolveColsArgs {
+  KLevel L;
+  CutGroupDev G;
+  const double* x;
+  const double* b;
+  const double* W;
+  double* dbuf;
+  int ncol;
+  __device__ void run() const { cut_solve_cols_body<D, K>(L, G, x, b, W, dbuf, ncol); }
+};
+
 // dst = src on a node list (the cut region before a run of two-buffer cut steps).
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy_nodes(const int32_t* __restrict__ nodes, int64_t n,
@@ -1656,16 +1773,32 @@ __global__ __launch_bounds__(256) void k_copy_nodes(const int32_t* __restrict__ 
 
 // Cut patches, phase 2: x[I_j] += d_j for all patches of the colour.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cut_update(const int32_t* __restrict__ nodes, int64_t n,
-                                                    const T* __restrict__ dbuf, T* __restrict__ x, int64_t ldx) {
+__device__ __forceinline__ void cut_update_body(const int32_t* __restrict__ nodes, int64_t n,
+                                                const T* __restrict__ dbuf, T* __restrict__ x, int64_t ldx) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e < n) x[blockIdx.y * ldx + nodes[e]] += dbuf[blockIdx.y * n + e];
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_cut_update(const int32_t* __restrict__ nodes, int64_t n,
+                                                    const T* __restrict__ dbuf, T* __restrict__ x, int64_t ldx) {
+  cut_update_body<T>(nodes, n, dbuf, x, ldx);
+}
+
+// argument record of k_cut_update for grouped launches (k_grouped)
+template <typename T>
+struct CutUpdateArgs {
+  const int32_t* nodes;
+  int64_t n;
+  const T* dbuf;
+  T* x;
+  int64_t ldx;
+  __device__ void run() const { cut_update_body<T>(nodes, n, dbuf, x, ldx); }
+};
+
 // x_f[I] += sum_J P(I, J) x_c[J] for every active fine node (embedding).
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const T* __restrict__ xc,
-                                                     T* __restrict__ xf) {
+__device__ __forceinline__ void prolong_add_body(KLevel Lc, KLevel Lf, const T* __restrict__ xc, T* __restrict__ xf) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1;
   __shared__ double p1d[S::NC1 * N1];
@@ -1716,6 +1849,22 @@ __global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const
   xf[node] += acc;
 }
 
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(KLevel Lc, KLevel Lf, const T* __restrict__ xc,
+                                                     T* __restrict__ xf) {
+  prolong_add_body<D, K, T>(Lc, Lf, xc, xf);
+}
+
+// argument record of k_prolong_add for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct ProlongAddArgs {
+  KLevel Lc;
+  KLevel Lf;
+  const T* xc;
+  T* xf;
+  __device__ void run() const { prolong_add_body<D, K, T>(Lc, Lf, xc, xf); }
+};
+
 // b_c[J] = sum_I P(I, J) r_f[I] for every active coarse node (transpose).  In
 // every direction the fine nodes with a non-zero weight form one contiguous
 // range: [2J-2k+1, 2J+2k-1] around a coarse vertex, [2kC+1, 2kC+2k-1] inside a
@@ -1734,8 +1883,7 @@ __device__ __forceinline__ double restrict_weight(const double* p1d, int J, int 
 }
 
 template <int D, int K, typename T>
-__global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T* __restrict__ rf,
-                                                  T* __restrict__ bc) {
+__device__ __forceinline__ void restrict_body(KLevel Lc, KLevel Lf, const T* __restrict__ rf, T* __restrict__ bc) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1;
   __shared__ double p1d[S::NC1 * N1];
@@ -1811,10 +1959,26 @@ __global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T*
   bc[node] = acc;
 }
 
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_restrict(KLevel Lc, KLevel Lf, const T* __restrict__ rf,
+                                                  T* __restrict__ bc) {
+  restrict_body<D, K, T>(Lc, Lf, rf, bc);
+}
+
+// argument record of k_restrict for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct RestrictArgs {
+  KLevel Lc;
+  KLevel Lf;
+  const T* rf;
+  T* bc;
+  __device__ void run() const { restrict_body<D, K, T>(Lc, Lf, rf, bc); }
+};
+
 // x_0 = A_0^{-1} b_0 on the coarsest level: one 64-wide wavefront per row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const int32_t* __restrict__ dof_node,
-                                                int n0, const T* __restrict__ b, T* __restrict__ x, int64_t ld) {
+__device__ __forceinline__ void coarse_body(const T* __restrict__ inv, const int32_t* __restrict__ dof_node, int n0,
+                                            const T* __restrict__ b, T* __restrict__ x, int64_t ld) {
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (row >= n0) return;
@@ -1828,11 +1992,45 @@ __global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_zero_active(const int32_t* __restrict__ dof_node, int64_t n, T* __restrict__ x,
-                                                     int64_t ld) {
+__global__ __launch_bounds__(256) void k_coarse(const T* __restrict__ inv, const int32_t* __restrict__ dof_node,
+                                                int n0, const T* __restrict__ b, T* __restrict__ x, int64_t ld) {
+  coarse_body<T>(inv, dof_node, n0, b, x, ld);
+}
+
+// argument record of k_coarse for grouped launches (k_grouped)
+template <typename T>
+struct CoarseArgs {
+  const T* inv;
+  const int32_t* dof_node;
+  int n0;
+  const T* b;
+  T* x;
+  int64_t ld;
+  __device__ void run() const { coarse_body<T>(inv, dof_node, n0, b, x, ld); }
+};
+
+template <typename T>
+__device__ __forceinline__ void zero_active_body(const int32_t* __restrict__ dof_node, int64_t n, T* __restrict__ x,
+                                                 int64_t ld) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[blockIdx.y * ld + dof_node[i]] = 0;
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_active(const int32_t* __restrict__ dof_node, int64_t n,
+                                                     T* __restrict__ x, int64_t ld) {
+  zero_active_body<T>(dof_node, n, x, ld);
+}
+
+// argument record of k_zero_active for grouped launches (k_grouped)
+template <typename T>
+struct ZeroActiveArgs {
+  const int32_t* dof_node;
+  int64_t n;
+  T* x;
+  int64_t ld;
+  __device__ void run() const { zero_active_body<T>(dof_node, n, x, ld); }
+};
 
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ dof_node, int64_t n,
@@ -1856,6 +2054,31 @@ namespace {
 
 inline unsigned blocks(int64_t n, int b = 256) { return static_cast<unsigned>((n + b - 1) / b); }
 
+// Launch recorder of the calling thread (see set_launch_recorder).
+thread_local std::vector<LaunchRecord>* t_rec = nullptr;
+
+// While recording: append the grouped form of a launch and return true.
+template <int LB, typename A>
+bool record(dim3 g, dim3 b, const A& a) {
+  if (!t_rec) return false;
+  LaunchRecord r;
+  r.fn = reinterpret_cast<const void*>(&dev::k_grouped<LB, A>);
+  r.grid[0] = g.x;
+  r.grid[1] = g.y;
+  r.block = b.x;
+  r.args.assign(reinterpret_cast<const unsigned char*>(&a), reinterpret_cast<const unsigned char*>(&a) + sizeof(A));
+  t_rec->push_back(std::move(r));
+  return true;
+}
+
+// While recording, a launch without a grouped form leaves an empty record
+// (the group that recorded it cannot be formed).
+bool record_none() {
+  if (!t_rec) return false;
+  t_rec->push_back(LaunchRecord{});
+  return true;
+}
+
 // The defaults of LaunchPolicy: a grid cap of 256 CUs x 8 resident 256-thread
 // blocks for the grid-stride kernels that stage level tables in LDS (every
 // block loads the tables once), and larger blocks for cut-patch launches of
@@ -1874,6 +2097,9 @@ hipError_t dispatch(int d, int k, F&& f) {
 
 }  // namespace
 
+void set_launch_recorder(std::vector<LaunchRecord>* rec) { t_rec = rec; }
+bool launch_recording() { return t_rec != nullptr; }
+
 int tables_size(int d, int k) {
   int n = -1;
   (void)dispatch(d, k, [&](auto D, auto K) {
@@ -1888,23 +2114,30 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
                         int ncol, const LaunchPolicy& lp) {
   if (L.n_dofs == 0) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
-    if (L.n_faces > 0) {
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s, L, x,
-                         W);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+    // while recording, the pre-passes are recorded also where they have no
+    // work, so that the launch sequence does not depend on the geometry
+    if (L.n_faces > 0 || t_rec) {
+      const dim3 g(std::max(1u, blocks(L.n_faces)), ncol);
+      if (!record<256>(g, dim3(256), dev::FaceWArgs<D.value, K.value, T>{L, x, W})) {
+        hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, T>), g, dim3(256), 0, s, L, x, W);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
     }
-    if (L.n_spec > 0) {
+    if (L.n_spec > 0 || t_rec) {
       constexpr int CPB = dev::CellShape<D.value, K.value>::CPB;
-      const dim3 g(static_cast<unsigned>((L.n_spec + CPB - 1) / CPB));
-      if (ncol == 1)
-        hipLaunchKernelGGL((dev::k_cell_ax<D.value, K.value, T, 1>), g, dim3(64), 0, s, L, x, W, C, 1);
-      else
+      const dim3 g(std::max(1u, static_cast<unsigned>((L.n_spec + CPB - 1) / CPB)));
+      if (ncol == 1) {
+        if (!record<64>(g, dim3(64), dev::CellAxArgs<D.value, K.value, T, 1>{L, x, W, C, 1}))
+          hipLaunchKernelGGL((dev::k_cell_ax<D.value, K.value, T, 1>), g, dim3(64), 0, s, L, x, W, C, 1);
+      } else if (!record<64>(g, dim3(64), dev::CellAxArgs<D.value, K.value, T, kMaxCols>{L, x, W, C, ncol})) {
         hipLaunchKernelGGL((dev::k_cell_ax<D.value, K.value, T, kMaxCols>), g, dim3(64), 0, s, L, x, W, C, ncol);
+      }
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     const unsigned nb = std::max(1u, std::min<unsigned>(static_cast<unsigned>(L.n_tiles), lp.max_blocks / ncol + 1));
+    if (record<256>(dim3(nb, ncol), dim3(256), dev::ApplyArgs<D.value, K.value, T>{L, x, b, y, C})) return hipSuccess;
     hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, C);
     return hipGetLastError();
   });
@@ -1913,10 +2146,12 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
 template <typename T>
 hipError_t launch_interior_step(int d, int k, const KLevel& L, const int32_t* verts, int nv, T* x, const T* b,
                                 hipStream_t s, int ncol, const LaunchPolicy& lp) {
-  if (nv == 0) return hipSuccess;
+  if (nv == 0 && !t_rec) return hipSuccess;  // recorded also without work (see launch_apply)
   return dispatch(d, k, [&](auto D, auto K) {
     constexpr int PPB = dev::Shape<D.value, K.value>::PPB;
     const unsigned nb = std::max(1u, std::min<unsigned>(blocks(nv, PPB), lp.max_blocks / ncol + 1));
+    if (record<256>(dim3(nb, ncol), dim3(256), dev::InteriorStepArgs<D.value, K.value, T>{L, verts, nv, x, b}))
+      return hipSuccess;
     hipLaunchKernelGGL((dev::k_interior_step<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, verts, nv,
                        x, b);
     return hipGetLastError();
@@ -1927,6 +2162,7 @@ template <typename T>
 hipError_t launch_cut_solve(int d, int k, const KLevel& L, const CutGroupDev& G, const T* x, const T* b, T* dbuf,
                             hipStream_t s, int ncol, T* xb, const CopyJob& cj, const LaunchPolicy& lp) {
   if (G.n_patch == 0) return hipSuccess;
+  if (record_none()) return hipSuccess;
   return dispatch(d, k, [&](auto D, auto K) {
     using C = dev::CutShape<D.value, K.value>;
     if (xb == nullptr && cj.n != 0) return hipErrorInvalidValue;  // a copy job needs the second buffer
@@ -1962,6 +2198,7 @@ template <typename T>
 hipError_t launch_copy_nodes(const int32_t* nodes, int64_t n, const T* src, T* dst, int64_t ld, hipStream_t s,
                              int ncol) {
   if (n == 0) return hipSuccess;
+  if (record_none()) return hipSuccess;
   hipLaunchKernelGGL((dev::k_copy_nodes<T>), dim3(blocks(n), ncol), dim3(256), 0, s, nodes, n, src, dst, ld);
   return hipGetLastError();
 }
@@ -1971,13 +2208,17 @@ hipError_t launch_cut_solve_mfma(int d, int k, const KLevel& L, const CutGroupDe
   if (G.n_patch == 0) return hipSuccess;
   if (!G.inv_tiles || !G.tile_off || ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
   return dispatch(d, k, [&](auto D, auto K) {
-    if (L.n_faces > 0) {  // ghost-face jumps of the current x, all columns
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, float>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s,
-                         L, x, W);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+    if (L.n_faces > 0 || t_rec) {  // ghost-face jumps of the current x, all columns
+      const dim3 g(std::max(1u, blocks(L.n_faces)), ncol);
+      if (!record<256>(g, dim3(256), dev::FaceWArgs<D.value, K.value, float>{L, x, W})) {
+        hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, float>), g, dim3(256), 0, s, L, x, W);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
     }
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+    if (record<TH>(dim3(G.n_patch), dim3(TH), dev::CutSolveMfmaArgs<D.value, K.value>{L, G, x, b, W, dbuf, ncol}))
+      return hipSuccess;
     hipLaunchKernelGGL((dev::k_cut_solve_mfma<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, W,
                        dbuf, ncol);
     return hipGetLastError();
@@ -1989,13 +2230,17 @@ hipError_t launch_cut_solve_cols(int d, int k, const KLevel& L, const CutGroupDe
   if (G.n_patch == 0) return hipSuccess;
   if (ncol < 1 || ncol > kMaxCols) return hipErrorInvalidValue;
   return dispatch(d, k, [&](auto D, auto K) {
-    if (L.n_faces > 0) {  // ghost-face jumps of the current x, all columns
-      hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, double>), dim3(blocks(L.n_faces), ncol), dim3(256), 0, s,
-                         L, x, W);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+    if (L.n_faces > 0 || t_rec) {  // ghost-face jumps of the current x, all columns
+      const dim3 g(std::max(1u, blocks(L.n_faces)), ncol);
+      if (!record<256>(g, dim3(256), dev::FaceWArgs<D.value, K.value, double>{L, x, W})) {
+        hipLaunchKernelGGL((dev::k_face_w<D.value, K.value, double>), g, dim3(256), 0, s, L, x, W);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
     }
     constexpr int TH = dev::CutShape<D.value, K.value>::THREADS;
+    if (record<TH>(dim3(G.n_patch), dim3(TH), dev::CutSolveColsArgs<D.value, K.value>{L, G, x, b, W, dbuf, ncol}))
+      return hipSuccess;
     hipLaunchKernelGGL((dev::k_cut_solve_cols<D.value, K.value>), dim3(G.n_patch), dim3(TH), 0, s, L, G, x, b, W,
                        dbuf, ncol);
     return hipGetLastError();
@@ -2005,6 +2250,8 @@ hipError_t launch_cut_solve_cols(int d, int k, const KLevel& L, const CutGroupDe
 template <typename T>
 hipError_t launch_cut_update(const CutGroupDev& G, const T* dbuf, T* x, int64_t ldx, hipStream_t s, int ncol) {
   if (G.n_nodes == 0) return hipSuccess;
+  if (record<256>(dim3(blocks(G.n_nodes), ncol), dim3(256), dev::CutUpdateArgs<T>{G.nodes, G.n_nodes, dbuf, x, ldx}))
+    return hipSuccess;
   hipLaunchKernelGGL((dev::k_cut_update<T>), dim3(blocks(G.n_nodes), ncol), dim3(256), 0, s, G.nodes, G.n_nodes, dbuf,
                      x, ldx);
   return hipGetLastError();
@@ -2014,6 +2261,8 @@ template <typename T>
 hipError_t launch_prolong_add(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* xc, T* xf, hipStream_t s,
                               int ncol) {
   return dispatch(d, k, [&](auto D, auto K) {
+    if (record<256>(dim3(blocks(Lf.n_dofs), ncol), dim3(256), dev::ProlongAddArgs<D.value, K.value, T>{Lc, Lf, xc, xf}))
+      return hipSuccess;
     hipLaunchKernelGGL((dev::k_prolong_add<D.value, K.value, T>), dim3(blocks(Lf.n_dofs), ncol), dim3(256), 0, s, Lc,
                        Lf, xc, xf);
     return hipGetLastError();
@@ -2024,6 +2273,8 @@ template <typename T>
 hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, const T* rf, T* bc, hipStream_t s,
                            int ncol) {
   return dispatch(d, k, [&](auto D, auto K) {
+    if (record<256>(dim3(blocks(Lc.n_dofs), ncol), dim3(256), dev::RestrictArgs<D.value, K.value, T>{Lc, Lf, rf, bc}))
+      return hipSuccess;
     hipLaunchKernelGGL((dev::k_restrict<D.value, K.value, T>), dim3(blocks(Lc.n_dofs), ncol), dim3(256), 0, s, Lc,
                        Lf, rf, bc);
     return hipGetLastError();
@@ -2033,13 +2284,16 @@ hipError_t launch_restrict(int d, int k, const KLevel& Lc, const KLevel& Lf, con
 template <typename T>
 hipError_t launch_coarse(const T* inv, const int32_t* dof_node, int n0, const T* b, T* x, int64_t ld, hipStream_t s,
                          int ncol) {
+  if (record<256>(dim3(blocks(n0, 4), ncol), dim3(256), dev::CoarseArgs<T>{inv, dof_node, n0, b, x, ld})) return hipSuccess;
   hipLaunchKernelGGL((dev::k_coarse<T>), dim3(blocks(n0, 4), ncol), dim3(256), 0, s, inv, dof_node, n0, b, x, ld);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_zero_active(const int32_t* dof_node, int64_t n, T* x, int64_t ld, hipStream_t s, int ncol) {
-  if (n == 0) return hipSuccess;
+  if (n == 0 && !t_rec) return hipSuccess;
+  if (record<256>(dim3(std::max(1u, blocks(n)), ncol), dim3(256), dev::ZeroActiveArgs<T>{dof_node, n, x, ld}))
+    return hipSuccess;
   hipLaunchKernelGGL((dev::k_zero_active<T>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, x, ld);
   return hipGetLastError();
 }
@@ -2048,6 +2302,7 @@ template <typename TS, typename TD>
 hipError_t launch_scatter(const int32_t* dof_node, int64_t n, const TS* src, TD* lat, int64_t ld, hipStream_t s,
                           int ncol) {
   if (n == 0) return hipSuccess;
+  if (record_none()) return hipSuccess;
   hipLaunchKernelGGL((dev::k_scatter<TS, TD>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, src, lat, ld);
   return hipGetLastError();
 }
@@ -2056,6 +2311,7 @@ template <typename TS, typename TD>
 hipError_t launch_gather(const int32_t* dof_node, int64_t n, const TS* lat, TD* dst, int64_t ld, hipStream_t s,
                          int ncol) {
   if (n == 0) return hipSuccess;
+  if (record_none()) return hipSuccess;
   hipLaunchKernelGGL((dev::k_gather<TS, TD>), dim3(blocks(n), ncol), dim3(256), 0, s, dof_node, n, lat, dst, ld);
   return hipGetLastError();
 }

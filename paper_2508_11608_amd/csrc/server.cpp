@@ -13,9 +13,15 @@
 // budget is refused with CMG_ENOMEM before its set-up.  The batch is solved by one multi-column PCG on the slot's
 // stream: every V-cycle launch carries all requests of the batch, requests
 // that arrive while others run join the next batch, and batches of different
-// slots overlap on the device.  The column arithmetic of the multi-column
-// solve does not depend on the other columns, so a result is the same alone
-// and in any batch or mix.
+// slots overlap on the device.  A batch of one request is joined by single
+// queued requests of other geometries with the same lattice shape (dimension,
+// degree, levels, coarse mesh, box, precision, tolerance and iteration limit)
+// whose hierarchies are resident and idle, up to 8 problems: they are solved
+// by one grouped PCG (cmg_group_solve), whose V-cycle steps are one launch over
+// all of them; groups stay cached while their members are resident.  The
+// column arithmetic of the multi-column solve does not depend on the other
+// columns, and a grouped solve equals the one-column solve of each member, so
+// a result is the same alone and in any batch, group or mix.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -30,6 +36,7 @@
 #include <set>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/cutmg.h"
@@ -38,6 +45,7 @@
 namespace {
 
 constexpr size_t kBatch = 8;  // requests per multi-column solve (cmg_solve_multi takes up to 8 columns)
+constexpr size_t kGroup = 8;  // problems per grouped solve (cmg_group_create takes up to 8)
 
 struct OwnedRequest {
   uint64_t ticket = 0;
@@ -73,6 +81,21 @@ struct OwnedRequest {
     put_i(q.quad_n);
     put_i(q.precond_fp32);
     for (double g : q.gamma_m) put_d(g);
+    return k;
+  }
+  // requests of different geometries that can share one grouped solve
+  std::string shape_key() const {
+    std::string k;
+    auto put = [&k](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    put(&dim, sizeof dim);
+    put(&box_lo, sizeof box_lo);
+    put(&box_hi, sizeof box_hi);
+    put(&params.k, sizeof params.k);
+    put(&params.n_levels, sizeof params.n_levels);
+    put(&params.coarse_cells, sizeof params.coarse_cells);
+    put(&params.precond_fp32, sizeof params.precond_fp32);
+    put(&rtol, sizeof rtol);
+    put(&maxit, sizeof maxit);
     return k;
   }
   // requests that can share one multi-column solve
@@ -112,6 +135,10 @@ void free_entry(Entry& e) {
 }  // namespace
 
 struct cmg_server {
+  struct CachedGroup {
+    std::vector<std::string> keys;  // the members' hierarchy keys, in member order
+    cmg_group* g = nullptr;
+  };
   size_t budget = 0;
   int device = 0;
   std::chrono::steady_clock::time_point t0;
@@ -121,6 +148,7 @@ struct cmg_server {
   std::map<uint64_t, Done> done;
   std::list<Entry> cache;
   std::set<std::string> pending;  // hierarchies being set up
+  std::map<std::string, CachedGroup> groups;  // by the members' keys, concatenated in member order
   size_t used = 0;
   uint64_t next_ticket = 1, use_clock = 0;
   bool stop = false;
@@ -200,7 +228,20 @@ cmg_status acquire(cmg_server* S, const OwnedRequest& rq, Entry** out, cmg_resul
         S->used -= victim->bytes;
         Entry dead = *victim;
         S->cache.erase(victim);
+        // its cached groups go with it (none is in use: that needs every member)
+        std::vector<cmg_group*> gone;
+        for (auto it = S->groups.begin(); it != S->groups.end();) {
+          bool has = false;
+          for (const std::string& k : it->second.keys) has = has || k == dead.key;
+          if (has) {
+            gone.push_back(it->second.g);
+            it = S->groups.erase(it);
+          } else {
+            ++it;
+          }
+        }
         lk.unlock();
+        for (cmg_group* g : gone) cmg_group_destroy(g);
         free_entry(dead);
         lk.lock();
         continue;
@@ -250,6 +291,168 @@ void release(cmg_server* S, Entry* e) {
   S->cv.notify_all();
 }
 
+// Right-hand side of one request into bc (n entries) on the worker's stream:
+// Fourier loads on the device (the hierarchy's quadrature plan is built at its
+// first use and then accounted in the memory in use), the manufactured load on
+// the host.
+cmg_status load_rhs(cmg_server* S, Entry* e, const OwnedRequest& q, double* bc, int64_t n, hipStream_t stream) {
+  if (!q.kappa.empty()) {
+    size_t before = 0, after = 0;
+    cmg_device_bytes(e->p, 7, &before);
+    const cmg_status st = cmg_rhs_fourier_device(e->p, static_cast<int>(q.amp.size()), q.kappa.data(),
+                                                 q.amp.data(), q.phase.data(), bc, stream);
+    cmg_device_bytes(e->p, 7, &after);
+    if (after > before) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->used += after - before;
+      e->bytes += after - before;
+    }
+    return st;
+  }
+  std::vector<double> B(static_cast<size_t>(n));
+  cmg_status st = cmg_rhs_manufactured(e->p, B.data());
+  if (st == CMG_OK &&
+      (hipMemcpyAsync(bc, B.data(), B.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
+       hipStreamSynchronize(stream) != hipSuccess))
+    st = CMG_EHIP;
+  return st;
+}
+
+// Partners of a single request rq whose hierarchy the caller holds: the only
+// queued request of each other geometry of rq's lattice shape whose hierarchy
+// is resident and idle (taken from the queue, the hierarchy held from here),
+// up to kGroup problems in all.  Never waits for a hierarchy.
+void take_partners(cmg_server* S, const OwnedRequest& rq, std::vector<OwnedRequest>& partners,
+                   std::vector<Entry*>& pe) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  const std::string sk = rq.shape_key();
+  std::unordered_map<std::string, int> count;
+  for (const OwnedRequest& q : S->queue)
+    if (q.shape_key() == sk) ++count[q.key()];
+  std::set<std::string> taken{rq.key()};
+  for (auto it = S->queue.begin(); it != S->queue.end() && partners.size() + 1 < kGroup;) {
+    Entry* hit = nullptr;
+    if (it->shape_key() == sk) {
+      const std::string key = it->key();
+      if (count[key] == 1 && !taken.count(key) && !S->pending.count(key))
+        for (Entry& e : S->cache)
+          if (e.key == key && !e.in_use) hit = &e;
+    }
+    if (!hit) {
+      ++it;
+      continue;
+    }
+    hit->in_use = true;
+    hit->last_use = ++S->use_clock;
+    taken.insert(hit->key);
+    pe.push_back(hit);
+    partners.push_back(std::move(*it));
+    it = S->queue.erase(it);
+  }
+}
+
+// A single request rq (its hierarchy e0 held, res0 its admission record) with
+// partners of other geometries of its lattice shape (their hierarchies pe
+// held): one grouped PCG, or one-column solves one after another if the group
+// cannot be formed (the members' cut colours differ); the results are the
+// same either way.  Releases every hierarchy and finishes every request.
+void solve_group(cmg_server* S, OwnedRequest& rq, Entry* e0, const cmg_result& res0,
+                 std::vector<OwnedRequest>& partners, std::vector<Entry*>& pe, hipStream_t stream) {
+  const int G = 1 + static_cast<int>(partners.size());
+  std::vector<OwnedRequest*> req(G);
+  req[0] = &rq;
+  for (int i = 1; i < G; ++i) req[i] = &partners[i - 1];
+  std::vector<cmg_result> res(G);
+  const double t_start = S->now();
+  for (int i = 0; i < G; ++i) {
+    res[i] = cmg_result{};
+    res[i].t_submit = req[i]->t_submit;
+    res[i].t_start = i == 0 ? res0.t_start : t_start;
+    res[i].t_admitted = i == 0 ? res0.t_admitted : t_start;
+    res[i].cache_hit = i == 0 ? res0.cache_hit : 1;
+    res[i].batch = 1;
+    res[i].group = 1;
+  }
+  std::vector<Entry*> ent(G, nullptr);
+  std::vector<cmg_status> st(G, CMG_OK);
+  std::vector<int64_t> n(G, 0);
+  std::vector<cmg_solve_info> info(G, cmg_solve_info{0, 0.0, 0.0});
+  std::vector<std::vector<double>> X(G);
+  ent[0] = e0;
+  for (int i = 1; i < G; ++i) ent[i] = pe[i - 1];
+  for (int i = 0; i < G; ++i) {
+    if (!ent[i]) continue;
+    cmg_ndofs(ent[i]->p, req[i]->params.n_levels - 1, &n[i]);
+    st[i] = load_rhs(S, ent[i], *req[i], ent[i]->db, n[i], stream);
+  }
+  // the members that reach the solve
+  std::vector<int> m;
+  for (int i = 0; i < G; ++i)
+    if (ent[i] && st[i] == CMG_OK) m.push_back(i);
+  const double t_solve = S->now();
+  for (int i = 0; i < G; ++i) res[i].t_solve_start = t_solve;
+  cmg_group* g = nullptr;
+  std::string gk;
+  if (m.size() > 1) {
+    for (int i : m) gk += ent[i]->key;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->groups.find(gk);
+    if (it != S->groups.end()) g = it->second.g;
+  }
+  if (m.size() > 1 && !g) {
+    std::vector<cmg_problem*> ps;
+    cmg_server::CachedGroup cg;
+    for (int i : m) {
+      ps.push_back(ent[i]->p);
+      cg.keys.push_back(ent[i]->key);
+    }
+    if (cmg_group_create(ps.data(), static_cast<int>(ps.size()), &g) == CMG_OK) {
+      cg.g = g;
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->groups[gk] = cg;
+    } else {
+      g = nullptr;
+    }
+  }
+  if (g) {
+    std::vector<const double*> b;
+    std::vector<double*> x;
+    std::vector<cmg_solve_info> gi(m.size());
+    std::vector<cmg_status> gs(m.size(), CMG_OK);
+    for (int i : m) {
+      b.push_back(ent[i]->db);
+      x.push_back(ent[i]->dx);
+    }
+    (void)cmg_group_solve(g, b.data(), x.data(), rq.rtol, rq.maxit, gi.data(), gs.data(), stream);
+    for (size_t j = 0; j < m.size(); ++j) {
+      st[m[j]] = gs[j];
+      info[m[j]] = gi[j];
+      res[m[j]].group = static_cast<int>(m.size());
+    }
+  } else {
+    for (int i : m) st[i] = cmg_solve_multi(ent[i]->p, 1, ent[i]->db, ent[i]->dx, rq.rtol, rq.maxit, &info[i], stream);
+  }
+  for (int i : m) {
+    if (st[i] != CMG_OK && st[i] != CMG_ENOTCONV) continue;
+    X[i].resize(static_cast<size_t>(n[i]));
+    if (hipMemcpyAsync(X[i].data(), ent[i]->dx, X[i].size() * sizeof(double), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      st[i] = CMG_EHIP;
+  }
+  for (int i = 0; i < G; ++i)
+    if (ent[i]) release(S, ent[i]);
+  for (int i = 0; i < G; ++i) {
+    if (st[i] != CMG_OK && st[i] != CMG_ENOTCONV && st[i] != CMG_ENOMEM)
+      std::fprintf(stderr, "cutmg server: request of a group of %d failed with status %d: %s\n", G,
+                   static_cast<int>(st[i]), cmg_last_error());
+    res[i].n_dofs = n[i];
+    res[i].info = info[i];
+    res[i].status = st[i];
+    finish(S, *req[i], res[i], std::move(X[i]));
+  }
+}
+
 void worker(cmg_server* S) {
   (void)hipSetDevice(S->device);
   hipStream_t stream = nullptr;
@@ -281,9 +484,21 @@ void worker(cmg_server* S) {
       res[c].t_submit = batch[c].t_submit;
       res[c].t_start = t_start;
       res[c].batch = nb;
+      res[c].group = 1;
     }
     Entry* e = nullptr;
     cmg_status st = acquire(S, rq, &e, res[0]);
+    if (nb == 1 && st == CMG_OK) {
+      // partners, taken only once the head's hierarchy is held and only if
+      // idle (never waited for), so that two slots never wait on each other
+      std::vector<OwnedRequest> partners;
+      std::vector<Entry*> pe;
+      take_partners(S, rq, partners, pe);
+      if (!partners.empty()) {
+        solve_group(S, batch[0], e, res[0], partners, pe, stream);
+        continue;
+      }
+    }
     for (int c = 1; c < nb; ++c) {
       res[c].cache_hit = res[0].cache_hit;
       res[c].t_admitted = res[0].t_admitted;
@@ -296,33 +511,8 @@ void worker(cmg_server* S) {
       const size_t bytes = static_cast<size_t>(n) * nb * sizeof(double);
       double* db = e->db;
       double* dx = e->dx;
-      // Fourier loads are assembled on the device, on the worker's stream (the
-      // hierarchy's quadrature plan is built on its first use and then
-      // accounted in the memory in use); the manufactured load on the host
-      std::vector<double> B;
-      for (int c = 0; c < nb && st == CMG_OK; ++c) {
-        const OwnedRequest& q = batch[c];
-        double* bc = db + static_cast<size_t>(c) * n;
-        if (!q.kappa.empty()) {
-          size_t before = 0, after = 0;
-          cmg_device_bytes(e->p, 7, &before);
-          st = cmg_rhs_fourier_device(e->p, static_cast<int>(q.amp.size()), q.kappa.data(), q.amp.data(),
-                                      q.phase.data(), bc, stream);
-          cmg_device_bytes(e->p, 7, &after);
-          if (after > before) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->used += after - before;
-            e->bytes += after - before;
-          }
-          continue;
-        }
-        B.resize(static_cast<size_t>(n));
-        st = cmg_rhs_manufactured(e->p, B.data());
-        if (st == CMG_OK &&
-            (hipMemcpyAsync(bc, B.data(), B.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
-             hipStreamSynchronize(stream) != hipSuccess))
-          st = CMG_EHIP;
-      }
+      for (int c = 0; c < nb && st == CMG_OK; ++c)
+        st = load_rhs(S, e, batch[c], db + static_cast<size_t>(c) * n, n, stream);
       const double t_solve = S->now();
       for (int c = 0; c < nb; ++c) res[c].t_solve_start = t_solve;
       if (st == CMG_OK) st = cmg_solve_multi(e->p, nb, db, dx, rq.rtol, rq.maxit, info.data(), stream);
@@ -418,6 +608,7 @@ void cmg_server_destroy(cmg_server* S) {
     S->cv.notify_all();
   }
   for (std::thread& t : S->workers) t.join();
+  for (auto& kv : S->groups) cmg_group_destroy(kv.second.g);
   for (Entry& e : S->cache) free_entry(e);
   delete S;
 }

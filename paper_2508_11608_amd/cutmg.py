@@ -53,7 +53,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("n_dofs", ctypes.c_int64), ("info", SolveInfo), ("cache_hit", ctypes.c_int),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_admitted", ctypes.c_double),
-                ("t_solve_start", ctypes.c_double), ("t_done", ctypes.c_double), ("batch", ctypes.c_int)]
+                ("t_solve_start", ctypes.c_double), ("t_done", ctypes.c_double), ("batch", ctypes.c_int),
+                ("group", ctypes.c_int)]
 
 
 EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cmg_apply", "cmg_colour_step", "cmg_smooth",
@@ -61,7 +62,8 @@ EXPORTED = ["cmg_setup", "cmg_setup_host", "cmg_set_precision", "cmg_ndofs", "cm
             "cmg_export", "cmg_timing", "cmg_timing_read", "cmg_destroy", "cmg_last_error", "cmg_upload",
             "cmg_device_bytes", "cmg_server_create", "cmg_submit", "cmg_poll", "cmg_server_destroy",
             "cmg_vcycle_multi", "cmg_solve_multi", "cmg_gmres", "cmg_vcycle_solve", "cmg_footprint",
-            "cmg_set_launch", "cmg_set_ghost_coupling", "cmg_apply_noalloc", "cmg_rhs_fourier_device", "cmg_set_graphs"]
+            "cmg_set_launch", "cmg_set_ghost_coupling", "cmg_apply_noalloc", "cmg_rhs_fourier_device", "cmg_set_graphs",
+            "cmg_group_create", "cmg_group_vcycle", "cmg_group_solve", "cmg_group_destroy"]
 
 _lib = None
 
@@ -109,6 +111,10 @@ def load_library():
         "cmg_set_launch": [P, I, I],
         "cmg_set_ghost_coupling": [P, I],
         "cmg_set_graphs": [P, I],
+        "cmg_group_create": [ctypes.POINTER(P), I, ctypes.POINTER(P)],
+        "cmg_group_vcycle": [P, ctypes.POINTER(V), ctypes.POINTER(V), V],
+        "cmg_group_solve": [P, ctypes.POINTER(V), ctypes.POINTER(V), D, I, ctypes.POINTER(SolveInfo),
+                            ctypes.POINTER(ctypes.c_int), V],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -118,6 +124,8 @@ def load_library():
     lib.cmg_destroy.restype = None
     lib.cmg_server_destroy.argtypes = [P]
     lib.cmg_server_destroy.restype = None
+    lib.cmg_group_destroy.argtypes = [P]
+    lib.cmg_group_destroy.restype = None
     lib.cmg_last_error.argtypes = []
     lib.cmg_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -390,6 +398,56 @@ class Problem:
         return dict(zip(keys, (int(t) for t in v)))
 
 
+class Group:
+    """Grouped V-cycles of several problems of one lattice shape (cmg_group_*)."""
+
+    def __init__(self, problems):
+        load_library()
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p._h for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(_lib.cmg_group_create(arr, len(self.problems), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cmg_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts):
+        if len(ts) != len(self.problems):
+            raise ValueError("one vector per member")
+        return (ctypes.c_void_p * len(ts))(*[_dev(t, p.ndofs(None)).value for t, p in zip(ts, self.problems)])
+
+    def vcycle(self, rs, zs=None):
+        """zs[m] = B_m rs[m] for every member."""
+        import torch
+
+        zs = [torch.empty_like(r) for r in rs] if zs is None else zs
+        _check(_lib.cmg_group_vcycle(self._h, self._ptrs(rs), self._ptrs(zs), _stream()))
+        return zs
+
+    def solve(self, bs, xs=None, rtol=1e-8, maxit=200, raise_on_fail=True):
+        """One PCG per member with grouped V-cycles; returns the solutions and one info dict per member."""
+        import torch
+
+        xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+        g = len(self.problems)
+        info = (SolveInfo * g)()
+        status = (ctypes.c_int * g)()
+        st = _lib.cmg_group_solve(self._h, self._ptrs(bs), self._ptrs(xs), rtol, maxit, info, status, _stream())
+        if raise_on_fail:
+            _check(st)
+        return xs, [{"iterations": i.iterations, "rel_residual": i.rel_residual, "n_frac": i.n_frac, "status": s}
+                    for i, s in zip(info, status)]
+
+
 def footprint(workload, fp32: bool = False, multi: bool = False, quad_n: int = 14):
     """(device bytes, finest-level DoFs) of the problem cmg_setup would build,
     from counts only (cmg_footprint); host only."""
@@ -469,7 +527,8 @@ class Server:
         out = {"status": res.status, "n_dofs": res.n_dofs, "iterations": res.info.iterations,
                "rel_residual": res.info.rel_residual, "cache_hit": bool(res.cache_hit),
                "t_submit": res.t_submit, "t_start": res.t_start, "t_admitted": res.t_admitted,
-               "t_solve_start": res.t_solve_start, "t_done": res.t_done, "batch": res.batch}
+               "t_solve_start": res.t_solve_start, "t_done": res.t_done, "batch": res.batch,
+               "group": res.group}
         return out, x
 
     def close(self):

@@ -1,0 +1,138 @@
+"""Grouped V-cycles (cmg_group_*): several problems of one lattice shape whose
+V-cycle steps run as one launch each, through the C ABI.
+
+Every member's grouped V-cycle and grouped PCG must equal, bit for bit, what the
+member gives alone in the same form (cmg_vcycle_multi / cmg_solve_multi with one
+column); the members differ in geometry, so their cut patches, special cells,
+ghost faces and operator tiles differ, and every grouped launch runs blocks
+beyond some member's work.  One member's grouped V-cycle is also compared with
+the oracle.  Every case prints its name first so that a failing GPU run can be
+located."""
+import numpy as np
+import pytest
+
+import oracle_cache
+import workloads as W
+
+try:  # import at collection time: the first import on a fresh machine is slow
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = {
+    "2d-Q2-N32": [W.disc_q2(), W.offcentre_disc(2, 4), W.ellipse(2, 4), W.disc_union(2, 4)],
+    "3d-Q2-N16": [W.ball_q2().with_levels(3), W.offcentre_ball(2, 3), W.ball_union(2, 3)],
+    "3d-Q3-N16": [W.offcentre_ball(3, 3), W.ball_union(3, 3)],
+}
+TOL_VCYCLE = 1e-10
+
+
+def _cuda(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module", params=list(GROUPS), ids=list(GROUPS))
+def group(request):
+    import torch
+    from paper_2508_11608_amd import Problem
+
+    ws = GROUPS[request.param]
+    print(f"\n[group] {request.param}: " + ", ".join(w.name for w in ws), flush=True)
+    ps = [Problem(w) for w in ws]
+    yield request.param, ws, ps
+    for p in ps:
+        p.close()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_group_vcycle_equals_member_alone(group, fp32):
+    from paper_2508_11608_amd import Group
+
+    name, ws, ps = group
+    print(f"  [case] {name} vcycle fp32={fp32}", flush=True)
+    for p in ps:
+        p.set_precision(fp32)
+    g = Group(ps)
+    try:
+        # three grouped V-cycles in a row: the first captures the graph, the
+        # others replay it, with the members' own calls in between
+        for rep in range(3):
+            rs = [_cuda(W.random_vector(p.ndofs(), seed=900 + 10 * rep + i)) for i, p in enumerate(ps)]
+            zs = [z.cpu().numpy() for z in g.vcycle(rs)]
+            for i, p in enumerate(ps):
+                alone = p.vcycle_multi(rs[i][None, :])[0].cpu().numpy()
+                assert np.array_equal(zs[i], alone), (rep, ws[i].name)
+    finally:
+        g.close()
+        for p in ps:
+            p.set_precision(False)
+
+
+def test_group_vcycle_matches_oracle(group):
+    from paper_2508_11608_amd import Group
+
+    name, ws, ps = group
+    print(f"  [case] {name} vcycle vs oracle", flush=True)
+    g = Group(ps)
+    try:
+        rs = [W.random_vector(p.ndofs(), seed=950 + i) for i, p in enumerate(ps)]
+        zs = [z.cpu().numpy() for z in g.vcycle([_cuda(r) for r in rs])]
+    finally:
+        g.close()
+    # the smallest member (the oracle's cut-cell rule is slow on unions)
+    i = min(range(len(ps)), key=lambda j: ps[j].ndofs())
+    H = oracle_cache.build(ws[i])[3]
+    err = _rel(zs[i], H.vcycle(rs[i]))
+    print(f"  {ws[i].name}: grouped V-cycle vs oracle {err:.2e}")
+    assert err < TOL_VCYCLE
+
+
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_group_solve_equals_member_alone(group, fp32):
+    from paper_2508_11608_amd import Group
+
+    name, ws, ps = group
+    print(f"  [case] {name} solve fp32={fp32}", flush=True)
+    for p in ps:
+        p.set_precision(fp32)
+    g = Group(ps)
+    try:
+        bs = [_cuda(p.rhs_manufactured()) for p in ps]
+        xs, infos = g.solve(bs, rtol=1e-8, maxit=200)
+        for i, p in enumerate(ps):
+            x1, info1 = p.solve_multi(bs[i][None, :], rtol=1e-8, maxit=200)
+            print(f"  {ws[i].name}: {infos[i]['iterations']} its grouped, {info1[0]['iterations']} alone")
+            assert infos[i]["status"] == 0
+            assert infos[i]["iterations"] == info1[0]["iterations"]
+            assert infos[i]["rel_residual"] == info1[0]["rel_residual"]
+            assert np.array_equal(xs[i].cpu().numpy(), x1[0].cpu().numpy()), ws[i].name
+    finally:
+        g.close()
+        for p in ps:
+            p.set_precision(False)
+
+
+def test_group_members_of_other_shapes_are_refused():
+    from paper_2508_11608_amd import CutmgError, Group, Problem
+
+    print("\n[case] group of a 2-D and a 3-D problem; a problem twice", flush=True)
+    a, b = Problem(W.disc_q2().with_levels(3)), Problem(W.offcentre_ball(2, 3))
+    try:
+        with pytest.raises(CutmgError) as e:
+            Group([a, b])
+        assert e.value.status == -1  # CMG_EINVAL
+        with pytest.raises(CutmgError) as e:
+            Group([a, a])
+        assert e.value.status == -1
+    finally:
+        a.close()
+        b.close()

@@ -139,3 +139,30 @@ def test_request_larger_than_the_budget_is_refused_before_set_up():
     print(f"  large: status {rb['status']}; small: status {rs['status']}, {rs['iterations']} its; {dt:.2f} s", flush=True)
     assert rb["status"] == -2 and xb is None
     assert rs["status"] == 0 and rs["rel_residual"] <= 1e-8
+
+
+def test_single_requests_of_one_lattice_shape_are_grouped():
+    """Single queued requests of different resident geometries of one lattice
+    shape are solved by one grouped PCG (cmg_group_solve), and every result
+    equals the same request alone on a fresh server, bit for bit."""
+    from paper_2508_11608_amd import Server
+
+    ws = [W.disc_q2(), W.offcentre_disc(2, 4), W.ellipse(2, 4), W.disc_union(2, 4)]
+    print("\n[case] grouped serving: " + ", ".join(w.name for w in ws), flush=True)
+    srv = Server(8 << 30, 1)
+    _run(srv, [(w, W.fourier_modes(2, 3000 + i), True) for i, w in enumerate(ws)])  # all resident
+    # a longer request first, so that the four single requests queue behind it
+    reqs = [(W.offcentre_ball(2, 3), W.fourier_modes(3, 3099), True)]
+    reqs += [(w, W.fourier_modes(2, 3100 + i), True) for i, w in enumerate(ws)]
+    res = _run(srv, reqs)
+    srv.close()
+    print("  groups:", [r["group"] for r, _ in res], flush=True)
+    assert max(r["group"] for r, _ in res[1:]) > 1
+    for (w, f, fp32), (r, x) in zip(reqs[1:], res[1:]):
+        alone = Server(8 << 30, 1)
+        (r1, x1), = _run(alone, [(w, f, fp32)])
+        alone.close()
+        print(f"  {w.name}: group {r['group']}, {r['iterations']} its; alone {r1['iterations']} its", flush=True)
+        assert r["status"] == 0 and r1["status"] == 0 and r1["group"] == 1
+        assert r["iterations"] == r1["iterations"]
+        assert np.array_equal(x, x1), w.name

@@ -159,3 +159,23 @@ def test_perm_export_is_the_lattice_order():
     nn = P.counts(2)["nodes_per_dir"]
     assert perm[0] >= 0 and perm[-1] < nn ** 2
     P.close()
+
+
+def test_group_arguments_are_checked_before_any_device_work():
+    """cmg_group_create refuses bad member counts and problems that were set
+    up on the host only (CMG_EINVAL); nothing is recorded or allocated."""
+    from paper_2508_11608_amd import Group, Problem
+    from paper_2508_11608_amd.cutmg import load_library
+
+    lib = load_library()
+    out = ctypes.c_void_p()
+    assert lib.cmg_group_create(None, 1, ctypes.byref(out)) == CMG_EINVAL
+    P = Problem(W.disc_q2().with_levels(2), device=False)
+    try:
+        arr = (ctypes.c_void_p * 9)(*([P._h.value] * 9))
+        assert lib.cmg_group_create(arr, 0, ctypes.byref(out)) == CMG_EINVAL
+        assert lib.cmg_group_create(arr, 9, ctypes.byref(out)) == CMG_EINVAL
+        assert _status(lambda: Group([P])) == CMG_EINVAL  # host-only problem
+        assert out.value is None
+    finally:
+        P.close()

@@ -105,6 +105,24 @@ def paper_circle(k: int, L: int, n_c: int = 2) -> Workload:
                     centers=((0.0, 0.0),), semi=((1.0, 1.0),), n_c=n_c)
 
 
+def shape_family(n: int, seed: int = 0, dim: int = 3, k: int = 2, n_levels: int = 4) -> list:
+    """n geometries of one lattice shape (same dim, k, levels, box): each an
+    ellipsoid with centre in U[-0.2, 0.2]^d and semi-axes in U[0.45, 0.7], or
+    (probability 1/2) the union of two such ellipsoids with semi-axes in
+    U[0.35, 0.55] and centres in U[-0.3, 0.3]^d, drawn from default_rng(seed).
+    Large enough that every colour of every level has cut patches."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        m = 1 if rng.random() < 0.5 else 2
+        c, lo, hi = (0.2, 0.45, 0.7) if m == 1 else (0.3, 0.35, 0.55)
+        centers = tuple(tuple(float(v) for v in rng.uniform(-c, c, dim)) for _ in range(m))
+        semi = tuple(tuple(float(v) for v in rng.uniform(lo, hi, dim)) for _ in range(m))
+        out.append(Workload(f"family{seed}-{i}-d{dim}-m{m}-Q{k}-N{4 * 2 ** (n_levels - 1)}", dim, k, n_levels,
+                            centers=centers, semi=semi))
+    return out
+
+
 def random_vector(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
     """Seeded standard-normal test vector(s), float64, shape (n,) or (nrhs, n)."""
     rng = np.random.default_rng(seed)
