@@ -108,7 +108,8 @@ def serve(args):
                     k, w, ts = pending.pop(t)
                     out.append((k, w, ts, time.perf_counter() - t0, r[0]))
                     print(f"[serve {tag}] {len(out)}/{len(stream)} request {k} {w.name}: status {r[0]['status']}, "
-                          f"{r[0]['iterations']} its, batch {r[0]['batch']}, {out[-1][3] - ts:.3f} s",
+                          f"{r[0]['iterations']} its, batch {r[0]['batch']}, group {r[0]['group']}, "
+                          f"{out[-1][3] - ts:.3f} s",
                           file=sys.stderr, flush=True)
             time.sleep(0.0005)
         return out, time.perf_counter() - t0
@@ -122,6 +123,7 @@ def serve(args):
     sat_rate = len(reqs) / wall
     dofs = sum(r["n_dofs"] * r["iterations"] for *_, r in out)
     sat_batch = [r["batch"] for *_, r in out]
+    sat_group = sum(r["group"] > 1 for *_, r in out)
     rng = np.random.default_rng(1)
     arr = np.cumsum(rng.exponential(1.0 / (args.rate * sat_rate), len(reqs)))
     arr -= arr[0]
@@ -146,6 +148,8 @@ def serve(args):
         "all_converged": ok, "saturation_req_per_s": sat_rate,
         "saturation_mean_batch": float(np.mean(sat_batch)), "saturation_max_batch": int(max(sat_batch)),
         "poisson_mean_batch": float(np.mean([r["batch"] for *_, r in out])),
+        "saturation_grouped_requests": int(sat_group),
+        "poisson_grouped_requests": int(sum(r["group"] > 1 for *_, r in out)),
     }
 
 
