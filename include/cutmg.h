@@ -287,7 +287,7 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
  * group's V-cycle is then one launch over all members (blockIdx.z selects the
  * member), and the grouped V-cycle is replayed from one HIP graph.  A member
  * stays usable alone, but no other call may run on a member while a call of
- * its group runs.
+ * its group runs, and a group must be destroyed before any of its members.
  *
  * cmg_group_vcycle: z[m] = B_m r[m] for every member m (n_L of that member
  * entries each, canonical order); bit for bit what

@@ -124,8 +124,9 @@ def test_group_solve_equals_member_alone(group, fp32):
 def test_group_members_of_other_shapes_are_refused():
     from paper_2508_11608_amd import CutmgError, Group, Problem
 
-    print("\n[case] group of a 2-D and a 3-D problem; a problem twice", flush=True)
+    print("\n[case] group of a 2-D and a 3-D problem; a problem twice; members of two precisions", flush=True)
     a, b = Problem(W.disc_q2().with_levels(3)), Problem(W.offcentre_ball(2, 3))
+    c = Problem(W.offcentre_disc(2, 3))
     try:
         with pytest.raises(CutmgError) as e:
             Group([a, b])
@@ -133,6 +134,38 @@ def test_group_members_of_other_shapes_are_refused():
         with pytest.raises(CutmgError) as e:
             Group([a, a])
         assert e.value.status == -1
+        c.set_precision(True)
+        with pytest.raises(CutmgError) as e:
+            Group([a, c])
+        assert e.value.status == -1
     finally:
+        a.close()
+        b.close()
+        c.close()
+
+
+def test_group_solve_freezes_a_failing_member():
+    """A member whose right-hand side is not finite stops with CMG_EINVAL (as
+    cmg_solve_multi does) while the other members still converge, to the same
+    bits as alone; the call returns the failing member's status."""
+    import torch
+    from paper_2508_11608_amd import CutmgError, Group, Problem
+
+    print("\n[case] grouped solve with a non-finite right-hand side in one member", flush=True)
+    a, b = Problem(W.disc_q2().with_levels(3)), Problem(W.offcentre_disc(2, 3))
+    g = Group([a, b])
+    try:
+        ba = torch.full((a.ndofs(),), float("nan"), dtype=torch.float64, device="cuda")
+        bb = _cuda(b.rhs_manufactured())
+        xs, infos = g.solve([ba, bb], raise_on_fail=False)
+        assert infos[0]["status"] == -1 and infos[1]["status"] == 0
+        x1, info1 = b.solve_multi(bb[None, :])
+        assert infos[1]["iterations"] == info1[0]["iterations"]
+        assert np.array_equal(xs[1].cpu().numpy(), x1[0].cpu().numpy())
+        with pytest.raises(CutmgError) as e:
+            g.solve([ba, bb])
+        assert e.value.status == -1
+    finally:
+        g.close()
         a.close()
         b.close()
