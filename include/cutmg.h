@@ -285,9 +285,11 @@ cmg_status cmg_solve_multi(cmg_problem* p, int nrhs, const double* b, double* x,
  * every level; otherwise it returns CMG_EINVAL and keeps nothing.  It uploads
  * the members' kernel arguments as one device table.  Each step of the
  * group's V-cycle is then one launch over all members (blockIdx.z selects the
- * member), and the grouped V-cycle is replayed from one HIP graph.  A member
- * stays usable alone, but no other call may run on a member while a call of
- * its group runs, and a group must be destroyed before any of its members.
+ * member), and the grouped V-cycle is replayed from one HIP graph.  The group
+ * keeps the precision and ghost coupling its members had when it was created.
+ * A member stays usable alone, but no other call may run on a member while a
+ * call of its group runs, and a group must be destroyed before any of its
+ * members.
  *
  * cmg_group_vcycle: z[m] = B_m r[m] for every member m (n_L of that member
  * entries each, canonical order); bit for bit what
