@@ -92,6 +92,37 @@ void special_cells(const cmg::HostLevel& h, int dim, std::vector<int32_t>* spec,
   }
 }
 
+// The operator tiles (B^d cells, B as in the kernels' tile shape) split by
+// what their staged cells -1 .. B-1 hold: all inside the box, active and
+// regular (special id -1) -> tsf, the sum-factorised kernel; else -> mix, the
+// kernel with dense rows and the special-cell values.
+void split_tiles(const cmg::HostLevel& h, int dim, int k, const std::vector<int32_t>& sid,
+                 std::vector<int32_t>* mix, std::vector<int32_t>* tsf) {
+  const int B = (dim == 3 && k == 3) ? 2 : 4;
+  const int NTd = (h.N + B - 1) / B;
+  const int ncell = dim == 3 ? (B + 1) * (B + 1) * (B + 1) : (B + 1) * (B + 1);
+  for (int32_t t : h.tiles) {
+    int tc[3] = {0, 0, 0};
+    for (int a = 0, r = t; a < dim; ++a) {
+      tc[a] = r % NTd;
+      r /= NTd;
+    }
+    bool regular = true;
+    for (int e = 0; e < ncell && regular; ++e) {
+      int64_t cl = 0, st = 1;
+      for (int a = 0, r = e; a < dim; ++a) {
+        const int c = B * tc[a] - 1 + r % (B + 1);
+        r /= B + 1;
+        if (c < 0 || c >= h.N) regular = false;
+        cl += c * st;
+        st *= h.N;
+      }
+      regular = regular && sid[static_cast<size_t>(cl)] == -1;
+    }
+    (regular ? tsf : mix)->push_back(t);
+  }
+}
+
 }  // namespace
 
 struct cmg_problem {
@@ -310,18 +341,24 @@ cmg_status upload_all(cmg_problem* P) {
     TRY(upload(own, h.face_dir, &fdir));
     TRY(upload(own, h.cell_gid, &cgid));
     TRY(upload(own, h.cell_faces, &cfaces));
-    TRY(upload(own, h.tiles, &tiles));
     k.n_faces = static_cast<int64_t>(h.face_lower.size());
     k.face_lower = flow;
     k.face_dir = fdir;
     k.cell_gid = cgid;
     k.cell_faces = cfaces;
-    k.n_tiles = static_cast<int>(h.tiles.size());
-    k.tiles = tiles;
     k.n_cut = h.n_cut;
     {
       std::vector<int32_t> spec, info, sid;
       special_cells(h, cfg.dim, &spec, &info, &sid);
+      std::vector<int32_t> tmix, tsf;
+      split_tiles(h, cfg.dim, cfg.k, sid, &tmix, &tsf);
+      int32_t* dtsf;
+      TRY(upload(own, tmix, &tiles));
+      TRY(upload(own, tsf, &dtsf));
+      k.n_tiles = static_cast<int>(tmix.size());
+      k.tiles = tiles;
+      k.n_tiles_sf = static_cast<int>(tsf.size());
+      k.tiles_sf = dtsf;
       int32_t *dspec, *dinfo, *dsid;
       TRY(upload(own, spec, &dspec));
       TRY(upload(own, info, &dinfo));

@@ -30,8 +30,10 @@ struct KLevel {
   const uint8_t* face_dir;   // its normal direction
   const int32_t* cell_gid;   // per cell: row of cell_faces or -1
   const int32_t* cell_faces; // 2d face ids per cell with ghost faces (-1: none)
-  int n_tiles;               // operator tiles owning active nodes
-  const int32_t* tiles;
+  int n_tiles;               // operator tiles owning active nodes whose staged cells (-1 .. B-1 around
+  const int32_t* tiles;      // the tile) include a special or inactive cell: dense rows and pre-pass values
+  int n_tiles_sf;            // the other tiles owning active nodes: every staged cell active and regular,
+  const int32_t* tiles_sf;   // applied by sum factorisation
   int64_t n_spec;            // special cells: cut, or with a ghost face
   const int32_t* spec_cells; // background cell of every special cell
   const int32_t* spec_info;  // per special cell 1 + 2d entries: cut id (-1: uncut), ghost face ids (-1: none)

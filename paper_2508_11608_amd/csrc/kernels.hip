@@ -534,6 +534,187 @@ struct ApplyArgs {
   __device__ void run() const { apply_body<D, K, T>(L, x, b, y, C); }
 };
 
+// Entry (s, j) of the 1-D matrix assembled from the element matrix e ((k+1) x
+// (k+1), row-major) over the NCELL staged cells of an operator tile along one
+// direction (cell c holds staged nodes K c .. K c + K).  tile1d_nz tells
+// whether some cell holds both nodes; with compile-time s and j both fold.
+template <int K, int NCELL>
+__host__ __device__ constexpr bool tile1d_nz(int s, int j) {
+  for (int c = 0; c < NCELL; ++c)
+    if (s >= K * c && s <= K * c + K && j >= K * c && j <= K * c + K) return true;
+  return false;
+}
+template <int K, int NCELL>
+__device__ __forceinline__ double tile1d(const double* e, int s, int j) {
+  double v = 0;
+#pragma unroll
+  for (int c = 0; c < NCELL; ++c)
+    if (s >= K * c && s <= K * c + K && j >= K * c && j <= K * c + K) v += e[(s - K * c) * (K + 1) + (j - K * c)];
+  return v;
+}
+// The same for a run-time row s: the cells holding s are s/K - 1 and s/K when
+// s is a cell boundary, else s/K.
+template <int K, int NCELL>
+__device__ __forceinline__ double tile1d_rt(const double* e, int s, int j) {
+  const int c1 = s / K, c0 = s % K == 0 ? c1 - 1 : c1;
+  double v = 0;
+  for (int c = c0; c <= c1; ++c)
+    if (c >= 0 && c < NCELL && j >= K * c && j <= K * c + K) v += e[(s - K * c) * (K + 1) + (j - K * c)];
+  return v;
+}
+
+// y = A x (b == nullptr) or y = b - A x on the active nodes of a tile whose
+// staged cells -1 .. B-1 are all active and regular.  There A is the sum over
+// directions a of tensor products of the assembled 1-D stiffness h^(d-2) K1
+// along a and the assembled 1-D mass along the others (the uncut cell
+// stiffness has this form, summed over the staged cells), applied by one pass
+// per direction: along the slowest direction every staged line gives Mhat x
+// and Khat x on the owned rows; in 3-D the next direction gives Mhat Mhat x and
+// Khat Mhat x + Mhat Khat x; every owned node contracts direction 0 at its own
+// position.  Only the band of the 1-D matrices is applied.
+template <int D, int K, typename T>
+__device__ __forceinline__ void apply_sf_body(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y) {
+  using S = Shape<D, K>;
+  using A = ApplyShape<D, K>;
+  constexpr int N1 = S::N1, B = A::B, R1 = A::R1, C1 = A::C1, O1 = A::O1;
+  constexpr int NW = D == 3 ? R1 * O1 * O1 : 1;                      // values per second-pass array
+  constexpr int NXV = D == 3 ? (A::NR > 2 * NW ? A::NR : 2 * NW) : A::NR;
+  constexpr int NU = D == 3 ? R1 * R1 * O1 : R1 * O1;                // values per first-pass array
+  __shared__ double m1[N1 * N1], k1[N1 * N1];
+  __shared__ T xv[NXV];     // x staged; in 3-D then the second pass: [0, NW) and [NW, 2 NW)
+  __shared__ T ua[2][NU];   // first pass: Mhat x and Khat x along the slowest direction
+  for (int i = threadIdx.x; i < N1 * N1; i += blockDim.x) {
+    m1[i] = L.tables[S::T_MHAT + i];
+    k1[i] = L.tables[S::T_K1S + i];
+  }
+  x += blockIdx.y * L.n_nodes;  // column blockIdx.y
+  if (b) b += blockIdx.y * L.n_nodes;
+  y += blockIdx.y * L.n_nodes;
+  const int NTd = (L.N + B - 1) / B;
+  for (int ti = blockIdx.x; ti < L.n_tiles_sf; ti += gridDim.x) {
+    __syncthreads();  // tables, and the previous tile finished with the LDS buffers
+    int tc[3] = {0, 0, 0};
+    {
+      int r = L.tiles_sf[ti];
+#pragma unroll
+      for (int a = 0; a < D; ++a) { tc[a] = r % NTd; r /= NTd; }
+    }
+    for (int e = threadIdx.x; e < A::NR; e += blockDim.x) {
+      int I[3];
+      bool in = true;
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        I[a] = K * (B * tc[a] - 1) + r % R1;
+        r /= R1;
+        in = in && I[a] >= 0 && I[a] < L.nn;
+      }
+      xv[e] = in ? x[lat(D, L.nn, I)] : (T)0;
+    }
+    __syncthreads();
+    // slowest direction: every staged line, rows K .. K + O1 - 1
+    constexpr int NLA = D == 3 ? R1 * R1 : R1;
+    for (int l = threadIdx.x; l < NLA; l += blockDim.x) {
+      T xl[R1];
+#pragma unroll
+      for (int j = 0; j < R1; ++j) xl[j] = xv[l + NLA * j];
+#pragma unroll
+      for (int q = 0; q < O1; ++q) {
+        T um = 0, uk = 0;
+#pragma unroll
+        for (int j = 0; j < R1; ++j) {
+          if (!tile1d_nz<K, C1>(K + q, j)) continue;
+          um += (T)tile1d<K, C1>(m1, K + q, j) * xl[j];
+          uk += (T)tile1d<K, C1>(k1, K + q, j) * xl[j];
+        }
+        ua[0][l * O1 + q] = um;
+        ua[1][l * O1 + q] = uk;
+      }
+    }
+    __syncthreads();
+    if constexpr (D == 3) {
+      // direction 1 on the lines (s0, q2): Mhat Mhat x into [0, NW), Khat Mhat x + Mhat Khat x into [NW, 2 NW)
+      for (int t = threadIdx.x; t < R1 * O1; t += blockDim.x) {
+        const int s0 = t % R1, q2 = t / R1;
+        T ul[R1], kl[R1];
+#pragma unroll
+        for (int j = 0; j < R1; ++j) {
+          ul[j] = ua[0][(s0 + R1 * j) * O1 + q2];
+          kl[j] = ua[1][(s0 + R1 * j) * O1 + q2];
+        }
+#pragma unroll
+        for (int q = 0; q < O1; ++q) {
+          T vmm = 0, vxx = 0;
+#pragma unroll
+          for (int j = 0; j < R1; ++j) {
+            if (!tile1d_nz<K, C1>(K + q, j)) continue;
+            vmm += (T)tile1d<K, C1>(m1, K + q, j) * ul[j];
+            vxx += (T)tile1d<K, C1>(k1, K + q, j) * ul[j];
+            vxx += (T)tile1d<K, C1>(m1, K + q, j) * kl[j];
+          }
+          xv[s0 + R1 * (q + O1 * q2)] = vmm;
+          xv[NW + s0 + R1 * (q + O1 * q2)] = vxx;
+        }
+      }
+      __syncthreads();
+    }
+    // direction 0 at every owned node: Khat (first array) + Mhat (second array)
+    const T* f0 = D == 3 ? xv : &ua[0][0];
+    const T* f1 = D == 3 ? xv + NW : &ua[1][0];
+#pragma unroll 1
+    for (int e = threadIdx.x; e < A::NO; e += blockDim.x) {
+      int q[3], I[3];
+      bool own = true;
+      int r = e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        q[a] = r % O1;
+        r /= O1;
+        I[a] = K * B * tc[a] + q[a];
+        // the layer q = B K belongs to the next tile unless this is the last one
+        own = own && I[a] < L.nn && (q[a] < B * K || tc[a] == NTd - 1);
+      }
+      if (!own) continue;
+      const int64_t node = lat(D, L.nn, I);
+      const T bv = b ? b[node] : (T)0;
+      const int s = K + q[0];
+      // second-pass value of staged column j: 3-D index j + R1 (q1 + O1 q2), 2-D j O1 + q1
+      const int rest = D == 3 ? R1 * (q[1] + O1 * q[2]) : q[1];
+      T ax = 0;
+#pragma unroll
+      for (int dj = -K; dj <= K; ++dj) {
+        // s >= K, so j >= 0; the line ends at R1 - 1 = (B + 1) K, so for K >= 2
+        // the last owned rows reach past it: those j hold no matrix entry, and
+        // the words past the line were not written by this block (not
+        // necessarily finite), so they are skipped
+        const int j = s + dj;
+        if (j >= R1) continue;
+        const int at = D == 3 ? j + rest : j * O1 + rest;
+        ax += (T)tile1d_rt<K, C1>(k1, s, j) * f0[at];
+        ax += (T)tile1d_rt<K, C1>(m1, s, j) * f1[at];
+      }
+      y[node] = b ? bv - ax : ax;
+    }
+  }
+}
+
+template <int D, int K, typename T>
+__global__ __launch_bounds__(256) void k_apply_sf(KLevel L, const T* __restrict__ x, const T* __restrict__ b,
+                                                  T* __restrict__ y) {
+  apply_sf_body<D, K, T>(L, x, b, y);
+}
+
+// argument record of k_apply_sf for grouped launches (k_grouped)
+template <int D, int K, typename T>
+struct ApplySfArgs {
+  KLevel L;
+  const T* x;
+  const T* b;
+  T* y;
+  __device__ void run() const { apply_sf_body<D, K, T>(L, x, b, y); }
+};
+
 // Entry (r, j) of a 1-D matrix assembled on the 2k+1 closure nodes of a patch
 // from the element matrix e ((k+1) x (k+1), row-major) of its two cells, the
 // second cell starting at node k.  patch1d_nz tells whether some cell holds
@@ -2136,10 +2317,24 @@ hipError_t launch_apply(int d, int k, const KLevel& L, const T* x, const T* b, T
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    const unsigned nb = std::max(1u, std::min<unsigned>(static_cast<unsigned>(L.n_tiles), lp.max_blocks / ncol + 1));
-    if (record<256>(dim3(nb, ncol), dim3(256), dev::ApplyArgs<D.value, K.value, T>{L, x, b, y, C})) return hipSuccess;
-    hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, C);
-    return hipGetLastError();
+    // the two tile kernels write disjoint owned nodes
+    if (L.n_tiles > 0 || t_rec) {
+      const unsigned nb = std::max(1u, std::min<unsigned>(static_cast<unsigned>(L.n_tiles), lp.max_blocks / ncol + 1));
+      if (!record<256>(dim3(nb, ncol), dim3(256), dev::ApplyArgs<D.value, K.value, T>{L, x, b, y, C})) {
+        hipLaunchKernelGGL((dev::k_apply<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y, C);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
+    if (L.n_tiles_sf > 0 || t_rec) {
+      const unsigned nb =
+          std::max(1u, std::min<unsigned>(static_cast<unsigned>(L.n_tiles_sf), lp.max_blocks / ncol + 1));
+      if (!record<256>(dim3(nb, ncol), dim3(256), dev::ApplySfArgs<D.value, K.value, T>{L, x, b, y})) {
+        hipLaunchKernelGGL((dev::k_apply_sf<D.value, K.value, T>), dim3(nb, ncol), dim3(256), 0, s, L, x, b, y);
+        return hipGetLastError();
+      }
+    }
+    return hipSuccess;
   });
 }
 

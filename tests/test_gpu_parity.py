@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [W.disc_q2(), W.offcentre_disc(1, 4), W.offcentre_disc(3, 3), W.ellipse(2, 3),
          W.offcentre_ball(2, 3), W.ball_q2().with_levels(3), W.offcentre_ball(3, 2), W.offcentre_ball(1, 3),
-         W.disc_union(2, 3), W.ball_union(2, 3),
+         W.disc_union(2, 3), W.ball_union(2, 3), W.box_disc(1, 4), W.box_disc(2, 4), W.box_disc(3, 3),
+         W.box_ball(2, 3),
          W.Workload(**{**W.offcentre_disc(3, 3).__dict__, "name": "disc-off-Q3-gamma-m", "gamma_m": (0.07, 0.12, 0.05)})]
 
 TOL_APPLY = 1e-12

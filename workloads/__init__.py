@@ -73,6 +73,18 @@ def ellipse(k: int = 2, n_levels: int = 4) -> Workload:
     return Workload(f"ellipse-Q{k}", 2, k, n_levels, centers=((0.031, -0.047),), semi=((0.72, 0.51),))
 
 
+def box_disc(k: int = 2, n_levels: int = 4) -> Workload:
+    """A disc of radius 1.3 around the origin: it covers [-1, 1]^2 except the
+    corners, so the operator tiles along the box edges are regular up to the
+    box (the last owned layer of the last tile included)."""
+    return Workload(f"box-disc-Q{k}", 2, k, n_levels, centers=((0.0, 0.0),), semi=((1.3, 1.3),))
+
+
+def box_ball(k: int = 2, n_levels: int = 3) -> Workload:
+    """The 3-D counterpart of box_disc (radius 1.3 in [-1, 1]^3)."""
+    return Workload(f"box-ball-Q{k}", 3, k, n_levels, centers=((0.0, 0.0, 0.0),), semi=((1.3, 1.3, 1.3),))
+
+
 def disc_union(k: int = 2, n_levels: int = 3) -> Workload:
     """Two overlapping discs (union)."""
     return Workload(f"disc-union-Q{k}", 2, k, n_levels, centers=((-0.21, 0.05), (0.27, -0.11)),
