@@ -1576,8 +1576,10 @@ __global__ __launch_bounds__(TH) void k_cut_solve(KLevel L, CutGroupDev G,
 // the current x just before) to all columns, into parts[pair][column]; each
 // node then sums its 1..2^d pairs in a fixed order.  Every column follows the
 // same arithmetic in the same order, so its result does not depend on the
-// other columns.  Writes rs[i][c] = b_c - (A x_c) at node i for i < nj,
-// c < ncol.  All threads of the block call it (it synchronises).
+// other columns.  Returns the residual rows in the LDS of the staged closure
+// (free once the pairs are formed): rs[i][c] = b_c - (A x_c) at node i for
+// i < nj and c < ncol, zero elsewhere in the first nrows rows (nrows <= the
+// closure's node count).  All threads of the block call it (it synchronises).
 template <int D, int K, typename T, int NCOL>
 struct PairSmem {
   using S = Shape<D, K>;
@@ -1593,7 +1595,7 @@ struct PairSmem {
 template <int D, int K, typename T, int NCOL>
 __device__ void cut_residual_cols(const KLevel& L, const CutGroupDev& G, int gp, const T* __restrict__ x,
                                   const T* __restrict__ b, const T* __restrict__ W, int ncol,
-                                  PairSmem<D, K, T, NCOL>& sm, T (*rs)[NCOL], int& off, int& nj) {
+                                  PairSmem<D, K, T, NCOL>& sm, int nrows, int& off, int& nj) {
   using S = Shape<D, K>;
   constexpr int N1 = S::N1, NL = S::NL, NC = S::NC, NC1 = S::NC1, NP1 = S::NP1, NCELL = 1 << D;
   constexpr int NT = Pow<N1, D - 1>::v;
@@ -1792,10 +1794,11 @@ __device__ void cut_residual_cols(const KLevel& L, const CutGroupDev& G, int gp,
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) acc[c] += sm.parts[t][c];
     }
+    T(*rs)[NCOL] = sm.xs;
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c)
-      if (c < ncol) rs[tid][c] = bv[c] - acc[c];
+    for (int c = 0; c < NCOL; ++c) rs[tid][c] = c < ncol ? bv[c] - acc[c] : (T)0;
   }
+  for (int e = nj * NCOL + tid; e < nrows * NCOL; e += TH) (&sm.xs[0][0])[e] = 0;
   __syncthreads();
 }
 
@@ -1818,13 +1821,14 @@ __device__ __forceinline__ void cut_solve_mfma_body(KLevel L, CutGroupDev G, con
   using S = Shape<D, K>;
   constexpr int NPK = (S::NP + 3) / 4 * 4;
   __shared__ PairSmem<D, K, float, kMaxCols> sm;
-  __shared__ float rs[NPK][kMaxCols];  // residual columns; rows >= nj and columns >= ncol stay zero
+  static_assert(NPK <= S::NC, "the residual rows fit in the staged closure");
   const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = xcd_block(blockIdx.x, gridDim.x);
   if (gp >= G.n_patch) return;  // grouped launches: a block beyond this problem's patches
-  for (int e = tid; e < NPK * kMaxCols; e += nth) (&rs[0][0])[e] = 0.f;
   int off, nj;
-  cut_residual_cols<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
+  cut_residual_cols<D, K, float, kMaxCols>(L, G, gp, x, b, W, ncol, sm, NPK, off, nj);
+  // residual columns; rows >= nj and columns >= ncol are zero
+  const float(*rs)[kMaxCols] = sm.xs;
   const int lane = tid % 64, wave = tid / 64, nwave = nth / 64;
   const int nrb = (nj + 15) / 16, nkb = (nj + 3) / 4;
   const int kr = lane / 16, jc = lane % 16;
@@ -1891,13 +1895,13 @@ __device__ __forceinline__ void cut_solve_cols_body(KLevel L, CutGroupDev G, con
   constexpr int NB = 8;                        // independent inverse loads in flight per thread
   constexpr int NPB = (S::NP + NB - 1) / NB * NB;
   __shared__ PairSmem<D, K, double, kMaxCols> sm;
-  __shared__ double rs[NPB][kMaxCols];         // rows >= nj and columns >= ncol stay zero
+  static_assert(NPB <= S::NC, "the residual rows fit in the staged closure");
   const int tid = threadIdx.x, nth = blockDim.x;
   const int gp = xcd_block(blockIdx.x, gridDim.x);
   if (gp >= G.n_patch) return;  // grouped launches: a block beyond this problem's patches
-  for (int e = tid; e < NPB * kMaxCols; e += nth) (&rs[0][0])[e] = 0.0;
   int off, nj;
-  cut_residual_cols<D, K, double, kMaxCols>(L, G, gp, x, b, W, ncol, sm, rs, off, nj);
+  cut_residual_cols<D, K, double, kMaxCols>(L, G, gp, x, b, W, ncol, sm, NPB, off, nj);
+  const double(*rs)[kMaxCols] = sm.xs;  // rows >= nj and columns >= ncol are zero
   const double* inv = G.inv_t<double>() + G.inv_off[gp];
   for (int i = tid; i < nj; i += nth) {
     double acc[kMaxCols];
