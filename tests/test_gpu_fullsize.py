@@ -121,39 +121,52 @@ def _patch_update(R, V, x, b, interior):
     return I, x[I] + np.linalg.solve(Aj, r), np.linalg.cond(Aj)
 
 
-@pytest.mark.parametrize("interior,colour", [(False, 0), (False, 5), (True, 3)], ids=["cut-c0", "cut-c5", "interior-c3"])
-def test_colour_step_sampled_patches(full, interior, colour):
+@pytest.mark.parametrize("interior,colour,fp32", [(False, 0, False), (False, 5, False), (True, 3, False),
+                                                (False, 0, True), (True, 3, True)],
+                         ids=["cut-c0", "cut-c5", "interior-c3", "cut-c0-fp32", "interior-c3-fp32"])
+def test_colour_step_sampled_patches(full, interior, colour, fp32):
     w, P, R = full
-    print(f"  [case] {w.name} {'interior' if interior else 'cut'} colour step {colour} at full size", flush=True)
+    print(f"  [case] {w.name} {'interior' if interior else 'cut'} colour step {colour} at full size, fp32={fp32}",
+          flush=True)
     L = w.n_levels - 1
     n = R.L.n_dofs
     x = W.random_vector(n, seed=1220 + colour)
     b = W.random_vector(n, seed=1230 + colour)
     xg = _cuda(x)
-    P.colour_step(L, interior, colour, xg, _cuda(b))
+    P.set_precision(fp32)
+    try:
+        P.colour_step(L, interior, colour, xg, _cuda(b))
+    finally:
+        P.set_precision(False)
     xn = xg.cpu().numpy()
     cut_v, int_v = R.patch_masks(colour)
     vmask = int_v if interior else cut_v
     verts = np.argwhere(vmask)
     print(f"  {len(verts)} patches in the colour", flush=True)
-    # nodes outside the colour's patches are left exactly as they were
+    # nodes outside the colour's patches are left exactly as they were (in FP32
+    # the step runs on x rounded to FP32)
     inside = R.internal_node_mask(vmask)
     node_dof = R.L.dof_of_node[inside]
     touched = np.zeros(n, dtype=bool)
     touched[node_dof[node_dof >= 0]] = True
-    assert np.array_equal(xn[~touched], x[~touched])
+    x_in = x.astype(np.float32).astype(np.float64) if fp32 else x
+    assert np.array_equal(xn[~touched], x_in[~touched])
     # sampled patches against the oracle's local solves
     rng = np.random.default_rng(1240 + colour)
     worst, worst_cond = 0.0, 0.0
     for v in verts[rng.choice(len(verts), 8, replace=False)]:
         I, ref, cond = _patch_update(R, tuple(int(t) for t in v), x, b, interior)
-        err = np.abs(xn[I] - ref).max() / max(np.abs(ref - x[I]).max(), 1e-300)
+        # FP64: relative to the patch correction; FP32: to the updated values
+        # (the FP32 step also rounds x itself)
+        scale = np.abs(ref).max() if fp32 else np.abs(ref - x[I]).max()
+        err = np.abs(xn[I] - ref).max() / max(scale, 1e-300)
         print(f"    patch {tuple(int(t) for t in v)}: {len(I)} DoFs, cond {cond:.1e}, error {err:.2e}")
-        # both sides solve the same local system in FP64: the difference is
-        # bounded by its condition number times the rounding unit
-        assert err < 1e-10 + 1e-14 * cond
+        # both sides solve the same local system, the library in FP64 or with
+        # the FP32 rounding of the FP64 inverse and FP32 arithmetic: the
+        # difference is bounded by the condition number times the rounding unit
+        assert err < (1e-5 + 1e-6 * cond if fp32 else 1e-10 + 1e-14 * cond)
         worst, worst_cond = max(worst, err), max(worst_cond, cond)
-    print(f"  8 sampled patches: max error {worst:.2e} (relative to the patch correction), max cond {worst_cond:.1e}")
+    print(f"  8 sampled patches: max error {worst:.2e}, max cond {worst_cond:.1e}")
 
 
 @pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
